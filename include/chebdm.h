@@ -1,0 +1,193 @@
+/*
+ * chebdm.h - C ABI of the dense Chebyshev Fermi-operator library for MI355X (gfx950).
+ *
+ * The library builds the single-particle density matrix
+ *     D = f(H) = [I + exp(beta (H - mu I))]^{-1}                (paper, Sec. II.B, eq. "fermi")
+ * of a dense symmetric Hamiltonian without diagonalisation, as the degree-L
+ * Chebyshev expansion D_L = sum_{n<=L} c_n T_n(H~) evaluated with the
+ * O(sqrt(L)) baby-step/giant-step scheme of Sec. II.B (eqs. "ansatz",
+ * "ansatz3"): k-1 products for T_2..T_k, m-1 products over T_k blocks, L = km-1.
+ * All device work runs in the library's own HIP kernels.
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are dense, float64, row-major with a leading dimension
+ *     ld >= n (element (i,j) at p[i*ld + j]).  H must be symmetric; it is not
+ *     checked.  Because H and D are symmetric, row- and column-major agree.
+ *   - Pointers named d* are device pointers on the handle's device and stay
+ *     owned by the caller; pointers named h* / *_out are host pointers.
+ *   - Work is ordered on the handle's HIP stream.  Entry points that return
+ *     host values (bounds, coefficients, mu, info, moments) synchronise that
+ *     stream before returning; chebdm_density with info == NULL does not.
+ *   - dD must not alias dH.  The library owns a workspace of about
+ *     (k + m) * ld^2 elements, grown on demand and kept until chebdm_destroy.
+ *   - emin/emax arguments: pass NAN (both) to let the call compute Gershgorin
+ *     bounds of H itself, or the caller's own outer bounds of the spectrum.
+ *   - Return value: CHEBDM_OK (0), a positive warning (result usable), or a
+ *     negative error; chebdm_last_error() then describes the failure
+ *     (thread-local string).  No C++ exception crosses this interface.
+ *   - A handle must not be used from two threads at once.
+ */
+#ifndef CHEBDM_H
+#define CHEBDM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CHEBDM_ABI_VERSION 1
+
+typedef struct chebdm_ctx* chebdm_handle;
+
+/* Arithmetic of the matrix products (the bounds, coefficients, traces,
+ * moments and the mu bisection are always float64). */
+enum chebdm_prec {
+    CHEBDM_FP64 = 0,   /* float64 MFMA products, float64 matrices            */
+    CHEBDM_FP32 = 1,   /* float32 MFMA products, float32 matrices            */
+    CHEBDM_BF16X3 = 2  /* float32 matrices, products as three bfloat16 MFMA  */
+                       /* terms hi*hi + hi*lo + lo*hi, float32 accumulation  */
+};
+
+/* How the giant steps combine the blocks (both give the same polynomial). */
+enum chebdm_giant {
+    CHEBDM_GIANT_COMPOSITION = 0, /* sum_l T_l(T_k) R_l by Clenshaw over l (default) */
+    CHEBDM_GIANT_POWER = 1        /* paper's sum_j T_k^j S_j by Horner (eq. "ansatz") */
+};
+
+enum chebdm_status {
+    CHEBDM_OK = 0,
+    CHEBDM_WARN_NOCONV = 1,       /* bisection stopped before |tr D - N_e| < tol */
+    CHEBDM_ERR_ARG = -1,          /* invalid argument                            */
+    CHEBDM_ERR_HIP = -2,          /* a HIP runtime call failed                   */
+    CHEBDM_ERR_OOM = -3,          /* workspace allocation failed                 */
+    CHEBDM_ERR_NONFINITE = -4,    /* H holds NaN or Inf                          */
+    CHEBDM_ERR_BRACKET = -5,      /* N_e not inside (t(mu~=-1), t(mu~=1))        */
+    CHEBDM_ERR_UNSUPPORTED = -6   /* option combination not built                */
+};
+
+typedef struct {
+    int32_t prec;        /* enum chebdm_prec, default CHEBDM_FP64                  */
+    int32_t giant_form;  /* enum chebdm_giant, default CHEBDM_GIANT_COMPOSITION    */
+    int32_t k_override;  /* baby-step count k; 0 = ceil(sqrt(L+1))                 */
+    int32_t n_quad;      /* quadrature nodes M for c_n; 0 = automatic rule         */
+    int32_t max_iter;    /* bisection sweep cap; 0 = 200                           */
+    int32_t reserved;
+    double tol;          /* target |tr D - N_e| of the mu search; 0 = 1e-10        */
+} chebdm_opts;
+
+typedef struct {
+    int32_t k, m;        /* baby-step count and block count, L + 1 <= k*m           */
+    int32_t n_gemm;      /* matrix products executed                               */
+    int32_t n_quad;      /* quadrature nodes M used for the coefficients           */
+    int32_t iters;       /* bisection sweeps (mu search)                           */
+    int32_t status;      /* same as the return value                               */
+    double emin, emax;   /* spectral bounds used                                   */
+    double mu;           /* chemical potential used (energy units)                 */
+    double trace;        /* tr D in float64 (or t(mu) when no D was built)         */
+    double trace_err;    /* |t(mu) - N_e| of the bisection (mu search only)        */
+} chebdm_info;
+
+/* Fill *o with the defaults listed above. */
+void chebdm_default_opts(chebdm_opts* o);
+
+/* Version of this ABI (CHEBDM_ABI_VERSION). */
+int chebdm_abi_version(void);
+
+/* Thread-local description of the last failure in this thread ("" if none). */
+const char* chebdm_last_error(void);
+
+/* Create a handle bound to HIP device `device` and stream `stream`
+ * (a hipStream_t; NULL = the legacy default stream).  *out receives the handle. */
+int chebdm_create(chebdm_handle* out, int device, void* stream);
+
+/* Release the handle and its workspace (waits for its stream first). */
+int chebdm_destroy(chebdm_handle h);
+
+/* Re-bind the handle to another stream on the same device. */
+int chebdm_set_stream(chebdm_handle h, void* stream);
+
+/*
+ * Spectral bounds of H by Gershgorin's discs (reading of Sec. II.B, which
+ * asks for the lowest and highest eigenvalues e_a, e_b without a method):
+ *     emin = min_i (H_ii - r_i),  emax = max_i (H_ii + r_i),  r_i = sum_{j!=i} |H_ij|,
+ * summed in float64 in a fixed order (deterministic).
+ * dH: n x n, leading dimension ldh >= n.  Writes host doubles *emin, *emax.
+ * Errors: CHEBDM_ERR_ARG (n < 1, ldh < n, NULL pointers),
+ *         CHEBDM_ERR_NONFINITE (H holds NaN/Inf).
+ */
+int chebdm_bounds(chebdm_handle h, const double* dH, int64_t n, int64_t ldh,
+                  double* emin, double* emax);
+
+/*
+ * Chebyshev coefficients c_0..c_L of the Fermi function on [emin, emax]
+ * (the expansion sum c_n T_n of Sec. II.B; projection is a reading):
+ *     c_n = (2 - delta_{n0})/M * sum_{j<M} f(x_j) cos(n theta_j),
+ *     theta_j = pi (j + 1/2)/M,  x_j = cos theta_j,
+ *     f(x) = 1/(1 + exp(beta' (x - mu~))),  beta' = beta (emax-emin)/2,
+ *     mu~ = (mu - (emin+emax)/2) / ((emax-emin)/2)       (eq. "fermifunc").
+ * n_quad = M (0 = automatic: 2^ceil(log2 max(2(L+1), L/2 + 7 beta' + 64))).
+ * Computed on the device in float64; c_out: host array of order+1 doubles.
+ * Errors: CHEBDM_ERR_ARG (order < 0, beta <= 0, emax <= emin, M < L+1).
+ */
+int chebdm_coeffs(chebdm_handle h, double beta, double mu, double emin, double emax,
+                  int32_t order, int32_t n_quad, double* c_out);
+
+/*
+ * Density matrix at a given chemical potential mu (Sec. II.B and III.B):
+ * bounds (if NaN) -> T_1 = H~ -> coefficients -> block coefficients
+ * (power form d of eq. "X", or composition form) -> baby steps T_2..T_k in
+ * the stage order of Algorithm 1 -> block sums -> m-1 giant steps -> D.
+ * dD: n x n output, leading dimension ldd >= n (only that n x n part is
+ * written).  opts may be NULL (defaults).  info may be NULL.
+ * Errors: CHEBDM_ERR_ARG, CHEBDM_ERR_NONFINITE, CHEBDM_ERR_OOM, CHEBDM_ERR_HIP,
+ *         CHEBDM_ERR_UNSUPPORTED (BF16X3 with the power form).
+ */
+int chebdm_density(chebdm_handle h, const double* dH, int64_t n, int64_t ldh,
+                   double beta, double mu, int32_t order, const chebdm_opts* opts,
+                   double emin, double emax, double* dD, int64_t ldd, chebdm_info* info);
+
+/*
+ * Chemical potential with tr D_L(mu) = n_elec, then (if dD != NULL) D at it.
+ * The trace moments tau_n = tr T_n(H~), n <= L, come from the baby steps and
+ * a ladder T_{2k}, ..., T_{(m-1)k} through 2 T_a T_b = T_{a+b} + T_{|a-b|}
+ * (eq. "identity"); t(mu~) = sum_n c_n(mu~) tau_n is bisected on
+ * mu~ in [-1, 1] (midpoint rule; stop when |t - n_elec| < tol, when the
+ * bracket is narrower than 4 ulp, or after max_iter sweeps).
+ * Writes *mu_out (energy units, host).  0 < n_elec < n required.
+ * Returns CHEBDM_WARN_NOCONV if the bracket collapsed before tol was met.
+ * Errors: as chebdm_density, plus CHEBDM_ERR_BRACKET.
+ */
+int chebdm_mu_search(chebdm_handle h, const double* dH, int64_t n, int64_t ldh,
+                     double beta, double n_elec, int32_t order, const chebdm_opts* opts,
+                     double emin, double emax, double* mu_out, double* dD, int64_t ldd,
+                     chebdm_info* info);
+
+/*
+ * Trace moments tau_0..tau_L of T_n(H~) (the quantities the mu search
+ * bisects on), computed as in chebdm_mu_search.  tau_out: host, order+1 doubles.
+ */
+int chebdm_moments(chebdm_handle h, const double* dH, int64_t n, int64_t ldh,
+                   int32_t order, const chebdm_opts* opts, double emin, double emax,
+                   double* tau_out);
+
+/*
+ * Block coefficients for given c_0..c_L (host in, host out), k = opts->k_override
+ * or ceil(sqrt(L+1)), m = ceil((L+1)/k).  coef_out: m x k row-major, entry
+ * (l, i) is the weight of T_i in block l:
+ *   CHEBDM_GIANT_POWER:       d_{i,l} of eq. "ansatz3", from c = X d (eq. "X")
+ *                             by back substitution over the row blocks l = m-1..0;
+ *   CHEBDM_GIANT_COMPOSITION: e_{l,i} with sum_n c_n T_n = sum_l T_l(T_k) R_l,
+ *                             R_l = sum_i e_{l,i} T_i, from the same identity.
+ * Runs on the device.  Writes *k_out, *m_out.  coef_out must hold k*m doubles
+ * (pass k_out/m_out first with coef_out == NULL to query the size).
+ */
+int chebdm_block_coeffs(chebdm_handle h, const double* c, int32_t order, int32_t giant_form,
+                        int32_t k_override, int32_t* k_out, int32_t* m_out, double* coef_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHEBDM_H */

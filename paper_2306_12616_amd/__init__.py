@@ -1,0 +1,11 @@
+"""Dense Chebyshev Fermi-operator expansion on MI355X (gfx950).
+
+The computation lives in ``libchebdm.so`` (hand-written HIP kernels behind the
+C ABI of ``include/chebdm.h``); this package is its thin Python binding with
+the same entry-point names.  PyTorch provides device memory and streams.
+"""
+from ._binding import (  # noqa: F401
+    BF16X3, COMPOSITION, EXPORTED, FP32, FP64, LIB_PATH, POWER,
+    ChebdmError, Handle, Info, Opts, chebdm_block_coeffs, chebdm_bounds, chebdm_coeffs, chebdm_density,
+    chebdm_moments, chebdm_mu_search, load_library, make_opts,
+)

@@ -1,0 +1,249 @@
+"""ctypes binding of ``libchebdm.so``: argument marshalling only.
+
+Every step of the computation runs in the library's HIP kernels; this module
+turns torch tensors into device pointers and leading dimensions, picks up
+torch's current HIP stream, and converts status codes into exceptions.
+There is no fallback: if the library is missing the import of the first
+entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libchebdm.so")
+
+FP64, FP32, BF16X3 = 0, 1, 2
+COMPOSITION, POWER = 0, 1
+OK, WARN_NOCONV = 0, 1
+ERR_ARG, ERR_HIP, ERR_OOM, ERR_NONFINITE, ERR_BRACKET, ERR_UNSUPPORTED = -1, -2, -3, -4, -5, -6
+
+_PREC_NAMES = {"fp64": FP64, "f64": FP64, "fp32": FP32, "f32": FP32, "bf16x3": BF16X3}
+_FORM_NAMES = {"composition": COMPOSITION, "clenshaw": COMPOSITION, "power": POWER, "horner": POWER}
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("giant_form", ctypes.c_int32), ("k_override", ctypes.c_int32),
+                ("n_quad", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tol", ctypes.c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("m", ctypes.c_int32), ("n_gemm", ctypes.c_int32),
+                ("n_quad", ctypes.c_int32), ("iters", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("emin", ctypes.c_double), ("emax", ctypes.c_double), ("mu", ctypes.c_double),
+                ("trace", ctypes.c_double), ("trace_err", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ChebdmError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"chebdm error {code}: {message}")
+        self.code = code
+
+
+_lib = None
+
+_SIGNATURES = {
+    "chebdm_default_opts": (None, [ctypes.POINTER(Opts)]),
+    "chebdm_abi_version": (ctypes.c_int, []),
+    "chebdm_last_error": (ctypes.c_char_p, []),
+    "chebdm_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p]),
+    "chebdm_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "chebdm_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "chebdm_bounds": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "chebdm_coeffs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_double)]),
+    "chebdm_density": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(Opts),
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.POINTER(Info)]),
+    "chebdm_mu_search": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(Opts),
+                                        ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(Info)]),
+    "chebdm_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.c_int32, ctypes.POINTER(Opts), ctypes.c_double, ctypes.c_double,
+                                      ctypes.POINTER(ctypes.c_double)]),
+    "chebdm_block_coeffs": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                           ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
+}
+
+EXPORTED = tuple(_SIGNATURES)
+
+
+def load_library(path: str = LIB_PATH):
+    """Load ``libchebdm.so`` once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2306_12616_amd.build` "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, allow_warn: bool = False) -> int:
+    if rc < 0 or (rc > 0 and not allow_warn):
+        msg = load_library().chebdm_last_error().decode(errors="replace")
+        raise ChebdmError(rc, msg)
+    return rc
+
+
+def make_opts(prec="fp64", giant="composition", k_override: int = 0, n_quad: int = 0,
+              max_iter: int = 0, tol: float = 0.0) -> Opts:
+    o = Opts()
+    load_library().chebdm_default_opts(ctypes.byref(o))
+    o.prec = _PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
+    o.giant_form = _FORM_NAMES[giant] if isinstance(giant, str) else int(giant)
+    o.k_override = int(k_override)
+    o.n_quad = int(n_quad)
+    if max_iter:
+        o.max_iter = int(max_iter)
+    if tol:
+        o.tol = float(tol)
+    return o
+
+
+def _current_stream_ptr(device: int) -> int:
+    import torch
+
+    return int(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _matrix_args(t, name: str):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on a HIP device")
+    if t.dtype != torch.float64 or t.dim() != 2 or t.shape[0] != t.shape[1]:
+        raise TypeError(f"{name} must be a square float64 matrix")
+    if t.stride(1) != 1 or t.stride(0) < t.shape[0]:
+        raise TypeError(f"{name} must be row-major with leading dimension >= n")
+    return ctypes.c_void_p(t.data_ptr()), int(t.shape[0]), int(t.stride(0))
+
+
+class Handle:
+    """Owns a ``chebdm_handle`` bound to one device; follows torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        lib = load_library()
+        self.device = int(device)
+        self._stream = _current_stream_ptr(self.device)
+        h = ctypes.c_void_p()
+        _check(lib.chebdm_create(ctypes.byref(h), self.device, ctypes.c_void_p(self._stream)))
+        self._h = h
+
+    @property
+    def ptr(self):
+        s = _current_stream_ptr(self.device)
+        if s != self._stream:
+            _check(load_library().chebdm_set_stream(self._h, ctypes.c_void_p(s)))
+            self._stream = s
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().chebdm_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def chebdm_bounds(h: Handle, H):
+    p, n, ld = _matrix_args(H, "H")
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    _check(load_library().chebdm_bounds(h.ptr, p, n, ld, ctypes.byref(lo), ctypes.byref(hi)))
+    return lo.value, hi.value
+
+
+def chebdm_coeffs(h: Handle, beta: float, mu: float, emin: float, emax: float, order: int, n_quad: int = 0):
+    out = np.empty(order + 1, dtype=np.float64)
+    _check(load_library().chebdm_coeffs(h.ptr, beta, mu, emin, emax, order, n_quad,
+                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
+
+
+def chebdm_block_coeffs(h: Handle, c, order: int, giant="composition", k_override: int = 0):
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    if c.size < order + 1:
+        raise ValueError("need order + 1 coefficients")
+    form = _FORM_NAMES[giant] if isinstance(giant, str) else int(giant)
+    k, m = ctypes.c_int32(), ctypes.c_int32()
+    lib = load_library()
+    _check(lib.chebdm_block_coeffs(h.ptr, None, order, form, k_override, ctypes.byref(k), ctypes.byref(m), None))
+    out = np.empty(k.value * m.value, dtype=np.float64)
+    _check(lib.chebdm_block_coeffs(h.ptr, c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), order, form,
+                                   k_override, ctypes.byref(k), ctypes.byref(m),
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return k.value, m.value, out.reshape(m.value, k.value)
+
+
+def chebdm_density(h: Handle, H, beta: float, mu: float, order: int, opts: Optional[Opts] = None,
+                   emin: float = math.nan, emax: float = math.nan, D=None, want_info: bool = True):
+    import torch
+
+    p, n, ld = _matrix_args(H, "H")
+    if D is None:
+        D = torch.empty((n, n), dtype=torch.float64, device=H.device)
+    pd, nd, ldd = _matrix_args(D, "D")
+    if nd != n:
+        raise ValueError("D must match H's size")
+    info = Info()
+    _check(load_library().chebdm_density(h.ptr, p, n, ld, beta, mu, order,
+                                         ctypes.byref(opts) if opts is not None else None, emin, emax, pd, ldd,
+                                         ctypes.byref(info) if want_info else None))
+    return D, (info.as_dict() if want_info else None)
+
+
+def chebdm_mu_search(h: Handle, H, beta: float, n_elec: float, order: int, opts: Optional[Opts] = None,
+                     emin: float = math.nan, emax: float = math.nan, want_density: bool = True, D=None,
+                     allow_noconv: bool = True):
+    import torch
+
+    p, n, ld = _matrix_args(H, "H")
+    pd, ldd = None, n
+    if want_density:
+        if D is None:
+            D = torch.empty((n, n), dtype=torch.float64, device=H.device)
+        pd, nd, ldd = _matrix_args(D, "D")
+        if nd != n:
+            raise ValueError("D must match H's size")
+    else:
+        D = None
+    mu = ctypes.c_double()
+    info = Info()
+    rc = load_library().chebdm_mu_search(h.ptr, p, n, ld, beta, n_elec, order,
+                                         ctypes.byref(opts) if opts is not None else None, emin, emax,
+                                         ctypes.byref(mu), pd, ldd, ctypes.byref(info))
+    _check(rc, allow_warn=allow_noconv)
+    return mu.value, D, info.as_dict()
+
+
+def chebdm_moments(h: Handle, H, order: int, opts: Optional[Opts] = None, emin: float = math.nan,
+                   emax: float = math.nan):
+    p, n, ld = _matrix_args(H, "H")
+    out = np.empty(order + 1, dtype=np.float64)
+    _check(load_library().chebdm_moments(h.ptr, p, n, ld, order, ctypes.byref(opts) if opts is not None else None,
+                                         emin, emax, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out

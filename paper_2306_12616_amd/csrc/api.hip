@@ -1,0 +1,643 @@
+// Host runtime behind the C ABI: argument checks, the baby/giant-step plan,
+// the workspace, and the launch sequence of each entry point.
+//
+// Pipeline (Sec. II.B and III.B of the paper, readings noted in chebdm.h):
+//   bounds -> T_1 = H~ -> [mu search: moments -> bisection] -> c_n -> block
+//   coefficients -> baby steps (Algorithm 1 stages, one grouped launch per
+//   stage) -> block sums R_l (one pass) -> m-1 giant steps -> D.
+// Everything after the bounds runs on the device without host round trips;
+// the host needs the bounds once, to size the quadrature from beta'.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace chebdm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(CHEBDM_ERR_HIP, std::string(#expr) + " failed: " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define CHECK(call)                 \
+    do {                            \
+        int rc_ = (call);           \
+        if (rc_ < 0) return rc_;    \
+    } while (0)
+
+constexpr int64_t kMaxN = 65535;            // grid rows of the element-wise kernels
+constexpr int64_t kSmallVec = 48 * 48 + 64; // c, block coefficients, tau
+constexpr int64_t kPartialDoubles = 1024 * 48 * 48;  // Gram partials (>= Gershgorin partials)
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+struct Plan {
+    int64_t n = 0, ld = 0;
+    int order = 0, k = 1, m = 1, M = 0;
+    int prec = CHEBDM_FP64, form = CHEBDM_GIANT_COMPOSITION;
+    int max_iter = 200;
+    double tol = 1e-10;
+    size_t elem = 8;
+    int n_gemm = 0;
+};
+
+}  // namespace
+
+struct chebdm_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    // matrix workspace: T_1..T_k then R_0..R_{m-1}, each ld x ld
+    void* mats = nullptr;
+    size_t mats_bytes = 0;
+    int64_t lay_n = -1, lay_ld = -1, lay_count = -1;
+    size_t lay_elem = 0;
+    // small device buffers
+    void* small = nullptr;
+    size_t small_bytes = 0;
+    int64_t small_M = 0;
+    DevScalars* scal = nullptr;
+    double *c = nullptr, *coef = nullptr, *tau = nullptr, *trb = nullptr, *gram = nullptr, *trD = nullptr;
+    double *ftab = nullptr, *xtab = nullptr, *w = nullptr, *partial = nullptr;
+    // pinned host mirror for read-backs
+    DevScalars* h_scal = nullptr;
+    double* h_trD = nullptr;
+};
+
+namespace {
+
+int set_device(chebdm_handle h) {
+    HIP_TRY(hipSetDevice(h->device));
+    return 0;
+}
+
+int ensure_small(chebdm_handle h, int64_t M) {
+    if (h->small && M <= h->small_M) return 0;
+    if (h->small) {
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        HIP_TRY(hipFree(h->small));
+        h->small = nullptr;
+    }
+    const int64_t Mcap = M < 4096 ? 4096 : M;
+    const int64_t doubles = 64 /*scalars*/ + 4 * kSmallVec + 48 * 48 + 64 + 3 * Mcap + kPartialDoubles;
+    const size_t bytes = (size_t)doubles * sizeof(double);
+    if (hipMalloc(&h->small, bytes) != hipSuccess) {
+        h->small = nullptr;
+        (void)hipGetLastError();
+        return fail(CHEBDM_ERR_OOM, "cannot allocate " + std::to_string(bytes) + " bytes of scalar workspace");
+    }
+    double* p = static_cast<double*>(h->small);
+    h->scal = reinterpret_cast<DevScalars*>(p);
+    p += 64;
+    h->c = p; p += kSmallVec;
+    h->coef = p; p += kSmallVec;
+    h->tau = p; p += kSmallVec;
+    h->trb = p; p += kSmallVec;
+    h->gram = p; p += 48 * 48;
+    h->trD = p; p += 64;
+    h->ftab = p; p += Mcap;
+    h->xtab = p; p += Mcap;
+    h->w = p; p += Mcap;
+    h->partial = p;
+    h->small_bytes = bytes;
+    h->small_M = Mcap;
+    return 0;
+}
+
+int ensure_mats(chebdm_handle h, const Plan& pl, int64_t count) {
+    const size_t bytes = (size_t)count * (size_t)pl.ld * (size_t)pl.ld * pl.elem;
+    if (bytes > h->mats_bytes) {
+        if (h->mats) {
+            HIP_TRY(hipStreamSynchronize(h->stream));
+            HIP_TRY(hipFree(h->mats));
+            h->mats = nullptr;
+            h->mats_bytes = 0;
+        }
+        if (hipMalloc(&h->mats, bytes) != hipSuccess) {
+            h->mats = nullptr;
+            (void)hipGetLastError();
+            return fail(CHEBDM_ERR_OOM, "cannot allocate " + std::to_string(bytes) + " bytes of matrix workspace");
+        }
+        h->mats_bytes = bytes;
+        h->lay_ld = -1;
+    }
+    // The kernels rely on a zero padding outside each n x n block; a new
+    // layout (n, leading dimension, element size or a larger count) is cleared once.
+    if (h->lay_n != pl.n || h->lay_ld != pl.ld || h->lay_elem != pl.elem || h->lay_count < count) {
+        HIP_TRY(hipMemsetAsync(h->mats, 0, bytes, h->stream));
+        h->lay_n = pl.n;
+        h->lay_ld = pl.ld;
+        h->lay_elem = pl.elem;
+        h->lay_count = count;
+    }
+    return 0;
+}
+
+// matrix slot s (0-based) of the workspace
+void* slot(chebdm_handle h, const Plan& pl, int64_t s) {
+    return static_cast<char*>(h->mats) + (size_t)s * (size_t)pl.ld * (size_t)pl.ld * pl.elem;
+}
+
+int read_scalars(chebdm_handle h) {
+    HIP_TRY(hipMemcpyAsync(h->h_scal, h->scal, sizeof(DevScalars), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->h_trD, h->trD, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+int quadrature_rule(int order, double beta_s) {
+    const double need = std::fmax(2.0 * (order + 1), 0.5 * order + 7.0 * beta_s + 64.0);
+    const double lg = std::ceil(std::log2(need));
+    if (!(lg < 30.0)) return -1;
+    return 1 << (int)lg;
+}
+
+int check_opts(const chebdm_opts* o, Plan& pl) {
+    chebdm_opts d;
+    chebdm_default_opts(&d);
+    if (!o) o = &d;
+    if (o->prec < CHEBDM_FP64 || o->prec > CHEBDM_BF16X3) return fail(CHEBDM_ERR_ARG, "unknown precision");
+    if (o->giant_form != CHEBDM_GIANT_COMPOSITION && o->giant_form != CHEBDM_GIANT_POWER)
+        return fail(CHEBDM_ERR_ARG, "unknown giant-step form");
+    if (o->giant_form == CHEBDM_GIANT_POWER && o->prec != CHEBDM_FP64)
+        return fail(CHEBDM_ERR_UNSUPPORTED,
+                    "the power form is float64 only: its coefficients grow like 2^m |c|");
+    if (o->k_override < 0 || o->n_quad < 0 || o->max_iter < 0 || !(o->tol >= 0.0))
+        return fail(CHEBDM_ERR_ARG, "negative option");
+    pl.prec = o->prec;
+    pl.form = o->giant_form;
+    pl.elem = o->prec == CHEBDM_FP64 ? 8 : 4;
+    pl.max_iter = o->max_iter ? o->max_iter : 200;
+    pl.tol = o->tol > 0.0 ? o->tol : 1e-10;
+    pl.M = o->n_quad;
+    pl.k = o->k_override;
+    return 0;
+}
+
+int plan_split(Plan& pl) {
+    const int64_t ncoef = (int64_t)pl.order + 1;
+    int64_t k = pl.k;
+    if (k <= 0) {
+        k = (int64_t)std::sqrt((double)ncoef);
+        while (k * k < ncoef) ++k;
+        while (k > 1 && (k - 1) * (k - 1) >= ncoef) --k;
+    }
+    const int64_t m = (ncoef + k - 1) / k;
+    if (k > kMaxBlocks || m > kMaxBlocks)
+        return fail(CHEBDM_ERR_ARG, "order " + std::to_string(pl.order) + " with k=" + std::to_string(k) +
+                                        " needs more than 48 baby steps or blocks");
+    pl.k = (int)k;
+    pl.m = (int)m;
+    return 0;
+}
+
+int validate_matrix(const void* dH, int64_t n, int64_t ldh) {
+    if (!dH) return fail(CHEBDM_ERR_ARG, "H is NULL");
+    if (n < 1 || n > kMaxN) return fail(CHEBDM_ERR_ARG, "n must be in [1, 65535]");
+    if (ldh < n) return fail(CHEBDM_ERR_ARG, "leading dimension smaller than n");
+    return 0;
+}
+
+// Bounds: the caller's, or Gershgorin's computed here (one read-back).
+int resolve_bounds(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, double& emin, double& emax) {
+    if (std::isnan(emin) || std::isnan(emax)) {
+        CHECK(ensure_small(h, 0));
+        HIP_TRY(launch_gershgorin(dH, n, ldh, h->partial, kPartialDoubles, h->scal, h->stream));
+        CHECK(read_scalars(h));
+        if (h->h_scal->nonfinite) return fail(CHEBDM_ERR_NONFINITE, "H holds NaN or Inf");
+        emin = h->h_scal->emin;
+        emax = h->h_scal->emax;
+    }
+    if (!std::isfinite(emin) || !std::isfinite(emax) || emax < emin)
+        return fail(CHEBDM_ERR_ARG, "bounds must be finite with emin <= emax");
+    return 0;
+}
+
+int plan_quadrature(Plan& pl, double beta, double emin, double emax) {
+    const double beta_s = beta * 0.5 * (emax - emin);
+    if (pl.M <= 0) pl.M = quadrature_rule(pl.order, beta_s);
+    if (pl.M <= 0) return fail(CHEBDM_ERR_ARG, "beta' too large for the quadrature rule");
+    if (pl.M < pl.order + 1) return fail(CHEBDM_ERR_ARG, "n_quad must be at least order + 1");
+    if (pl.M > (1 << 26)) return fail(CHEBDM_ERR_ARG, "n_quad above 2^26");
+    return 0;
+}
+
+// ---------------------------------------------------------------- GEMM helper
+
+struct Chain {
+    chebdm_handle h;
+    const Plan& pl;
+    int* n_gemm;
+    GemmBatch<double> b64;
+    GemmBatch<float> b32;
+
+    Chain(chebdm_handle hh, const Plan& p, int* ng) : h(hh), pl(p), n_gemm(ng) {
+        b64.count = 0;
+        b32.count = 0;
+    }
+    // Out = alpha A B + beta C + gamma E + delta I
+    void add(const void* A, const void* B, const void* C, double beta, const void* E, double gamma,
+             double alpha, double delta, void* Out, int64_t ld_out, int out_f64) {
+        if (pl.elem == 8) {
+            GemmDesc<double>& d = b64.d[b64.count++];
+            d = GemmDesc<double>{(const double*)A, (const double*)B, (const double*)C, (const double*)E, Out,
+                                 ld_out, alpha, beta, gamma, delta, out_f64, 0};
+        } else {
+            GemmDesc<float>& d = b32.d[b32.count++];
+            d = GemmDesc<float>{(const float*)A, (const float*)B, (const float*)C, (const float*)E, Out,
+                                ld_out, alpha, beta, gamma, delta, out_f64, 0};
+        }
+        ++*n_gemm;
+    }
+    int flush() {
+        hipError_t e = hipSuccess;
+        if (pl.elem == 8 && b64.count) e = launch_gemm_f64(b64, pl.n, pl.ld, h->stream);
+        if (pl.elem == 4 && b32.count)
+            e = launch_gemm_f32(b32, pl.n, pl.ld, pl.prec == CHEBDM_BF16X3, h->stream);
+        b64.count = 0;
+        b32.count = 0;
+        HIP_TRY(e);
+        return 0;
+    }
+};
+
+// T_i for i >= 1 lives in slot i-1.
+void* tslot(chebdm_handle h, const Plan& pl, int i) { return slot(h, pl, i - 1); }
+// R_l lives in slot k + l.
+void* rslot(chebdm_handle h, const Plan& pl, int l) { return slot(h, pl, pl.k + l); }
+
+// Baby steps T_2..T_k in the stages of Algorithm 1: stage 1 makes T_2; stage
+// s >= 2 makes T_{2^{s-2}+i} and T_{2^{s-1}+i} from already known T's.  The
+// products of one stage are independent and go out as one grouped launch.
+int baby_steps(chebdm_handle h, const Plan& pl, int* n_gemm) {
+    if (pl.k < 2) return 0;
+    Chain ch(h, pl, n_gemm);
+    // stage 1: T_2 = 2 T_1 T_1 - T_0
+    ch.add(tslot(h, pl, 1), tslot(h, pl, 1), nullptr, 0.0, nullptr, 0.0, 2.0, -1.0, tslot(h, pl, 2), pl.ld, 0);
+    CHECK(ch.flush());
+    for (int s = 2;; ++s) {
+        const int u = 1 << (s - 2), v = 1 << (s - 1);
+        if (u + 1 + u > pl.k && v + u + 1 > pl.k) break;
+        for (int i = u + 1; i <= v; ++i)
+            if (i + u <= pl.k) {
+                // T_{i+u} = 2 T_i T_u - T_{i-u}
+                const int r = i - u;
+                ch.add(tslot(h, pl, i), tslot(h, pl, u), r == 0 ? nullptr : tslot(h, pl, r), -1.0, nullptr, 0.0,
+                       2.0, r == 0 ? -1.0 : 0.0, tslot(h, pl, i + u), pl.ld, 0);
+            }
+        for (int i = u + 1; i <= v; ++i)
+            if (i + v <= pl.k) {
+                // T_{i+v} = 2 T_v T_i - T_{v-i}
+                const int r = v - i;
+                ch.add(tslot(h, pl, v), tslot(h, pl, i), r == 0 ? nullptr : tslot(h, pl, r), -1.0, nullptr, 0.0,
+                       2.0, r == 0 ? -1.0 : 0.0, tslot(h, pl, i + v), pl.ld, 0);
+            }
+        CHECK(ch.flush());
+        if (v >= pl.k) break;
+    }
+    return 0;
+}
+
+// Ladder T_{2k}, ..., T_{lmax k} (T_{lk} in R slot l-2) and the moments tau_0..tau_L.
+int moments_on_device(chebdm_handle h, const Plan& pl, int* n_gemm) {
+    const int k = pl.k, L = pl.order;
+    int lmax = (L >= 1) ? (L - 1) / k : 0;
+    if (lmax > pl.m - 1) lmax = pl.m - 1;
+    auto lptr = [&](int l) -> void* { return l == 1 ? tslot(h, pl, k) : rslot(h, pl, l - 2); };
+    Chain ch(h, pl, n_gemm);
+    for (int l = 1; l + 1 <= lmax; ++l) {
+        // T_{(l+1)k} = 2 T_k T_{lk} - T_{(l-1)k}
+        if (l == 1)
+            ch.add(tslot(h, pl, k), tslot(h, pl, k), nullptr, 0.0, nullptr, 0.0, 2.0, -1.0, lptr(2), pl.ld, 0);
+        else
+            ch.add(tslot(h, pl, k), lptr(l), lptr(l - 1), -1.0, nullptr, 0.0, 2.0, 0.0, lptr(l + 1), pl.ld, 0);
+        CHECK(ch.flush());
+    }
+    const int64_t stride = pl.ld * pl.ld;
+    HIP_TRY(launch_traces(tslot(h, pl, 1), stride, k, pl.n, pl.ld, pl.elem == 8, h->trb, h->stream));
+    if (lmax >= 1) {
+        std::vector<const void*> lm(lmax), tm(k);
+        for (int l = 1; l <= lmax; ++l) lm[l - 1] = lptr(l);
+        for (int i = 1; i <= k; ++i) tm[i - 1] = tslot(h, pl, i);
+        const int64_t nelem = pl.n * pl.ld;
+        if (pl.elem == 8)
+            HIP_TRY(launch_gram<double>((const double* const*)lm.data(), lmax, (const double* const*)tm.data(), k,
+                                        nelem, h->partial, kPartialDoubles, h->gram, h->stream));
+        else
+            HIP_TRY(launch_gram<float>((const float* const*)lm.data(), lmax, (const float* const*)tm.data(), k,
+                                       nelem, h->partial, kPartialDoubles, h->gram, h->stream));
+    }
+    HIP_TRY(launch_assemble_moments(h->trb, h->gram, k, pl.m, L, pl.n, h->tau, h->stream));
+    return 0;
+}
+
+// Block sums R_l (or S_j) and the giant steps; writes D (ldd) and its trace.
+int giant_steps(chebdm_handle h, const Plan& pl, double* dD, int64_t ldd, int* n_gemm) {
+    const int k = pl.k, m = pl.m;
+    const int64_t stride = pl.ld * pl.ld;
+    if (pl.elem == 8)
+        HIP_TRY(launch_combine<double>((const double*)tslot(h, pl, 1), stride, k, m, h->coef,
+                                       (double*)rslot(h, pl, 0), pl.n, pl.ld, h->stream));
+    else
+        HIP_TRY(launch_combine<float>((const float*)tslot(h, pl, 1), stride, k, m, h->coef,
+                                      (float*)rslot(h, pl, 0), pl.n, pl.ld, h->stream));
+    if (m == 1) {
+        HIP_TRY(launch_copy_out(rslot(h, pl, 0), pl.elem == 8, pl.ld, pl.n, dD, ldd, h->stream));
+    } else {
+        void* Y = k >= 1 ? tslot(h, pl, k) : nullptr;
+        Chain ch(h, pl, n_gemm);
+        if (pl.form == CHEBDM_GIANT_COMPOSITION) {
+            // Clenshaw over l with Y = T_k: B_{m-1} = R_{m-1};
+            // B_l = R_l + 2 Y B_{l+1} - B_{l+2} (in place in R_l); D = R_0 + Y B_1 - B_2.
+            for (int l = m - 2; l >= 1; --l) {
+                const void* b2 = (l + 2 <= m - 1) ? rslot(h, pl, l + 2) : nullptr;
+                ch.add(Y, rslot(h, pl, l + 1), b2, -1.0, rslot(h, pl, l), 1.0, 2.0, 0.0, rslot(h, pl, l), pl.ld, 0);
+                CHECK(ch.flush());
+            }
+            const void* b2 = (m >= 3) ? rslot(h, pl, 2) : nullptr;
+            ch.add(Y, rslot(h, pl, 1), b2, -1.0, rslot(h, pl, 0), 1.0, 1.0, 0.0, dD, ldd, 1);
+            CHECK(ch.flush());
+        } else {
+            // Horner with T_k (eq. "ansatz"): R = S_{m-1}; R <- S_j + T_k R, j = m-2..0.
+            for (int j = m - 2; j >= 1; --j) {
+                ch.add(Y, rslot(h, pl, j + 1), nullptr, 0.0, rslot(h, pl, j), 1.0, 1.0, 0.0, rslot(h, pl, j), pl.ld, 0);
+                CHECK(ch.flush());
+            }
+            ch.add(Y, rslot(h, pl, 1), nullptr, 0.0, rslot(h, pl, 0), 1.0, 1.0, 0.0, dD, ldd, 1);
+            CHECK(ch.flush());
+        }
+    }
+    HIP_TRY(launch_trace_f64(dD, pl.n, ldd, h->trD, h->stream));
+    return 0;
+}
+
+void fill_info(chebdm_info* info, const Plan& pl, double emin, double emax, double mu, double trace,
+               double trace_err, int iters, int status) {
+    if (!info) return;
+    info->k = pl.k;
+    info->m = pl.m;
+    info->n_gemm = pl.n_gemm;
+    info->n_quad = pl.M;
+    info->iters = iters;
+    info->status = status;
+    info->emin = emin;
+    info->emax = emax;
+    info->mu = mu;
+    info->trace = trace;
+    info->trace_err = trace_err;
+}
+
+double fermi_energy(double e, double beta, double mu) { return 1.0 / (1.0 + std::exp(beta * (e - mu))); }
+
+}  // namespace
+
+// =================================================================== C ABI
+
+extern "C" {
+
+void chebdm_default_opts(chebdm_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->prec = CHEBDM_FP64;
+    o->giant_form = CHEBDM_GIANT_COMPOSITION;
+    o->max_iter = 200;
+    o->tol = 1e-10;
+}
+
+int chebdm_abi_version(void) { return CHEBDM_ABI_VERSION; }
+
+const char* chebdm_last_error(void) { return g_last_error.c_str(); }
+
+int chebdm_create(chebdm_handle* out, int device, void* stream) {
+    if (!out) return fail(CHEBDM_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    HIP_TRY(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return fail(CHEBDM_ERR_ARG, "no such HIP device");
+    HIP_TRY(hipSetDevice(device));
+    chebdm_ctx* h = new (std::nothrow) chebdm_ctx();
+    if (!h) return fail(CHEBDM_ERR_OOM, "cannot allocate handle");
+    h->device = device;
+    h->stream = static_cast<hipStream_t>(stream);
+    if (hipHostMalloc((void**)&h->h_scal, sizeof(DevScalars) + 64, hipHostMallocDefault) != hipSuccess) {
+        delete h;
+        return fail(CHEBDM_ERR_OOM, "cannot allocate pinned host memory");
+    }
+    h->h_trD = reinterpret_cast<double*>(reinterpret_cast<char*>(h->h_scal) + sizeof(DevScalars) + 8);
+    g_last_error.clear();
+    *out = h;
+    return CHEBDM_OK;
+}
+
+int chebdm_destroy(chebdm_handle h) {
+    if (!h) return CHEBDM_OK;
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    if (h->mats) (void)hipFree(h->mats);
+    if (h->small) (void)hipFree(h->small);
+    if (h->h_scal) (void)hipHostFree(h->h_scal);
+    delete h;
+    return CHEBDM_OK;
+}
+
+int chebdm_set_stream(chebdm_handle h, void* stream) {
+    if (!h) return fail(CHEBDM_ERR_ARG, "handle is NULL");
+    h->stream = static_cast<hipStream_t>(stream);
+    return CHEBDM_OK;
+}
+
+int chebdm_bounds(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, double* emin, double* emax) {
+    if (!h || !emin || !emax) return fail(CHEBDM_ERR_ARG, "NULL argument");
+    CHECK(validate_matrix(dH, n, ldh));
+    CHECK(set_device(h));
+    double lo = NAN, hi = NAN;
+    CHECK(resolve_bounds(h, dH, n, ldh, lo, hi));
+    *emin = lo;
+    *emax = hi;
+    return CHEBDM_OK;
+}
+
+int chebdm_coeffs(chebdm_handle h, double beta, double mu, double emin, double emax, int32_t order,
+                  int32_t n_quad, double* c_out) {
+    if (!h || !c_out) return fail(CHEBDM_ERR_ARG, "NULL argument");
+    if (order < 0 || order + 1 > kSmallVec) return fail(CHEBDM_ERR_ARG, "order out of range");
+    if (!(beta > 0.0) || !std::isfinite(beta) || !std::isfinite(mu)) return fail(CHEBDM_ERR_ARG, "beta must be > 0");
+    if (!std::isfinite(emin) || !std::isfinite(emax) || !(emax > emin))
+        return fail(CHEBDM_ERR_ARG, "need finite emin < emax");
+    if (n_quad < 0) return fail(CHEBDM_ERR_ARG, "n_quad < 0");
+    CHECK(set_device(h));
+    Plan pl;
+    pl.order = order;
+    pl.M = n_quad;
+    CHECK(plan_quadrature(pl, beta, emin, emax));
+    CHECK(ensure_small(h, pl.M));
+    HIP_TRY(launch_set_scalars(h->scal, emin, emax, beta, mu, 1, 0.0, 0.0, 0, h->stream));
+    HIP_TRY(launch_fermi_coeffs(order, pl.M, h->scal, h->ftab, h->c, h->stream));
+    HIP_TRY(hipMemcpyAsync(c_out, h->c, sizeof(double) * (size_t)(order + 1), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return CHEBDM_OK;
+}
+
+int chebdm_block_coeffs(chebdm_handle h, const double* c, int32_t order, int32_t giant_form, int32_t k_override,
+                        int32_t* k_out, int32_t* m_out, double* coef_out) {
+    if (!h || !k_out || !m_out) return fail(CHEBDM_ERR_ARG, "NULL argument");
+    if (order < 0) return fail(CHEBDM_ERR_ARG, "order < 0");
+    if (giant_form != CHEBDM_GIANT_COMPOSITION && giant_form != CHEBDM_GIANT_POWER)
+        return fail(CHEBDM_ERR_ARG, "unknown giant-step form");
+    if (k_override < 0) return fail(CHEBDM_ERR_ARG, "k_override < 0");
+    Plan pl;
+    pl.order = order;
+    pl.k = k_override;
+    CHECK(plan_split(pl));
+    *k_out = pl.k;
+    *m_out = pl.m;
+    if (!coef_out) return CHEBDM_OK;
+    if (!c) return fail(CHEBDM_ERR_ARG, "c is NULL");
+    CHECK(set_device(h));
+    CHECK(ensure_small(h, 0));
+    HIP_TRY(hipMemcpyAsync(h->c, c, sizeof(double) * (size_t)(order + 1), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(launch_block_coeffs(h->c, order, pl.k, pl.m, giant_form, h->coef, h->stream));
+    HIP_TRY(hipMemcpyAsync(coef_out, h->coef, sizeof(double) * (size_t)pl.k * pl.m, hipMemcpyDeviceToHost,
+                           h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return CHEBDM_OK;
+}
+
+int chebdm_density(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, double beta, double mu,
+                   int32_t order, const chebdm_opts* opts, double emin, double emax, double* dD, int64_t ldd,
+                   chebdm_info* info) {
+    if (!h) return fail(CHEBDM_ERR_ARG, "handle is NULL");
+    CHECK(validate_matrix(dH, n, ldh));
+    if (!dD || ldd < n) return fail(CHEBDM_ERR_ARG, "D is NULL or ldd < n");
+    if (order < 0) return fail(CHEBDM_ERR_ARG, "order < 0");
+    if (!(beta > 0.0) || !std::isfinite(beta) || !std::isfinite(mu)) return fail(CHEBDM_ERR_ARG, "beta must be > 0");
+    Plan pl;
+    pl.n = n;
+    pl.order = order;
+    CHECK(check_opts(opts, pl));
+    CHECK(plan_split(pl));
+    CHECK(set_device(h));
+    CHECK(resolve_bounds(h, dH, n, ldh, emin, emax));
+    CHECK(ensure_small(h, 0));
+    if (emax == emin) {
+        // H = cI: D = f(c) I exactly (no spectrum map exists)
+        const double occ = fermi_energy(emin, beta, mu);
+        HIP_TRY(launch_fill_identity(dD, n, ldd, occ, h->stream));
+        if (info) {
+            HIP_TRY(hipStreamSynchronize(h->stream));
+            pl.M = 0;
+            fill_info(info, pl, emin, emax, mu, occ * (double)n, 0.0, 0, CHEBDM_OK);
+        }
+        return CHEBDM_OK;
+    }
+    CHECK(plan_quadrature(pl, beta, emin, emax));
+    CHECK(ensure_small(h, pl.M));
+    pl.ld = round_up(n, 128);
+    CHECK(ensure_mats(h, pl, pl.k + pl.m));
+    HIP_TRY(launch_set_scalars(h->scal, emin, emax, beta, mu, 1, 0.0, pl.tol, pl.max_iter, h->stream));
+    HIP_TRY(launch_shift(dH, n, ldh, h->scal, tslot(h, pl, 1), pl.ld, pl.prec, h->stream));
+    HIP_TRY(launch_fermi_coeffs(order, pl.M, h->scal, h->ftab, h->c, h->stream));
+    HIP_TRY(launch_block_coeffs(h->c, order, pl.k, pl.m, pl.form, h->coef, h->stream));
+    CHECK(baby_steps(h, pl, &pl.n_gemm));
+    CHECK(giant_steps(h, pl, dD, ldd, &pl.n_gemm));
+    if (info) {
+        CHECK(read_scalars(h));
+        fill_info(info, pl, emin, emax, mu, *h->h_trD, 0.0, 0, CHEBDM_OK);
+    }
+    return CHEBDM_OK;
+}
+
+int chebdm_mu_search(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, double beta, double n_elec,
+                     int32_t order, const chebdm_opts* opts, double emin, double emax, double* mu_out, double* dD,
+                     int64_t ldd, chebdm_info* info) {
+    if (!h || !mu_out) return fail(CHEBDM_ERR_ARG, "NULL argument");
+    CHECK(validate_matrix(dH, n, ldh));
+    if (dD && ldd < n) return fail(CHEBDM_ERR_ARG, "ldd < n");
+    if (order < 0) return fail(CHEBDM_ERR_ARG, "order < 0");
+    if (!(beta > 0.0) || !std::isfinite(beta)) return fail(CHEBDM_ERR_ARG, "beta must be > 0");
+    if (!(n_elec > 0.0) || !(n_elec < (double)n)) return fail(CHEBDM_ERR_ARG, "need 0 < n_elec < n");
+    Plan pl;
+    pl.n = n;
+    pl.order = order;
+    CHECK(check_opts(opts, pl));
+    CHECK(plan_split(pl));
+    CHECK(set_device(h));
+    CHECK(resolve_bounds(h, dH, n, ldh, emin, emax));
+    CHECK(ensure_small(h, 0));
+    if (emax == emin) {
+        // H = cI: tr f(c) I = n_elec fixes the occupation n_elec/n and mu in closed form
+        const double occ = n_elec / (double)n;
+        const double mu = emin - std::log(1.0 / occ - 1.0) / beta;
+        *mu_out = mu;
+        if (dD) HIP_TRY(launch_fill_identity(dD, n, ldd, occ, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        fill_info(info, pl, emin, emax, mu, n_elec, 0.0, 0, CHEBDM_OK);
+        return CHEBDM_OK;
+    }
+    CHECK(plan_quadrature(pl, beta, emin, emax));
+    CHECK(ensure_small(h, pl.M));
+    pl.ld = round_up(n, 128);
+    CHECK(ensure_mats(h, pl, pl.k + pl.m));
+    HIP_TRY(launch_set_scalars(h->scal, emin, emax, beta, 0.0, 0, n_elec, pl.tol, pl.max_iter, h->stream));
+    HIP_TRY(launch_shift(dH, n, ldh, h->scal, tslot(h, pl, 1), pl.ld, pl.prec, h->stream));
+    CHECK(baby_steps(h, pl, &pl.n_gemm));
+    CHECK(moments_on_device(h, pl, &pl.n_gemm));
+    HIP_TRY(launch_dct3(h->tau, order, pl.M, h->w, h->xtab, h->stream));
+    HIP_TRY(launch_bisect(h->w, h->xtab, pl.M, h->scal, h->stream));
+    if (dD) {
+        HIP_TRY(launch_fermi_coeffs(order, pl.M, h->scal, h->ftab, h->c, h->stream));
+        HIP_TRY(launch_block_coeffs(h->c, order, pl.k, pl.m, pl.form, h->coef, h->stream));
+        CHECK(giant_steps(h, pl, dD, ldd, &pl.n_gemm));
+    }
+    CHECK(read_scalars(h));
+    const DevScalars& s = *h->h_scal;
+    const double mu = s.cen + s.half * s.mu_s;
+    *mu_out = mu;
+    const int status = s.status;
+    const double tr = dD ? *h->h_trD : s.trace;
+    fill_info(info, pl, emin, emax, mu, tr, std::fabs(s.trace - n_elec), s.iters, status);
+    if (status == CHEBDM_ERR_BRACKET)
+        return fail(CHEBDM_ERR_BRACKET, "n_elec is not inside (t(mu~=-1), t(mu~=1)) of the expansion");
+    return status;
+}
+
+int chebdm_moments(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, int32_t order,
+                   const chebdm_opts* opts, double emin, double emax, double* tau_out) {
+    if (!h || !tau_out) return fail(CHEBDM_ERR_ARG, "NULL argument");
+    CHECK(validate_matrix(dH, n, ldh));
+    if (order < 0) return fail(CHEBDM_ERR_ARG, "order < 0");
+    Plan pl;
+    pl.n = n;
+    pl.order = order;
+    CHECK(check_opts(opts, pl));
+    CHECK(plan_split(pl));
+    CHECK(set_device(h));
+    CHECK(resolve_bounds(h, dH, n, ldh, emin, emax));
+    if (!(emax > emin)) return fail(CHEBDM_ERR_ARG, "moments need emin < emax");
+    CHECK(ensure_small(h, 0));
+    pl.ld = round_up(n, 128);
+    CHECK(ensure_mats(h, pl, pl.k + pl.m));
+    HIP_TRY(launch_set_scalars(h->scal, emin, emax, 1.0, 0.0, 0, 0.0, pl.tol, pl.max_iter, h->stream));
+    HIP_TRY(launch_shift(dH, n, ldh, h->scal, tslot(h, pl, 1), pl.ld, pl.prec, h->stream));
+    CHECK(baby_steps(h, pl, &pl.n_gemm));
+    CHECK(moments_on_device(h, pl, &pl.n_gemm));
+    HIP_TRY(hipMemcpyAsync(tau_out, h->tau, sizeof(double) * (size_t)(order + 1), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return CHEBDM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Internal declarations shared by the kernel files and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "chebdm.h"
+
+namespace chebdm {
+
+// Scalars that live on the device so that a pipeline can run without host
+// round trips (bounds -> scaling -> mu -> coefficients).
+struct DevScalars {
+    double emin, emax;    // spectral bounds
+    double cen, half;     // H~ = (H - cen I) / half
+    double beta_s;        // beta' = beta * half
+    double mu_s;          // mu~ = (mu - cen) / half
+    double trace;         // t(mu~) from the bisection, or tr D
+    double n_elec;        // target electron count
+    double tol;           // bisection tolerance
+    double lo, hi;        // final bracket
+    int32_t nonfinite;    // H held NaN/Inf
+    int32_t status;       // CHEBDM_OK / WARN_NOCONV / ERR_BRACKET
+    int32_t iters;        // bisection sweeps
+    int32_t max_iter;
+};
+
+constexpr int kMaxGroup = 32;   // GEMMs per grouped launch (one Algorithm-1 stage)
+constexpr int kMaxBlocks = 48;  // max k and max m (order <= 48*48 - 1)
+
+// One product of the chain: Out = alpha * A B + beta * C + gamma * E + delta * I.
+// A and B are symmetric polynomials of H~ (so A B is symmetric and both
+// operands may be read along rows); C, E may be null.
+template <typename T>
+struct GemmDesc {
+    const T* A;
+    const T* B;
+    const T* C;
+    const T* E;
+    void* Out;          // T* (workspace) or double* (final D) - see out_f64
+    int64_t ld_out;
+    double alpha, beta, gamma, delta;
+    int32_t out_f64;    // 1: Out is a double matrix (final density), else T
+    int32_t pad;
+};
+
+template <typename T>
+struct GemmBatch {
+    GemmDesc<T> d[kMaxGroup];
+    int32_t count;
+};
+
+// ---- bounds / shift / traces (k_bounds.hip)
+hipError_t launch_gershgorin(const double* H, int64_t n, int64_t ldh, double* partial,
+                             int64_t partial_cap, DevScalars* s, hipStream_t st);
+hipError_t launch_set_scalars(DevScalars* s, double emin, double emax, double beta, double mu,
+                              int has_mu, double n_elec, double tol, int max_iter, hipStream_t st);
+hipError_t launch_shift(const double* H, int64_t n, int64_t ldh, const DevScalars* s, void* T1,
+                        int64_t ldw, int prec, hipStream_t st);
+// traces of `count` matrices spaced `stride` elements apart (float or double), into out[0..count)
+hipError_t launch_traces(const void* base, int64_t stride, int count, int64_t n, int64_t ld,
+                         int is_f64, double* out, hipStream_t st);
+hipError_t launch_trace_f64(const double* D, int64_t n, int64_t ld, double* out, hipStream_t st);
+hipError_t launch_fill_identity(double* D, int64_t n, int64_t ldd, double value, hipStream_t st);
+hipError_t launch_copy_out(const void* src, int is_f64, int64_t ld, int64_t n, double* D, int64_t ldd,
+                           hipStream_t st);
+
+// ---- coefficients / decomposition / moments / bisection (k_cheb.hip)
+hipError_t launch_fermi_coeffs(int order, int M, const DevScalars* s, double* f_tab, double* c_out,
+                               hipStream_t st);
+hipError_t launch_block_coeffs(const double* c, int order, int k, int m, int form, double* coef,
+                               hipStream_t st);
+hipError_t launch_assemble_moments(const double* tr_baby, const double* gram, int k, int m,
+                                   int order, int64_t n, double* tau, hipStream_t st);
+hipError_t launch_dct3(const double* tau, int order, int M, double* w, double* x_tab,
+                       hipStream_t st);
+hipError_t launch_bisect(const double* w, const double* x_tab, int M, DevScalars* s,
+                         hipStream_t st);
+
+// ---- block sums and Gram contractions (k_combine.hip)
+// R_l = sum_{i<k} coef[l*k + i] T_i for l < m (T_0 = I implicit, T_i = tbase + (i-1)*stride)
+template <typename T>
+hipError_t launch_combine(const T* tbase, int64_t stride, int k, int m, const double* coef,
+                          T* rbase, int64_t n, int64_t ld, hipStream_t st);
+// G[l][i] = <L_l, T_i> (Frobenius) for l < nl, i < nt; L_l, T_i given by pointer lists
+template <typename T>
+hipError_t launch_gram(const T* const* lmats, int nl, const T* const* tmats, int nt, int64_t nelem,
+                       double* partial, int64_t partial_cap, double* G, hipStream_t st);
+
+// ---- matrix products (k_gemm.hip)
+hipError_t launch_gemm_f64(const GemmBatch<double>& b, int64_t n, int64_t ld, hipStream_t st);
+hipError_t launch_gemm_f32(const GemmBatch<float>& b, int64_t n, int64_t ld, int bf16x3,
+                           hipStream_t st);
+
+}  // namespace chebdm

@@ -1,0 +1,236 @@
+// Block sums and Gram contractions over the stack of Chebyshev matrices.
+//
+// Combine (Sec. III.B: the block sums S_j = sum_i d_{i,j} T_i are independent
+// and can be formed together): all m blocks R_l = sum_{i<k} coef[l][i] T_i
+// in one pass over T_1..T_{k-1}, i.e. the skinny product (m x k) (k x N^2).
+// The pass is HBM-bound (about 2.9 flop per byte in float64), so each thread
+// streams 16-byte vectors of one row of every T_i once and keeps up to 24
+// block accumulators in registers; T_0 = I adds coef[l][0] on the diagonal.
+// Full padded rows are processed: the zero padding of T_i yields zero
+// padding in R_l, so no column predicate is needed.
+//
+// Gram: G[l][i] = <L_l, T_i>_F (= tr(L_l T_i) for symmetric matrices), the
+// (nl x N^2)(N^2 x nt) contraction behind the trace moments.  It runs on the
+// float64 MFMA units with the matrices' elements as the K dimension; float
+// matrices are widened to float64 first so the moments keep float64 sums.
+// Per-workgroup partials are folded in a fixed order (deterministic).
+#include "internal.h"
+
+namespace chebdm {
+
+namespace {
+
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Vec16;
+template <> struct Vec16<double> { using V = f64x2; static constexpr int W = 2; };
+template <> struct Vec16<float> { using V = f32x4; static constexpr int W = 4; };
+
+constexpr int kCombineThreads = 256;
+
+template <typename T, int MB>
+__global__ void __launch_bounds__(kCombineThreads)
+k_combine(const T* __restrict__ tbase, int64_t stride, int k, int l0, int lcount,
+          const double* __restrict__ coef, T* __restrict__ rbase, int64_t n, int64_t ld) {
+    using V = typename Vec16<T>::V;
+    constexpr int W = Vec16<T>::W;
+    const int64_t row = blockIdx.y;
+    const int64_t col = ((int64_t)blockIdx.x * kCombineThreads + threadIdx.x) * W;
+    if (col >= ld) return;
+    const int64_t off = row * ld + col;
+
+    double acc[MB][W];
+    // T_0 = I: coef[l][0] on the diagonal
+#pragma unroll
+    for (int l = 0; l < MB; ++l) {
+        const double c0 = (l < lcount) ? coef[(int64_t)(l0 + l) * k] : 0.0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) acc[l][w] = (col + w == row) ? c0 : 0.0;
+    }
+    for (int i = 1; i < k; ++i) {
+        const V t = *reinterpret_cast<const V*>(tbase + (int64_t)(i - 1) * stride + off);
+#pragma unroll
+        for (int l = 0; l < MB; ++l) {
+            const double c = (l < lcount) ? coef[(int64_t)(l0 + l) * k + i] : 0.0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) acc[l][w] += c * (double)t[w];
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < MB; ++l) {
+        if (l < lcount) {
+            V o;
+#pragma unroll
+            for (int w = 0; w < W; ++w) o[w] = (T)acc[l][w];
+            *reinterpret_cast<V*>(rbase + (int64_t)(l0 + l) * stride + off) = o;
+        }
+    }
+}
+
+template <typename T>
+struct PtrList {
+    const T* p[kMaxBlocks];
+};
+
+constexpr int kGramThreads = 256;
+constexpr int kGramMax = 48;   // rows / columns of G handled (3 MFMA blocks of 16)
+
+__device__ __forceinline__ f64x2 load2(const double* p) { return *reinterpret_cast<const f64x2*>(p); }
+__device__ __forceinline__ f64x2 load2(const float* p) {
+    const f32x2 v = *reinterpret_cast<const f32x2*>(p);
+    return f64x2{(double)v[0], (double)v[1]};
+}
+
+template <typename T, int FM, int FN>
+__global__ void __launch_bounds__(kGramThreads)
+k_gram_partial(const PtrList<T> lm, int nl, const PtrList<T> tm, int nt, int64_t nchunk,
+               double* __restrict__ partial) {
+    constexpr int CH = 8;   // elements per chunk: 4 lane groups x 2
+    __shared__ double red[FM * 16][FN * 16 + 1];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lq = lane >> 4;
+    const int64_t gw = (int64_t)blockIdx.x * (kGramThreads / 64) + wave;
+    const int64_t nw = (int64_t)gridDim.x * (kGramThreads / 64);
+    const int64_t c_begin = nchunk * gw / nw, c_end = nchunk * (gw + 1) / nw;
+
+    const T* pa[FM];
+    const T* pb[FN];
+#pragma unroll
+    for (int f = 0; f < FM; ++f) {
+        const int li = f * 16 + lr;
+        pa[f] = lm.p[li < nl ? li : 0] + lq * 2;
+    }
+#pragma unroll
+    for (int g = 0; g < FN; ++g) {
+        const int ti = g * 16 + lr;
+        pb[g] = tm.p[ti < nt ? ti : 0] + lq * 2;
+    }
+    f64x4 acc[FM][FN];
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int g = 0; g < FN; ++g) acc[f][g] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+    for (int64_t c = c_begin; c < c_end; ++c) {
+        const int64_t e = c * CH;
+        f64x2 a[FM], b[FN];
+#pragma unroll
+        for (int f = 0; f < FM; ++f) a[f] = load2(pa[f] + e);
+#pragma unroll
+        for (int g = 0; g < FN; ++g) b[g] = load2(pb[g] + e);
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int f = 0; f < FM; ++f)
+#pragma unroll
+                for (int g = 0; g < FN; ++g)
+                    acc[f][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[f][s], b[g][s], acc[f][g], 0, 0, 0);
+    }
+    // v_mfma_f64_16x16x4f64 leaves G row 16f + lq + 4r, column 16g + lr in lane (lr, lq),
+    // register r; waves add in a fixed order
+    for (int w = 0; w < kGramThreads / 64; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int f = 0; f < FM; ++f)
+#pragma unroll
+                for (int g = 0; g < FN; ++g)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        double& slot = red[f * 16 + lq + 4 * r][g * 16 + lr];
+                        slot = (w == 0) ? acc[f][g][r] : slot + acc[f][g][r];
+                    }
+        }
+        __syncthreads();
+    }
+    constexpr int NE = FM * 16 * FN * 16;
+    for (int idx = threadIdx.x; idx < NE; idx += kGramThreads) {
+        const int rr = idx / (FN * 16), cc = idx % (FN * 16);
+        partial[(int64_t)blockIdx.x * kGramMax * kGramMax + rr * kGramMax + cc] = red[rr][cc];
+    }
+}
+
+__global__ void k_gram_final(const double* __restrict__ partial, int nblocks, int nl, int nt,
+                             double* __restrict__ G) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nl * nt) return;
+    const int l = idx / nt, i = idx % nt;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * kGramMax * kGramMax + l * kGramMax + i];
+    G[idx] = s;
+}
+
+template <typename T, int FM, int FN>
+void launch_gram_fixed(const PtrList<T>& L, int nl, const PtrList<T>& Tm, int nt, int64_t nchunk,
+                       int nblocks, double* partial, hipStream_t st) {
+    hipLaunchKernelGGL((k_gram_partial<T, FM, FN>), dim3(nblocks), dim3(kGramThreads), 0, st, L, nl, Tm,
+                       nt, nchunk, partial);
+}
+
+template <typename T, int FM>
+void launch_gram_fm(int fn, const PtrList<T>& L, int nl, const PtrList<T>& Tm, int nt, int64_t nchunk,
+                    int nblocks, double* partial, hipStream_t st) {
+    if (fn == 1) launch_gram_fixed<T, FM, 1>(L, nl, Tm, nt, nchunk, nblocks, partial, st);
+    else if (fn == 2) launch_gram_fixed<T, FM, 2>(L, nl, Tm, nt, nchunk, nblocks, partial, st);
+    else launch_gram_fixed<T, FM, 3>(L, nl, Tm, nt, nchunk, nblocks, partial, st);
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_combine(const T* tbase, int64_t stride, int k, int m, const double* coef, T* rbase,
+                          int64_t n, int64_t ld, hipStream_t st) {
+    constexpr int W = Vec16<T>::W;
+    if (ld % (W * 2) != 0) return hipErrorInvalidValue;
+    const int64_t per_block = (int64_t)kCombineThreads * W;
+    dim3 grid((unsigned)((ld + per_block - 1) / per_block), (unsigned)n);
+    for (int l0 = 0; l0 < m; l0 += 24) {
+        const int cnt = (m - l0) < 24 ? (m - l0) : 24;
+        if (cnt <= 8)
+            hipLaunchKernelGGL((k_combine<T, 8>), grid, dim3(kCombineThreads), 0, st, tbase, stride, k, l0,
+                               cnt, coef, rbase, n, ld);
+        else if (cnt <= 16)
+            hipLaunchKernelGGL((k_combine<T, 16>), grid, dim3(kCombineThreads), 0, st, tbase, stride, k, l0,
+                               cnt, coef, rbase, n, ld);
+        else
+            hipLaunchKernelGGL((k_combine<T, 24>), grid, dim3(kCombineThreads), 0, st, tbase, stride, k, l0,
+                               cnt, coef, rbase, n, ld);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gram(const T* const* lmats, int nl, const T* const* tmats, int nt, int64_t nelem,
+                       double* partial, int64_t partial_cap, double* G, hipStream_t st) {
+    if (nl <= 0 || nt <= 0) return hipSuccess;
+    if (nl > kGramMax || nt > kGramMax || nelem % 8 != 0) return hipErrorInvalidValue;
+    PtrList<T> L{}, Tm{};
+    for (int i = 0; i < nl; ++i) L.p[i] = lmats[i];
+    for (int i = 0; i < nt; ++i) Tm.p[i] = tmats[i];
+    const int64_t nchunk = nelem / 8;
+    int64_t nblocks = 1024;
+    if (nblocks * 4 > nchunk) nblocks = (nchunk + 3) / 4;
+    if (nblocks < 1) nblocks = 1;
+    if (nblocks * kGramMax * kGramMax > partial_cap) nblocks = partial_cap / (kGramMax * kGramMax);
+    if (nblocks < 1) return hipErrorInvalidValue;
+    const int fm = (nl + 15) / 16, fn = (nt + 15) / 16;
+    if (fm == 1) launch_gram_fm<T, 1>(fn, L, nl, Tm, nt, nchunk, (int)nblocks, partial, st);
+    else if (fm == 2) launch_gram_fm<T, 2>(fn, L, nl, Tm, nt, nchunk, (int)nblocks, partial, st);
+    else launch_gram_fm<T, 3>(fn, L, nl, Tm, nt, nchunk, (int)nblocks, partial, st);
+    hipLaunchKernelGGL(k_gram_final, dim3((unsigned)((nl * nt + 255) / 256)), dim3(256), 0, st,
+                       (const double*)partial, (int)nblocks, nl, nt, G);
+    return hipGetLastError();
+}
+
+template hipError_t launch_combine<double>(const double*, int64_t, int, int, const double*, double*, int64_t,
+                                           int64_t, hipStream_t);
+template hipError_t launch_combine<float>(const float*, int64_t, int, int, const double*, float*, int64_t,
+                                          int64_t, hipStream_t);
+template hipError_t launch_gram<double>(const double* const*, int, const double* const*, int, int64_t, double*,
+                                        int64_t, double*, hipStream_t);
+template hipError_t launch_gram<float>(const float* const*, int, const float* const*, int, int64_t, double*,
+                                       int64_t, double*, hipStream_t);
+
+}  // namespace chebdm

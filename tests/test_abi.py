@@ -1,0 +1,84 @@
+"""C-ABI contract on the CPU: the library loads, exports every declared entry
+point, and its host-side argument checks and planning work without a GPU
+(no compute call is made here)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+import paper_2306_12616_amd as chebdm
+from paper_2306_12616_amd import _binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "chebdm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(chebdm_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(chebdm.LIB_PATH):
+        import __graft_entry__
+
+        __graft_entry__.build()
+    return chebdm.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    declared = _declared_symbols()
+    assert declared, "header parse found no entry points"
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(_binding.EXPORTED)
+
+
+def test_abi_version_and_defaults(lib):
+    assert lib.chebdm_abi_version() == 1
+    o = chebdm.make_opts()
+    assert (o.prec, o.giant_form, o.k_override, o.n_quad, o.max_iter, o.tol) == (0, 0, 0, 0, 200, 1e-10)
+
+
+def _dbl():
+    return ctypes.c_double()
+
+
+def test_null_handle_is_rejected(lib):
+    lo, hi = _dbl(), _dbl()
+    assert lib.chebdm_bounds(None, None, 4, 4, ctypes.byref(lo), ctypes.byref(hi)) == _binding.ERR_ARG
+    c = (ctypes.c_double * 8)()
+    assert lib.chebdm_coeffs(None, 1.0, 0.0, -1.0, 1.0, 7, 0, c) == _binding.ERR_ARG
+    assert lib.chebdm_density(None, None, 4, 4, 1.0, 0.0, 4, None, math.nan, math.nan, None, 4, None) == _binding.ERR_ARG
+    mu = _dbl()
+    assert lib.chebdm_mu_search(None, None, 4, 4, 1.0, 2.0, 4, None, math.nan, math.nan, ctypes.byref(mu), None, 4,
+                                None) == _binding.ERR_ARG
+    assert lib.chebdm_moments(None, None, 4, 4, 4, None, math.nan, math.nan, c) == _binding.ERR_ARG
+    assert b"NULL" in lib.chebdm_last_error() or b"handle" in lib.chebdm_last_error()
+    assert lib.chebdm_destroy(None) == 0
+    assert lib.chebdm_set_stream(None, None) == _binding.ERR_ARG
+
+
+@pytest.mark.parametrize("order,k,m", [(128, 12, 11), (512, 23, 23), (256, 17, 16), (2048, 46, 45), (0, 1, 1),
+                                       (24, 5, 5), (1, 2, 1)])
+def test_block_split_matches_plan(lib, order, k, m):
+    # the size query of chebdm_block_coeffs is host-only planning
+    kk, mm = ctypes.c_int32(), ctypes.c_int32()
+    dummy = ctypes.c_void_p(1)
+    rc = lib.chebdm_block_coeffs(dummy, None, order, 0, 0, ctypes.byref(kk), ctypes.byref(mm), None)
+    assert rc == 0 and (kk.value, mm.value) == (k, m)
+
+
+def test_block_split_override_and_limits(lib):
+    kk, mm = ctypes.c_int32(), ctypes.c_int32()
+    dummy = ctypes.c_void_p(1)
+    assert lib.chebdm_block_coeffs(dummy, None, 100, 0, 7, ctypes.byref(kk), ctypes.byref(mm), None) == 0
+    assert (kk.value, mm.value) == (7, 15)
+    # more than 48 blocks is refused
+    assert lib.chebdm_block_coeffs(dummy, None, 2048, 0, 4, ctypes.byref(kk), ctypes.byref(mm), None) == _binding.ERR_ARG
+    assert lib.chebdm_block_coeffs(dummy, None, 48 * 48, 0, 0, ctypes.byref(kk), ctypes.byref(mm), None) == _binding.ERR_ARG
+    assert lib.chebdm_block_coeffs(dummy, None, -1, 0, 0, ctypes.byref(kk), ctypes.byref(mm), None) == _binding.ERR_ARG
+    assert lib.chebdm_block_coeffs(dummy, None, 10, 5, 0, ctypes.byref(kk), ctypes.byref(mm), None) == _binding.ERR_ARG

@@ -1,0 +1,126 @@
+"""GPU parity of the reduced-precision products and of the full-size workloads.
+
+Reduced precision (float32 MFMA, split-bf16 "bf16x3"): the products run in
+lower precision while bounds, coefficients, traces and the bisection stay
+float64.  The error is measured against the float64 oracle at the *same*
+chemical potential, so it isolates the products; the target is a max-abs
+error of 1e-5 for both forms.
+
+Full size: the benchmark shapes (N = 1000/2000/4000, order 512; N = 5000,
+order 2048) are compared on sampled rows, which the oracle computes one by
+one from the generator's eigenpairs: D[rows] = Q[rows] diag(p(lam~)) Q^T.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import chebyshev as ch
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2306_12616_amd as chebdm
+
+    chebdm.load_library()
+    return chebdm
+
+
+@pytest.fixture(scope="module")
+def handle(cd):
+    h = cd.Handle(0)
+    yield h
+    h.close()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _oracle_rows(q, lam, rows, order, beta, mu, emin, emax, M):
+    cen, a = ch.scaling(emin, emax)
+    c = ch.chebyshev_coeffs(order, beta * a, (mu - cen) / a, M)
+    p = ch.cheb_eval(c, (lam - cen) / a)
+    return (q[rows] * p) @ q.T
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("n,law,order,beta", [(256, "uniform", 128, 50.0), (520, "gaussmix6", 255, 60.0),
+                                              (700, "highdos", 512, 100.0)])
+def test_reduced_precision_density(cd, handle, prec, n, law, order, beta):
+    _say(f"density {prec} n={n} order={order}")
+    h, q, lam = synth.hamiltonian(n, law, seed=3000 + n)
+    mu = 0.05
+    D, info = cd.chebdm_density(handle, _dev(h), beta, mu, order, cd.make_opts(prec))
+    torch.cuda.synchronize()
+    rows = np.arange(n)
+    ref = _oracle_rows(q, lam, rows, order, beta, mu, info["emin"], info["emax"], info["n_quad"])
+    err = float(np.max(np.abs(D.cpu().numpy() - ref)))
+    _say(f"  max|D_{prec} - D_oracle| = {err:.3e}")
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_reduced_precision_mu_search(cd, handle, prec):
+    n, order, beta, ne = 300, 200, 80.0, 150.0
+    _say(f"mu_search {prec}")
+    h, q, lam = synth.hamiltonian(n, "gaussmix6", seed=77)
+    mu, D, info = cd.chebdm_mu_search(handle, _dev(h), beta, ne, order, cd.make_opts(prec))
+    torch.cuda.synchronize()
+    emin, emax = info["emin"], info["emax"]
+    cen, a = ch.scaling(emin, emax)
+    c = ch.chebyshev_coeffs(order, beta * a, (mu - cen) / a, info["n_quad"])
+    tau = ch.moments_from_eigs(lam, emin, emax, order)
+    t_err = abs(ch.trace_of_series(c, tau) - ne)
+    _say(f"  |t_oracle(mu_{prec}) - Ne| = {t_err:.3e}  iters={info['iters']}")
+    # moments from reduced-precision matrices: electron count within 1e-5 * N
+    assert t_err <= 1e-5 * n
+    assert abs(info["trace"] - ne) <= 1e-5 * n
+
+
+FULL = [
+    # n, law, order, beta, prec, seed
+    (1000, "gaussmix6", 512, 100.0, "fp64", 2000),
+    (2000, "gaussmix6", 512, 100.0, "fp64", 2001),
+    (4000, "gaussmix6", 512, 100.0, "fp64", 2002),
+    (1000, "gaussmix6", 512, 100.0, "fp32", 2000),
+    (4000, "gaussmix6", 512, 100.0, "fp32", 2002),
+    (5000, "highdos", 2048, 400.0, "bf16x3", 4000),
+    (5000, "highdos", 2048, 400.0, "fp32", 4000),
+]
+
+
+@pytest.mark.parametrize("case", FULL, ids=[f"n{c[0]}-L{c[2]}-{c[4]}" for c in FULL])
+def test_full_size_mu_search_sampled_rows(cd, handle, case):
+    n, law, order, beta, prec, seed = case
+    _say(f"full-size mu_search {case}")
+    h, q, lam = synth.hamiltonian(n, law, seed=seed)
+    mu, D, info = cd.chebdm_mu_search(handle, _dev(h), beta, n / 2, order, cd.make_opts(prec))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(seed)
+    rows = np.sort(rng.choice(n, size=6, replace=False))
+    rows[0] = 0
+    rows[-1] = n - 1
+    ref = _oracle_rows(q, lam, rows, order, beta, mu, info["emin"], info["emax"], info["n_quad"])
+    err = float(np.max(np.abs(D[rows].cpu().numpy() - ref)))
+    emin, emax = info["emin"], info["emax"]
+    cen, a = ch.scaling(emin, emax)
+    c = ch.chebyshev_coeffs(order, beta * a, (mu - cen) / a, info["n_quad"])
+    t_err = abs(ch.trace_of_series(c, ch.moments_from_eigs(lam, emin, emax, order)) - n / 2)
+    _say(f"  status={info['status']} iters={info['iters']} max|D-D_oracle|(rows)={err:.3e} "
+         f"|t_oracle(mu)-Ne|={t_err:.3e} |trD-Ne|={abs(info['trace'] - n / 2):.3e}")
+    if prec == "fp64":
+        assert info["status"] == 0 and err <= 1e-10 and t_err <= 1e-8
+    else:
+        assert err <= 1e-5 and t_err <= 1e-5 * n

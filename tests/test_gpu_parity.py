@@ -1,0 +1,291 @@
+"""GPU parity: the HIP path, called through the C ABI, against the CPU oracle.
+
+Tolerances (max-abs, float64 path): 1e-10 on D as the target states; bounds
+and coefficients are single reductions, compared at 1e-13 relative.  The
+chemical potential is compared through the oracle's own trace at the GPU's
+mu (several mu are correct to within the tolerance).  Same seeded inputs on
+both sides (``synth``); the oracle uses the generator's eigenpairs.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import chebyshev as ch
+from oracle import decomposition as dec
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2306_12616_amd as chebdm
+
+    chebdm.load_library()
+    return chebdm
+
+
+@pytest.fixture(scope="module")
+def handle(cd):
+    h = cd.Handle(0)
+    yield h
+    h.close()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _oracle_density(q, lam, order, beta, mu, emin, emax, M):
+    cen, a = ch.scaling(emin, emax)
+    c = ch.chebyshev_coeffs(order, beta * a, (mu - cen) / a, M)
+    return ch.density_from_eigs(q, lam, c, emin, emax), c
+
+
+# ------------------------------------------------------------------ bounds
+
+@pytest.mark.parametrize("n,law", [(1, "uniform"), (7, "uniform"), (256, "uniform"), (333, "gaussmix6"),
+                                   (1000, "highdos")])
+def test_bounds_match_oracle(cd, handle, n, law):
+    _say(f"bounds n={n} law={law}")
+    h, q, lam = synth.hamiltonian(n, law, seed=17 + n)
+    lo, hi = cd.chebdm_bounds(handle, _dev(h))
+    rlo, rhi = ch.gershgorin_bounds(h)
+    scale = max(abs(rlo), abs(rhi))
+    assert abs(lo - rlo) <= 1e-13 * scale and abs(hi - rhi) <= 1e-13 * scale
+
+
+def test_bounds_with_leading_dimension(cd, handle):
+    n, ld = 150, 211
+    h, _, _ = synth.hamiltonian(n, "uniform", seed=3)
+    big = torch.zeros((n, ld), dtype=torch.float64, device="cuda:0")
+    big[:, :n] = _dev(h)
+    view = big[:, :n]
+    lo, hi = cd.chebdm_bounds(handle, view)
+    rlo, rhi = ch.gershgorin_bounds(h)
+    assert abs(lo - rlo) < 1e-13 * abs(rlo) and abs(hi - rhi) < 1e-13 * abs(rhi)
+
+
+def test_bounds_nonfinite_error(cd, handle):
+    h, _, _ = synth.hamiltonian(64, "uniform", seed=1)
+    h[3, 5] = np.nan
+    with pytest.raises(cd.ChebdmError) as e:
+        cd.chebdm_bounds(handle, _dev(h))
+    assert e.value.code == -4
+
+
+# ------------------------------------------------------------ coefficients
+
+@pytest.mark.parametrize("order,beta,mu,emin,emax,M", [(128, 50.0, 0.1, -8.0, 8.0, 0), (512, 100.0, -0.3, -13.5, 13.6, 0),
+                                                       (40, 3.0, 0.0, -1.0, 1.0, 41), (2048, 400.0, 0.02, -25.0, 25.0, 0)])
+def test_coeffs_match_oracle(cd, handle, order, beta, mu, emin, emax, M):
+    _say(f"coeffs order={order} beta={beta}")
+    c = cd.chebdm_coeffs(handle, beta, mu, emin, emax, order, M)
+    cen, a = ch.scaling(emin, emax)
+    Mo = M or ch.quadrature_size(order, beta * a)
+    ref = ch.chebyshev_coeffs(order, beta * a, (mu - cen) / a, Mo)
+    assert np.max(np.abs(c - ref)) <= 1e-13
+
+
+@pytest.mark.parametrize("order,form,kov", [(128, "composition", 0), (128, "power", 0), (512, "composition", 0),
+                                            (24, "power", 0), (99, "power", 7), (2048, "composition", 0),
+                                            (0, "composition", 0), (5, "power", 1)])
+def test_block_coeffs_match_oracle(cd, handle, order, form, kov):
+    rng = np.random.default_rng(order + kov)
+    c = rng.uniform(-1, 1, order + 1) * np.exp(-0.01 * np.arange(order + 1))
+    k, m, coef = cd.chebdm_block_coeffs(handle, c, order, form, kov)
+    assert (k, m) == dec.split_order(order, kov or None)
+    if form == "composition":
+        ref = dec.composition_form_e(c, k, m)
+    else:
+        ref = dec.power_form_d(c, k, m).T     # d_{i,l} stored as [l][i]
+    scale = max(1.0, np.max(np.abs(ref)))
+    assert np.max(np.abs(coef - ref)) <= 1e-12 * scale
+
+
+# --------------------------------------------------------------- densities
+
+CASES = [
+    # n, law, order, beta, mu, form, k_override
+    (256, "uniform", 128, 50.0, 0.05, "composition", 0),
+    (256, "uniform", 128, 50.0, 0.05, "power", 0),
+    (300, "gaussmix6", 200, 80.0, -0.1, "composition", 0),
+    (130, "highdos", 63, 30.0, 0.0, "composition", 5),
+    (1, "uniform", 10, 20.0, 0.1, "composition", 0),
+    (70, "uniform", 0, 20.0, 0.1, "composition", 0),
+    (70, "uniform", 3, 20.0, 0.1, "power", 0),
+    (64, "uniform", 30, 20.0, 0.1, "composition", 1),
+    (520, "uniform", 255, 40.0, 0.2, "composition", 0),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"n{c[0]}-L{c[2]}-{c[5]}-k{c[6]}" for c in CASES])
+def test_density_fp64_matches_oracle(cd, handle, case):
+    n, law, order, beta, mu, form, kov = case
+    _say(f"density fp64 {case}")
+    h, q, lam = synth.hamiltonian(n, law, seed=1000 + n + order)
+    opts = cd.make_opts("fp64", form, k_override=kov)
+    D, info = cd.chebdm_density(handle, _dev(h), beta, mu, order, opts)
+    torch.cuda.synchronize()
+    emin, emax = info["emin"], info["emax"]
+    if n == 1:
+        # a 1 x 1 H has e_a = e_b: the library returns f(H_00) exactly
+        assert emin == emax == h[0, 0] and info["n_quad"] == 0
+        assert abs(D.item() - 1.0 / (1.0 + math.exp(beta * (h[0, 0] - mu)))) <= 1e-15
+        return
+    cen, a = ch.scaling(emin, emax)
+    M = ch.quadrature_size(order, beta * a)
+    assert info["n_quad"] == M
+    ref, c = _oracle_density(q, lam, order, beta, mu, emin, emax, M)
+    err = np.max(np.abs(D.cpu().numpy() - ref))
+    _say(f"  max|D - D_oracle| = {err:.3e}  k={info['k']} m={info['m']} gemms={info['n_gemm']}")
+    assert err <= 1e-10
+    assert abs(info["trace"] - np.trace(ref)) <= 1e-9
+    k, m = info["k"], info["m"]
+    assert info["n_gemm"] == max(k - 1, 0) + (m - 1)
+
+
+def test_density_writes_only_n_by_n(cd, handle):
+    n, ldd = 90, 101
+    h, q, lam = synth.hamiltonian(n, "uniform", seed=5)
+    out = torch.full((n, ldd), 7.0, dtype=torch.float64, device="cuda:0")
+    D, info = cd.chebdm_density(handle, _dev(h), 20.0, 0.0, 50, None, D=out[:, :n])
+    torch.cuda.synchronize()
+    assert torch.all(out[:, n:] == 7.0)
+    ref, _ = _oracle_density(q, lam, 50, 20.0, 0.0, info["emin"], info["emax"], info["n_quad"])
+    assert np.max(np.abs(D.cpu().numpy() - ref)) <= 1e-10
+
+
+def test_density_given_bounds(cd, handle):
+    n, order, beta, mu = 200, 100, 10.0, 0.1
+    h, q, lam = synth.hamiltonian(n, "uniform", seed=8)
+    emin, emax = float(lam.min()) - 0.01, float(lam.max()) + 0.01
+    D, info = cd.chebdm_density(handle, _dev(h), beta, mu, order, None, emin, emax)
+    torch.cuda.synchronize()
+    assert (info["emin"], info["emax"]) == (emin, emax)
+    ref, _ = _oracle_density(q, lam, order, beta, mu, emin, emax, info["n_quad"])
+    assert np.max(np.abs(D.cpu().numpy() - ref)) <= 1e-10
+
+
+def test_density_scalar_hamiltonian(cd, handle):
+    n, c0, beta, mu = 50, 0.3, 7.0, 0.1
+    h = c0 * np.eye(n)
+    D, info = cd.chebdm_density(handle, _dev(h), beta, mu, 64)
+    torch.cuda.synchronize()
+    occ = 1.0 / (1.0 + math.exp(beta * (c0 - mu)))
+    assert np.max(np.abs(D.cpu().numpy() - occ * np.eye(n))) <= 1e-15
+
+
+def test_power_form_refuses_reduced_precision(cd, handle):
+    h, _, _ = synth.hamiltonian(32, "uniform", seed=2)
+    with pytest.raises(cd.ChebdmError) as e:
+        cd.chebdm_density(handle, _dev(h), 10.0, 0.0, 20, cd.make_opts("fp32", "power"))
+    assert e.value.code == -6
+
+
+# ------------------------------------------------------------------ moments
+
+@pytest.mark.parametrize("n,order,kov", [(256, 128, 0), (300, 257, 0), (100, 50, 4), (64, 5, 0)])
+def test_moments_match_oracle(cd, handle, n, order, kov):
+    _say(f"moments n={n} order={order}")
+    h, q, lam = synth.hamiltonian(n, "gaussmix6", seed=n + order)
+    tau = cd.chebdm_moments(handle, _dev(h), order, cd.make_opts(k_override=kov))
+    lo, hi = ch.gershgorin_bounds(h)
+    lo_g, hi_g = cd.chebdm_bounds(handle, _dev(h))
+    ref = ch.moments_from_eigs(lam, lo_g, hi_g, order)
+    assert tau[0] == n
+    err = np.max(np.abs(tau - ref))
+    _say(f"  max|tau - tau_oracle| = {err:.3e}")
+    assert err <= 1e-11 * n
+
+
+# ------------------------------------------------------------------ mu search
+
+MU_CASES = [
+    # n, law, order, beta, n_elec, form
+    (256, "uniform", 128, 50.0, 128.0, "composition"),     # the N = 256 reference workload
+    (256, "uniform", 128, 50.0, 128.0, "power"),
+    (300, "gaussmix6", 200, 80.0, 101.5, "composition"),
+    (520, "highdos", 255, 60.0, 260.0, "composition"),
+]
+
+
+@pytest.mark.parametrize("case", MU_CASES, ids=[f"n{c[0]}-L{c[2]}-{c[5]}" for c in MU_CASES])
+def test_mu_search_matches_oracle(cd, handle, case):
+    n, law, order, beta, ne, form = case
+    _say(f"mu_search {case}")
+    h, q, lam = synth.hamiltonian(n, law, seed=2000 + n)
+    mu, D, info = cd.chebdm_mu_search(handle, _dev(h), beta, ne, order, cd.make_opts("fp64", form))
+    torch.cuda.synchronize()
+    assert info["status"] == 0, info
+    emin, emax = info["emin"], info["emax"]
+    cen, a = ch.scaling(emin, emax)
+    M = ch.quadrature_size(order, beta * a)
+    ref, c = _oracle_density(q, lam, order, beta, mu, emin, emax, M)
+    tau = ch.moments_from_eigs(lam, emin, emax, order)
+    t_or = ch.trace_of_series(c, tau)
+    err = np.max(np.abs(D.cpu().numpy() - ref))
+    _say(f"  mu={mu:.15f} iters={info['iters']} |t_gpu-Ne|={info['trace_err']:.2e} "
+         f"|t_oracle(mu)-Ne|={abs(t_or - ne):.2e} |trD-Ne|={abs(info['trace'] - ne):.2e} maxerr={err:.2e}")
+    assert info["trace_err"] < 1e-10
+    assert abs(t_or - ne) <= 1e-9
+    assert abs(info["trace"] - ne) <= 1e-9
+    assert err <= 1e-10
+    # the oracle's own bisection lands on the same mu up to the flat-trace resolution
+    mu_s, _, _, st = ch.bisect_mu(tau, order, beta * a, ne, 1e-10, M=M)
+    slope = (ch.trace_of_series(ch.chebyshev_coeffs(order, beta * a, mu_s + 1e-7, M), tau)
+             - ch.trace_of_series(ch.chebyshev_coeffs(order, beta * a, mu_s - 1e-7, M), tau)) / 2e-7
+    assert abs((mu - cen) / a - mu_s) <= 4e-9 / slope + 1e-15
+
+
+def test_mu_search_symmetric_spectrum_first_sweep(cd, handle):
+    n = 128
+    lam = synth.symmetric_pairs_spectrum(n, seed=4)
+    h, q, lam = synth.hamiltonian(n, lam=lam, seed=4)
+    mu, D, info = cd.chebdm_mu_search(handle, _dev(h), 30.0, n / 2, 64, None, -1.5, 1.5)
+    assert info["iters"] == 1 and mu == 0.0
+
+
+def test_mu_search_without_density(cd, handle):
+    h, q, lam = synth.hamiltonian(200, "uniform", seed=6)
+    mu1, D, info1 = cd.chebdm_mu_search(handle, _dev(h), 40.0, 77.0, 100, None, want_density=False)
+    mu2, D2, info2 = cd.chebdm_mu_search(handle, _dev(h), 40.0, 77.0, 100, None)
+    assert D is None and mu1 == mu2 and info1["iters"] == info2["iters"]
+    assert info1["n_gemm"] < info2["n_gemm"]
+
+
+def test_mu_search_errors_and_warnings(cd, handle):
+    h, q, lam = synth.hamiltonian(64, "uniform", seed=9)
+    H = _dev(h)
+    with pytest.raises(cd.ChebdmError) as e:
+        cd.chebdm_mu_search(handle, H, 10.0, 64.0, 32)
+    assert e.value.code == -1
+    with pytest.raises(cd.ChebdmError) as e:
+        cd.chebdm_mu_search(handle, H, 10.0, 0.0, 32)
+    assert e.value.code == -1
+    # max_iter = 1 cannot reach 1e-10: the result is flagged, not an error
+    mu, D, info = cd.chebdm_mu_search(handle, H, 10.0, 20.0, 32, cd.make_opts(max_iter=1))
+    assert info["status"] == 1 and info["iters"] == 1
+    # the bracket check fires when the requested count is outside (t(-1), t(1))
+    with pytest.raises(cd.ChebdmError) as e:
+        cd.chebdm_mu_search(handle, H, 10.0, 63.99, 4, None, -100.0, 100.0)
+    assert e.value.code == -5
+
+
+def test_mu_search_scalar_hamiltonian(cd, handle):
+    n, c0, beta, ne = 40, -0.2, 5.0, 10.0
+    mu, D, info = cd.chebdm_mu_search(handle, _dev(c0 * np.eye(n)), beta, ne, 16)
+    occ = ne / n
+    assert abs(1.0 / (1.0 + math.exp(beta * (c0 - mu))) - occ) < 1e-15
+    assert np.max(np.abs(D.cpu().numpy() - occ * np.eye(n))) <= 1e-15
