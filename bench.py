@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Throughput of the dense Chebyshev density-matrix path on one MI355X.
+
+One step = one pass of the whole hot path on a resident Hamiltonian:
+Gershgorin bounds -> H~ -> baby steps -> ladder + Gram moments -> mu
+bisection -> coefficients -> block sums -> giant steps -> D and tr D
+(``chebdm_mu_search`` with a density output).  Default workload: N = 4000,
+order 512, beta = 100, N_e = N/2, H = Q diag(lam) Q^T with lam from a
+six-Gaussian mixture (synthetic stand-in for the paper's model Hamiltonians).
+
+Prints one JSON line (stdout); progress goes to stderr.  ``roofline`` is the
+matrix-product kernel's algorithmic rate from HIP events recorded by the
+library on its own stream over the timed steps; ``cpu_baseline`` times the
+CPU oracle (LAPACK eigh route) on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "density matrices/s and % MFMA peak at N=1000/4000 vs plain FP64 path"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}   # dense MFMA peaks of MI355X
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_h(n, law, seed):
+    import synth
+
+    h, q, lam = synth.hamiltonian(n, law, seed=seed)
+    return h
+
+
+def run_steps(cd, handle, H, beta, n_elec, order, opts, steps, warmup, want_density=True):
+    import torch
+
+    D = torch.empty_like(H) if want_density else None
+    for _ in range(warmup):
+        cd.chebdm_mu_search(handle, H, beta, n_elec, order, opts, want_density=want_density, D=D)
+    torch.cuda.synchronize()
+    cd.chebdm_profile_enable(handle, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = None
+    for _ in range(steps):
+        mu, _, info = cd.chebdm_mu_search(handle, H, beta, n_elec, order, opts, want_density=want_density, D=D)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = cd.chebdm_profile_read(handle)
+    cd.chebdm_profile_enable(handle, False)
+    return dt, prof, info
+
+
+def roofline_of(prof, prec):
+    """Matrix-product kernel: algorithmic flops / summed launch time vs the MFMA peak."""
+    if prof["gemm_ms"] <= 0:
+        return None
+    flop = prof["gemm_flop"] * (3.0 if prec == "bf16x3" else 1.0)   # bf16x3 runs three bf16 products
+    achieved = flop / (prof["gemm_ms"] * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[prec]
+    return {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None,
+            "kernel": "k_gemm (symmetric product, fused epilogue)",
+            "launches": prof["gemm_launches"], "products": prof["gemm_products"],
+            "avg_launch_ms": round(prof["gemm_ms"] / max(1, prof["gemm_launches"]), 4)}
+
+
+def hbm_of(ms, nbytes):
+    if ms <= 0:
+        return None
+    return round(nbytes / (ms * 1e-3) / 1e9, 1)
+
+
+def cpu_baseline(h_np, beta, n_elec, order, budget_s=10.0, max_reps=3):
+    from oracle import chebyshev as ch
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    reps, t0 = 0, time.perf_counter()
+    while reps < max_reps:
+        ch.mu_search_density(h_np, beta, n_elec, order)
+        reps += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(reps / dt, 4), "unit": "density matrices/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{reps} full mu search + density at N={h_np.shape[0]}, order {order} "
+                      f"(oracle route: LAPACK eigh of H, moments, bisection, Q p(lam) Q^T), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=4000)
+    ap.add_argument("--order", type=int, default=512)
+    ap.add_argument("--beta", type=float, default=100.0)
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--no-breakdown", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the method has no multi-GPU path here "
+              f"(--gpus {args.gpus} requested)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2306_12616_amd as cd
+
+    if not torch.cuda.is_available():
+        print("no HIP device visible", file=sys.stderr)
+        sys.exit(1)
+    cd.load_library()
+    handle = cd.Handle(0)
+
+    n, order, beta = args.n, args.order, args.beta
+    n_elec = n / 2.0
+    log(f"generating H: n={n} law=gaussmix6 seed=2002")
+    h_np = make_h(n, "gaussmix6", 2002)
+    H = torch.from_numpy(h_np).to("cuda:0")
+    opts = cd.make_opts(args.prec)
+
+    log(f"timing {args.steps} steps (warmup {args.warmup}) of mu search + density, prec={args.prec}")
+    dt, prof, info = run_steps(cd, handle, H, beta, n_elec, order, opts, args.steps, args.warmup)
+    value = args.steps / dt
+    log(f"  {value:.3f} DM/s, {1e3 * dt / args.steps:.2f} ms/step, gemm {prof['gemm_ms'] / args.steps:.2f} ms/step")
+    roof = roofline_of(prof, args.prec)
+
+    result = {
+        "metric": METRIC, "value": round(value, 4), "unit": "density matrices/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3 (f32 accumulate)"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": f"mu search + density matrix, N={n}, order {order}, beta {beta:g}, "
+                               f"N_e=N/2, H=Q diag(lam) Q^T with lam from a 6-Gaussian mixture",
+                   "n": n, "order": order, "beta": beta, "n_elec": n_elec, "prec": args.prec,
+                   "k": info["k"], "m": info["m"], "products_per_step": info["n_gemm"],
+                   "n_quad": info["n_quad"], "bisection_sweeps": info["iters"]},
+        "roofline": roof,
+        "phases_ms_per_step": {"gemm": round(prof["gemm_ms"] / args.steps, 3),
+                               "combine": round(prof["combine_ms"] / args.steps, 3),
+                               "gram": round(prof["gram_ms"] / args.steps, 3),
+                               "other": round(1e3 * dt / args.steps - (prof["gemm_ms"] + prof["combine_ms"]
+                                                                       + prof["gram_ms"]) / args.steps, 3)},
+        "hbm_GBs": {"combine": hbm_of(prof["combine_ms"], prof["combine_bytes"]),
+                    "gram": hbm_of(prof["gram_ms"], prof["gram_bytes"]), "peak": PEAK_HBM_GBS},
+    }
+
+    if not args.no_breakdown:
+        rows = {}
+        cases = [(1000, "fp64"), (1000, "fp32"), (4000, "fp32"), (4000, "bf16x3"), (1000, "bf16x3")]
+        if args.prec != "fp64" or n != 4000:
+            cases.append((4000, "fp64"))
+        for nn, pr in cases:
+            log(f"breakdown n={nn} prec={pr}")
+            hh = H if nn == n else torch.from_numpy(make_h(nn, "gaussmix6", 2000 if nn == 1000 else 2002)).to("cuda:0")
+            steps = 20 if nn <= 1000 else 5
+            d2, p2, i2 = run_steps(cd, handle, hh, beta, nn / 2.0, order, cd.make_opts(pr), steps, 2)
+            r2 = roofline_of(p2, pr)
+            rows[f"n{nn}_{pr}"] = {"dm_per_s": round(steps / d2, 3), "ms_per_step": round(1e3 * d2 / steps, 3),
+                                   "gemm_frac_of_peak": r2["frac"] if r2 else None,
+                                   "gemm_tflops": r2["achieved"] if r2 else None}
+            # fixed-mu density only (no ladder / moments / bisection)
+        fp64_1000 = rows.get("n1000_fp64", {}).get("dm_per_s")
+        for key, row in rows.items():
+            base = fp64_1000 if key.startswith("n1000") else (value if args.prec == "fp64" and n == 4000 else
+                                                              rows.get("n4000_fp64", {}).get("dm_per_s"))
+            row["speedup_vs_fp64"] = round(row["dm_per_s"] / base, 3) if base else None
+        result["breakdown"] = rows
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on host cores")
+        result["cpu_baseline"] = cpu_baseline(h_np, beta, n_elec, order)
+    else:
+        result["cpu_baseline"] = None
+    handle.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

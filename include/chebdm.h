@@ -50,6 +50,15 @@ enum chebdm_prec {
                        /* terms hi*hi + hi*lo + lo*hi, float32 accumulation  */
 };
 
+/* Order of the baby-step products T_2..T_k (both give the same matrices). */
+enum chebdm_baby {
+    CHEBDM_BABY_AUTO = 0,       /* stages for CHEBDM_FP64, sequential otherwise           */
+    CHEBDM_BABY_STAGES = 1,     /* Algorithm 1: ceil(log2 k) stages of independent        */
+                                /* products T_{i+u} = 2 T_i T_u - T_{i-u}, one launch each */
+    CHEBDM_BABY_SEQUENTIAL = 2  /* T_{i+1} = 2 T_1 T_i - T_{i-1}: errors grow ~i instead  */
+                                /* of ~i^2, which matters for float32 / bf16 products     */
+};
+
 /* How the giant steps combine the blocks (both give the same polynomial). */
 enum chebdm_giant {
     CHEBDM_GIANT_COMPOSITION = 0, /* sum_l T_l(T_k) R_l by Clenshaw over l (default) */
@@ -73,7 +82,7 @@ typedef struct {
     int32_t k_override;  /* baby-step count k; 0 = ceil(sqrt(L+1))                 */
     int32_t n_quad;      /* quadrature nodes M for c_n; 0 = automatic rule         */
     int32_t max_iter;    /* bisection sweep cap; 0 = 200                           */
-    int32_t reserved;
+    int32_t baby_steps;  /* enum chebdm_baby, default CHEBDM_BABY_AUTO                */
     double tol;          /* target |tr D - N_e| of the mu search; 0 = 1e-10        */
 } chebdm_opts;
 
@@ -185,6 +194,36 @@ int chebdm_moments(chebdm_handle h, const double* dH, int64_t n, int64_t ldh,
  */
 int chebdm_block_coeffs(chebdm_handle h, const double* c, int32_t order, int32_t giant_form,
                         int32_t k_override, int32_t* k_out, int32_t* m_out, double* coef_out);
+
+/*
+ * Launch timing.  While enabled, the library records a HIP event pair on its
+ * stream around every launch of the matrix-product kernel (one pair per
+ * grouped launch), of the block-sum pass and of the Gram contraction.
+ * chebdm_profile_read synchronises the stream, sums the elapsed times since
+ * the last read (or enable) and clears them.  Algorithmic work counted:
+ *   gemm_flop   n^2 (n+1) per product (the n(n+1)/2 distinct outputs of a
+ *               symmetric product, 2n flops each; padding and the discarded
+ *               lower half of diagonal tiles are not counted);
+ *   *_bytes     one read or write of each n x n matrix the pass streams
+ *               (block sums: k-1 reads + m writes; Gram: nl + nt reads).
+ * Not for use while the stream is being captured into a graph.
+ */
+typedef struct {
+    int64_t gemm_launches;   /* launches of the product kernel                    */
+    int64_t gemm_products;   /* products in them (a grouped launch holds several) */
+    double gemm_ms;          /* summed launch durations                           */
+    double gemm_flop;        /* algorithmic flops of those products               */
+    int64_t combine_calls;
+    double combine_ms, combine_bytes;
+    int64_t gram_calls;
+    double gram_ms, gram_bytes;
+} chebdm_profile;
+
+/* Turn launch timing on (enable != 0) or off; clears the counters. */
+int chebdm_profile_enable(chebdm_handle h, int enable);
+
+/* Synchronise, report the timings gathered since the last read, clear them. */
+int chebdm_profile_read(chebdm_handle h, chebdm_profile* out);
 
 #ifdef __cplusplus
 }

@@ -6,6 +6,6 @@ the same entry-point names.  PyTorch provides device memory and streams.
 """
 from ._binding import (  # noqa: F401
     BF16X3, COMPOSITION, EXPORTED, FP32, FP64, LIB_PATH, POWER,
-    ChebdmError, Handle, Info, Opts, chebdm_block_coeffs, chebdm_bounds, chebdm_coeffs, chebdm_density,
-    chebdm_moments, chebdm_mu_search, load_library, make_opts,
+    ChebdmError, Handle, Info, Opts, Profile, chebdm_block_coeffs, chebdm_bounds, chebdm_coeffs, chebdm_density,
+    chebdm_moments, chebdm_mu_search, chebdm_profile_enable, chebdm_profile_read, load_library, make_opts,
 )

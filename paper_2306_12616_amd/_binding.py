@@ -24,12 +24,13 @@ OK, WARN_NOCONV = 0, 1
 ERR_ARG, ERR_HIP, ERR_OOM, ERR_NONFINITE, ERR_BRACKET, ERR_UNSUPPORTED = -1, -2, -3, -4, -5, -6
 
 _PREC_NAMES = {"fp64": FP64, "f64": FP64, "fp32": FP32, "f32": FP32, "bf16x3": BF16X3}
+_BABY_NAMES = {"auto": 0, "stages": 1, "sequential": 2}
 _FORM_NAMES = {"composition": COMPOSITION, "clenshaw": COMPOSITION, "power": POWER, "horner": POWER}
 
 
 class Opts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("giant_form", ctypes.c_int32), ("k_override", ctypes.c_int32),
-                ("n_quad", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_quad", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("baby_steps", ctypes.c_int32),
                 ("tol", ctypes.c_double)]
 
 
@@ -38,6 +39,16 @@ class Info(ctypes.Structure):
                 ("n_quad", ctypes.c_int32), ("iters", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("emin", ctypes.c_double), ("emax", ctypes.c_double), ("mu", ctypes.c_double),
                 ("trace", ctypes.c_double), ("trace_err", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("gemm_launches", ctypes.c_int64), ("gemm_products", ctypes.c_int64), ("gemm_ms", ctypes.c_double),
+                ("gemm_flop", ctypes.c_double), ("combine_calls", ctypes.c_int64), ("combine_ms", ctypes.c_double),
+                ("combine_bytes", ctypes.c_double), ("gram_calls", ctypes.c_int64), ("gram_ms", ctypes.c_double),
+                ("gram_bytes", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -77,6 +88,8 @@ _SIGNATURES = {
     "chebdm_block_coeffs": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                            ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
+    "chebdm_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "chebdm_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Profile)]),
 }
 
 EXPORTED = tuple(_SIGNATURES)
@@ -107,13 +120,14 @@ def _check(rc: int, allow_warn: bool = False) -> int:
 
 
 def make_opts(prec="fp64", giant="composition", k_override: int = 0, n_quad: int = 0,
-              max_iter: int = 0, tol: float = 0.0) -> Opts:
+              max_iter: int = 0, tol: float = 0.0, baby="auto") -> Opts:
     o = Opts()
     load_library().chebdm_default_opts(ctypes.byref(o))
     o.prec = _PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
     o.giant_form = _FORM_NAMES[giant] if isinstance(giant, str) else int(giant)
     o.k_override = int(k_override)
     o.n_quad = int(n_quad)
+    o.baby_steps = _BABY_NAMES[baby] if isinstance(baby, str) else int(baby)
     if max_iter:
         o.max_iter = int(max_iter)
     if tol:
@@ -247,3 +261,13 @@ def chebdm_moments(h: Handle, H, order: int, opts: Optional[Opts] = None, emin: 
     _check(load_library().chebdm_moments(h.ptr, p, n, ld, order, ctypes.byref(opts) if opts is not None else None,
                                          emin, emax, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return out
+
+
+def chebdm_profile_enable(h: Handle, enable: bool = True):
+    _check(load_library().chebdm_profile_enable(h.ptr, 1 if enable else 0))
+
+
+def chebdm_profile_read(h: Handle):
+    p = Profile()
+    _check(load_library().chebdm_profile_read(h.ptr, ctypes.byref(p)))
+    return p.as_dict()

@@ -49,7 +49,7 @@ int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 struct Plan {
     int64_t n = 0, ld = 0;
     int order = 0, k = 1, m = 1, M = 0;
-    int prec = CHEBDM_FP64, form = CHEBDM_GIANT_COMPOSITION;
+    int prec = CHEBDM_FP64, form = CHEBDM_GIANT_COMPOSITION, baby = CHEBDM_BABY_STAGES;
     int max_iter = 200;
     double tol = 1e-10;
     size_t elem = 8;
@@ -76,6 +76,15 @@ struct chebdm_ctx {
     // pinned host mirror for read-backs
     DevScalars* h_scal = nullptr;
     double* h_trD = nullptr;
+    // optional launch timing: HIP events recorded on the handle's stream
+    struct Ev {
+        hipEvent_t a = nullptr, b = nullptr;
+        int kind = 0, products = 0;
+        double flop = 0.0, bytes = 0.0;
+    };
+    bool prof = false;
+    std::vector<Ev> ev;
+    size_t ev_used = 0;
 };
 
 namespace {
@@ -147,6 +156,37 @@ int ensure_mats(chebdm_handle h, const Plan& pl, int64_t count) {
     return 0;
 }
 
+enum { PROF_GEMM = 0, PROF_COMBINE = 1, PROF_GRAM = 2 };
+
+// Opens a timed region on the handle's stream (no-op unless profiling is on).
+int prof_begin(chebdm_handle h, int kind, int products, double flop, double bytes, size_t* idx) {
+    *idx = (size_t)-1;
+    if (!h->prof) return 0;
+    if (h->ev_used == h->ev.size()) {
+        chebdm_ctx::Ev e;
+        HIP_TRY(hipEventCreate(&e.a));
+        HIP_TRY(hipEventCreate(&e.b));
+        h->ev.push_back(e);
+    }
+    chebdm_ctx::Ev& e = h->ev[h->ev_used];
+    e.kind = kind;
+    e.products = products;
+    e.flop = flop;
+    e.bytes = bytes;
+    HIP_TRY(hipEventRecord(e.a, h->stream));
+    *idx = h->ev_used++;
+    return 0;
+}
+
+int prof_end(chebdm_handle h, size_t idx) {
+    if (idx == (size_t)-1) return 0;
+    HIP_TRY(hipEventRecord(h->ev[idx].b, h->stream));
+    return 0;
+}
+
+// Algorithmic flops of one symmetric product: n(n+1)/2 distinct outputs, 2n flops each.
+double sym_product_flop(int64_t n) { return (double)n * (double)n * (double)(n + 1); }
+
 // matrix slot s (0-based) of the workspace
 void* slot(chebdm_handle h, const Plan& pl, int64_t s) {
     return static_cast<char*>(h->mats) + (size_t)s * (size_t)pl.ld * (size_t)pl.ld * pl.elem;
@@ -178,6 +218,11 @@ int check_opts(const chebdm_opts* o, Plan& pl) {
                     "the power form is float64 only: its coefficients grow like 2^m |c|");
     if (o->k_override < 0 || o->n_quad < 0 || o->max_iter < 0 || !(o->tol >= 0.0))
         return fail(CHEBDM_ERR_ARG, "negative option");
+    if (o->baby_steps < CHEBDM_BABY_AUTO || o->baby_steps > CHEBDM_BABY_SEQUENTIAL)
+        return fail(CHEBDM_ERR_ARG, "unknown baby-step schedule");
+    pl.baby = o->baby_steps != CHEBDM_BABY_AUTO
+                  ? o->baby_steps
+                  : (o->prec == CHEBDM_FP64 ? CHEBDM_BABY_STAGES : CHEBDM_BABY_SEQUENTIAL);
     pl.prec = o->prec;
     pl.form = o->giant_form;
     pl.elem = o->prec == CHEBDM_FP64 ? 8 : 4;
@@ -264,13 +309,17 @@ struct Chain {
         ++*n_gemm;
     }
     int flush() {
+        const int cnt = pl.elem == 8 ? b64.count : b32.count;
+        if (cnt == 0) return 0;
+        size_t ev;
+        CHECK(prof_begin(h, PROF_GEMM, cnt, cnt * sym_product_flop(pl.n), 0.0, &ev));
         hipError_t e = hipSuccess;
-        if (pl.elem == 8 && b64.count) e = launch_gemm_f64(b64, pl.n, pl.ld, h->stream);
-        if (pl.elem == 4 && b32.count)
-            e = launch_gemm_f32(b32, pl.n, pl.ld, pl.prec == CHEBDM_BF16X3, h->stream);
+        if (pl.elem == 8) e = launch_gemm_f64(b64, pl.n, pl.ld, h->stream);
+        else e = launch_gemm_f32(b32, pl.n, pl.ld, pl.prec == CHEBDM_BF16X3, h->stream);
         b64.count = 0;
         b32.count = 0;
         HIP_TRY(e);
+        CHECK(prof_end(h, ev));
         return 0;
     }
 };
@@ -286,6 +335,15 @@ void* rslot(chebdm_handle h, const Plan& pl, int l) { return slot(h, pl, pl.k + 
 int baby_steps(chebdm_handle h, const Plan& pl, int* n_gemm) {
     if (pl.k < 2) return 0;
     Chain ch(h, pl, n_gemm);
+    if (pl.baby == CHEBDM_BABY_SEQUENTIAL) {
+        // T_{i+1} = 2 T_1 T_i - T_{i-1}, T_0 = I
+        for (int i = 1; i < pl.k; ++i) {
+            ch.add(tslot(h, pl, 1), tslot(h, pl, i), i == 1 ? nullptr : tslot(h, pl, i - 1), -1.0, nullptr, 0.0,
+                   2.0, i == 1 ? -1.0 : 0.0, tslot(h, pl, i + 1), pl.ld, 0);
+            CHECK(ch.flush());
+        }
+        return 0;
+    }
     // stage 1: T_2 = 2 T_1 T_1 - T_0
     ch.add(tslot(h, pl, 1), tslot(h, pl, 1), nullptr, 0.0, nullptr, 0.0, 2.0, -1.0, tslot(h, pl, 2), pl.ld, 0);
     CHECK(ch.flush());
@@ -334,12 +392,15 @@ int moments_on_device(chebdm_handle h, const Plan& pl, int* n_gemm) {
         for (int l = 1; l <= lmax; ++l) lm[l - 1] = lptr(l);
         for (int i = 1; i <= k; ++i) tm[i - 1] = tslot(h, pl, i);
         const int64_t nelem = pl.n * pl.ld;
+        size_t ev;
+        CHECK(prof_begin(h, PROF_GRAM, 0, 0.0, (double)(lmax + k) * pl.n * pl.n * pl.elem, &ev));
         if (pl.elem == 8)
             HIP_TRY(launch_gram<double>((const double* const*)lm.data(), lmax, (const double* const*)tm.data(), k,
                                         nelem, h->partial, kPartialDoubles, h->gram, h->stream));
         else
             HIP_TRY(launch_gram<float>((const float* const*)lm.data(), lmax, (const float* const*)tm.data(), k,
                                        nelem, h->partial, kPartialDoubles, h->gram, h->stream));
+        CHECK(prof_end(h, ev));
     }
     HIP_TRY(launch_assemble_moments(h->trb, h->gram, k, pl.m, L, pl.n, h->tau, h->stream));
     return 0;
@@ -349,12 +410,15 @@ int moments_on_device(chebdm_handle h, const Plan& pl, int* n_gemm) {
 int giant_steps(chebdm_handle h, const Plan& pl, double* dD, int64_t ldd, int* n_gemm) {
     const int k = pl.k, m = pl.m;
     const int64_t stride = pl.ld * pl.ld;
+    size_t ev;
+    CHECK(prof_begin(h, PROF_COMBINE, 0, 0.0, (double)(k - 1 + m) * pl.n * pl.n * pl.elem, &ev));
     if (pl.elem == 8)
         HIP_TRY(launch_combine<double>((const double*)tslot(h, pl, 1), stride, k, m, h->coef,
                                        (double*)rslot(h, pl, 0), pl.n, pl.ld, h->stream));
     else
         HIP_TRY(launch_combine<float>((const float*)tslot(h, pl, 1), stride, k, m, h->coef,
                                       (float*)rslot(h, pl, 0), pl.n, pl.ld, h->stream));
+    CHECK(prof_end(h, ev));
     if (m == 1) {
         HIP_TRY(launch_copy_out(rslot(h, pl, 0), pl.elem == 8, pl.ld, pl.n, dD, ldd, h->stream));
     } else {
@@ -414,6 +478,7 @@ void chebdm_default_opts(chebdm_opts* o) {
     std::memset(o, 0, sizeof(*o));
     o->prec = CHEBDM_FP64;
     o->giant_form = CHEBDM_GIANT_COMPOSITION;
+    o->baby_steps = CHEBDM_BABY_AUTO;
     o->max_iter = 200;
     o->tol = 1e-10;
 }
@@ -447,6 +512,10 @@ int chebdm_destroy(chebdm_handle h) {
     if (!h) return CHEBDM_OK;
     (void)hipSetDevice(h->device);
     (void)hipStreamSynchronize(h->stream);
+    for (auto& e : h->ev) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
     if (h->mats) (void)hipFree(h->mats);
     if (h->small) (void)hipFree(h->small);
     if (h->h_scal) (void)hipHostFree(h->h_scal);
@@ -637,6 +706,47 @@ int chebdm_moments(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, in
     CHECK(moments_on_device(h, pl, &pl.n_gemm));
     HIP_TRY(hipMemcpyAsync(tau_out, h->tau, sizeof(double) * (size_t)(order + 1), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
+    return CHEBDM_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int chebdm_profile_enable(chebdm_handle h, int enable) {
+    if (!h) return fail(CHEBDM_ERR_ARG, "handle is NULL");
+    CHECK(set_device(h));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->prof = enable != 0;
+    h->ev_used = 0;
+    return CHEBDM_OK;
+}
+
+int chebdm_profile_read(chebdm_handle h, chebdm_profile* out) {
+    if (!h || !out) return fail(CHEBDM_ERR_ARG, "NULL argument");
+    CHECK(set_device(h));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    std::memset(out, 0, sizeof(*out));
+    for (size_t i = 0; i < h->ev_used; ++i) {
+        const chebdm_ctx::Ev& e = h->ev[i];
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, e.a, e.b));
+        if (e.kind == PROF_GEMM) {
+            out->gemm_launches += 1;
+            out->gemm_products += e.products;
+            out->gemm_ms += ms;
+            out->gemm_flop += e.flop;
+        } else if (e.kind == PROF_COMBINE) {
+            out->combine_calls += 1;
+            out->combine_ms += ms;
+            out->combine_bytes += e.bytes;
+        } else {
+            out->gram_calls += 1;
+            out->gram_ms += ms;
+            out->gram_bytes += e.bytes;
+        }
+    }
+    h->ev_used = 0;
     return CHEBDM_OK;
 }
 

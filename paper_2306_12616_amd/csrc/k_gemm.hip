@@ -16,6 +16,15 @@
 // R_l + 2 T_k B_{l+1} - B_{l+2}, the Horner step S_j + T_k R, and the "- T_0"
 // of the first products (delta = -1) without storing an identity matrix.
 //
+// Symmetric output: A B is symmetric, so only the tiles on and above the
+// diagonal are computed (blockIdx.x enumerates the upper triangle) and every
+// value is stored twice, at (i, j) and (j, i); inside a diagonal tile only
+// i <= j is kept.  This halves the executed flops and, more importantly,
+// keeps every matrix of the chain exactly symmetric: reading B along rows
+// equals B only for an exactly symmetric B, and an antisymmetric rounding
+// part left in the stored matrices grows along the recurrences (measured:
+// 6e-10 in float64 and O(1) in float32 at N = 1000, order 512).
+//
 // Workspace matrices are ld x ld with ld a multiple of 128 and a zero
 // padding outside the leading n x n block; the kernels read whole tiles
 // without bounds checks and write only the n x n block, so the padding stays
@@ -122,11 +131,25 @@ __device__ __forceinline__ void mma_chunk(typename Traits<P>::Acc (&acc)[FM][FN]
     }
 }
 
+// Tile (I, J), I <= J, of linear index t in the row-major upper triangle of a
+// T x T tile grid; row I starts at I*T - I*(I-1)/2.
+__device__ __forceinline__ void upper_tile(int t, int T, int& I, int& J) {
+    const double b = 2.0 * T + 1.0;
+    int i = (int)floor(0.5 * (b - sqrt(b * b - 8.0 * (double)t)));
+    if (i < 0) i = 0;
+    while (i > 0 && i * T - i * (i - 1) / 2 > t) --i;
+    while (i + 1 < T && (i + 1) * T - (i + 1) * i / 2 <= t) ++i;
+    I = i;
+    J = t - (i * T - i * (i - 1) / 2) + i;
+}
+
 // BM x BN workgroup tile, WGM x WGN wavefronts, each owning a (BM/WGM) x (BN/WGN) tile
-// made of 16 x 16 MFMA blocks.  blockIdx.z selects the product inside a grouped launch.
+// made of 16 x 16 MFMA blocks.  blockIdx.x: upper-triangle tile; blockIdx.z: the
+// product inside a grouped launch.
 template <int P, int BM, int BN, int WGM, int WGN>
 __global__ void __launch_bounds__(64 * WGM * WGN)
-k_gemm(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, int64_t kpad) {
+k_gemm(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, int64_t kpad, int ntile) {
+    static_assert(BM == BN, "the symmetric tiling needs square tiles");
     using T = typename Traits<P>::T;
     using Acc = typename Traits<P>::Acc;
     constexpr int KU = Traits<P>::KU;
@@ -138,8 +161,11 @@ k_gemm(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, int6
     const GemmDesc<T>& g = batch.d[blockIdx.z];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wm = wave / WGN, wn = wave % WGN;
-    const int64_t row0 = (int64_t)blockIdx.y * BM + wm * WTM;
-    const int64_t col0 = (int64_t)blockIdx.x * BN + wn * WTN;
+    int ti, tj;
+    upper_tile((int)blockIdx.x, ntile, ti, tj);
+    const bool diag_tile = ti == tj;
+    const int64_t row0 = (int64_t)ti * BM + wm * WTM;
+    const int64_t col0 = (int64_t)tj * BN + wn * WTN;
     const int lr = lane & 15, lq = lane >> 4;
 
     const T* __restrict__ pa = g.A + (row0 + lr) * ld + lq * KU;
@@ -187,15 +213,20 @@ k_gemm(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, int6
             for (int r = 0; r < 4; ++r) {
                 const int64_t row = row0 + f * 16 + (P == P_F64 ? lq + 4 * r : lq * 4 + r);
                 const int64_t col = col0 + q * 16 + lr;
-                if (row < n && col < n) {
+                if (row < n && col < n && !(diag_tile && row > col)) {
                     const int64_t idx = row * ld + col;
                     double v = alpha * (double)acc[f][q][r];
                     if (C) v += beta * (double)C[idx];
                     if (E) v += gamma * (double)E[idx];
                     if (row == col) v += delta;
-                    const int64_t o = row * g.ld_out + col;
-                    if (g.out_f64) static_cast<double*>(g.Out)[o] = v;
-                    else static_cast<T*>(g.Out)[o] = (T)v;
+                    const int64_t o = row * g.ld_out + col, om = col * g.ld_out + row;
+                    if (g.out_f64) {
+                        static_cast<double*>(g.Out)[o] = v;
+                        if (row != col) static_cast<double*>(g.Out)[om] = v;
+                    } else {
+                        static_cast<T*>(g.Out)[o] = (T)v;
+                        if (row != col) static_cast<T*>(g.Out)[om] = (T)v;
+                    }
                 }
             }
 }
@@ -207,8 +238,10 @@ hipError_t launch_cfg(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
     const int64_t kpad = (n + CH - 1) / CH * CH;
     if (kpad > ld || (n + BM - 1) / BM * BM > ld || (n + BN - 1) / BN * BN > ld)
         return hipErrorInvalidValue;
-    dim3 grid((unsigned)((n + BN - 1) / BN), (unsigned)((n + BM - 1) / BM), (unsigned)b.count);
-    hipLaunchKernelGGL((k_gemm<P, BM, BN, WGM, WGN>), grid, dim3(64 * WGM * WGN), 0, st, b, n, ld, kpad);
+    const int ntile = (int)((n + BM - 1) / BM);
+    dim3 grid((unsigned)(ntile * (ntile + 1) / 2), 1, (unsigned)b.count);
+    hipLaunchKernelGGL((k_gemm<P, BM, BN, WGM, WGN>), grid, dim3(64 * WGM * WGN), 0, st, b, n, ld, kpad,
+                       ntile);
     return hipGetLastError();
 }
 
@@ -216,7 +249,8 @@ template <int P>
 hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int64_t ld, hipStream_t st) {
     if (b.count <= 0) return hipSuccess;
     if (b.count > kMaxGroup || ld % 128 != 0) return hipErrorInvalidValue;
-    const int64_t big_tiles = ((n + 127) / 128) * ((n + 127) / 128) * b.count;
+    const int64_t t128 = (n + 127) / 128;
+    const int64_t big_tiles = t128 * (t128 + 1) / 2 * b.count;
     if (big_tiles >= 512) return launch_cfg<P, 128, 128, 2, 2>(b, n, ld, st);
     return launch_cfg<P, 64, 64, 2, 2>(b, n, ld, st);
 }

@@ -289,3 +289,42 @@ def test_mu_search_scalar_hamiltonian(cd, handle):
     occ = ne / n
     assert abs(1.0 / (1.0 + math.exp(beta * (c0 - mu))) - occ) < 1e-15
     assert np.max(np.abs(D.cpu().numpy() - occ * np.eye(n))) <= 1e-15
+
+
+# ------------------------------------------------------- structure and options
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_density_is_exactly_symmetric(cd, handle, prec):
+    # only upper-triangle tiles are computed and mirrored: D == D^T bit for bit
+    h, q, lam = synth.hamiltonian(333, "gaussmix6", seed=12)
+    D, info = cd.chebdm_density(handle, _dev(h), 40.0, 0.0, 150, cd.make_opts(prec))
+    torch.cuda.synchronize()
+    d = D.cpu().numpy()
+    assert np.array_equal(d, d.T)
+
+
+@pytest.mark.parametrize("baby", ["stages", "sequential"])
+@pytest.mark.parametrize("n,order", [(256, 128), (700, 512)])
+def test_baby_schedules_match_oracle(cd, handle, baby, n, order):
+    _say(f"baby={baby} n={n} order={order}")
+    h, q, lam = synth.hamiltonian(n, "gaussmix6", seed=40 + n)
+    D, info = cd.chebdm_density(handle, _dev(h), 100.0, 0.02, order, cd.make_opts("fp64", baby=baby))
+    torch.cuda.synchronize()
+    ref, _ = _oracle_density(q, lam, order, 100.0, 0.02, info["emin"], info["emax"], info["n_quad"])
+    err = np.max(np.abs(D.cpu().numpy() - ref))
+    _say(f"  max|D - D_oracle| = {err:.3e}")
+    assert err <= 1e-10
+
+
+def test_profile_counts_products(cd, handle):
+    h, q, lam = synth.hamiltonian(300, "uniform", seed=31)
+    H = _dev(h)
+    cd.chebdm_profile_enable(handle, True)
+    mu, D, info = cd.chebdm_mu_search(handle, H, 50.0, 150.0, 128)
+    prof = cd.chebdm_profile_read(handle)
+    cd.chebdm_profile_enable(handle, False)
+    assert prof["gemm_products"] == info["n_gemm"]
+    assert prof["gemm_flop"] == info["n_gemm"] * 300.0 * 300.0 * 301.0
+    assert prof["gemm_ms"] > 0 and prof["combine_calls"] == 1 and prof["gram_calls"] == 1
+    # read clears the counters
+    assert cd.chebdm_profile_read(handle)["gemm_launches"] == 0
