@@ -53,54 +53,59 @@ template <int P> struct Traits;
 template <> struct Traits<P_F64> {
     using T = double;
     using Acc = f64x4;
-    static constexpr int KU = 2;   // k per lane per chunk
+    static constexpr int MK = 1;   // k per MFMA and lane
 };
 template <> struct Traits<P_F32> {
     using T = float;
     using Acc = f32x4;
-    static constexpr int KU = 4;
+    static constexpr int MK = 1;
 };
 template <> struct Traits<P_BF16X3> {
     using T = float;
     using Acc = f32x4;
-    static constexpr int KU = 8;
+    static constexpr int MK = 8;
 };
 
-template <int P> struct Frag;
-template <> struct Frag<P_F64> { f64x2 v; };
-template <> struct Frag<P_F32> { f32x4 v; };
-template <> struct Frag<P_BF16X3> { f32x4 v0, v1; };
+// KU consecutive k of one row per lane, loaded as 16-byte vectors.
+template <typename T, int KU>
+struct Frag {
+    T v[KU];
+};
 
-template <int P>
-__device__ __forceinline__ void load_frag(Frag<P>& f, const typename Traits<P>::T* p) {
-    if constexpr (P == P_F64) {
-        f.v = *reinterpret_cast<const f64x2*>(p);
-    } else if constexpr (P == P_F32) {
-        f.v = *reinterpret_cast<const f32x4*>(p);
-    } else {
-        f.v0 = *reinterpret_cast<const f32x4*>(p);
-        f.v1 = *reinterpret_cast<const f32x4*>(p + 4);
+template <typename T, int KU>
+__device__ __forceinline__ void load_frag(Frag<T, KU>& f, const T* p) {
+    constexpr int PER = 16 / sizeof(T);
+    static_assert(KU % PER == 0, "KU must fill 16-byte loads");
+#pragma unroll
+    for (int c = 0; c < KU / PER; ++c) {
+        if constexpr (sizeof(T) == 8) {
+            const f64x2 x = *reinterpret_cast<const f64x2*>(p + c * PER);
+            f.v[c * 2] = x[0];
+            f.v[c * 2 + 1] = x[1];
+        } else {
+            const f32x4 x = *reinterpret_cast<const f32x4*>(p + c * PER);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) f.v[c * 4 + t] = x[t];
+        }
     }
 }
 
-__device__ __forceinline__ void split_bf16(const Frag<P_BF16X3>& f, bf16x8& hi, bf16x8& lo) {
+__device__ __forceinline__ void split_bf16(const float* x, bf16x8& hi, bf16x8& lo) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const float x0 = f.v0[t], x1 = f.v1[t];
-        const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1;
-        hi[t] = h0;
-        hi[t + 4] = h1;
-        lo[t] = (__bf16)(x0 - (float)h0);
-        lo[t + 4] = (__bf16)(x1 - (float)h1);
+    for (int t = 0; t < 8; ++t) {
+        const __bf16 h = (__bf16)x[t];
+        hi[t] = h;
+        lo[t] = (__bf16)(x[t] - (float)h);
     }
 }
 
-template <int P, int FM, int FN>
-__device__ __forceinline__ void mma_chunk(typename Traits<P>::Acc (&acc)[FM][FN], const Frag<P> (&a)[FM],
-                                          const Frag<P> (&b)[FN]) {
+template <int P, int KU, int FM, int FN>
+__device__ __forceinline__ void mma_chunk(typename Traits<P>::Acc (&acc)[FM][FN],
+                                          const Frag<typename Traits<P>::T, KU> (&a)[FM],
+                                          const Frag<typename Traits<P>::T, KU> (&b)[FN]) {
     if constexpr (P == P_F64) {
 #pragma unroll
-        for (int s = 0; s < 2; ++s)
+        for (int s = 0; s < KU; ++s)
 #pragma unroll
             for (int f = 0; f < FM; ++f)
 #pragma unroll
@@ -108,26 +113,29 @@ __device__ __forceinline__ void mma_chunk(typename Traits<P>::Acc (&acc)[FM][FN]
                     acc[f][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[f].v[s], b[g].v[s], acc[f][g], 0, 0, 0);
     } else if constexpr (P == P_F32) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int s = 0; s < KU; ++s)
 #pragma unroll
             for (int f = 0; f < FM; ++f)
 #pragma unroll
                 for (int g = 0; g < FN; ++g)
                     acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[f].v[s], b[g].v[s], acc[f][g], 0, 0, 0);
     } else {
-        bf16x8 ah[FM], al[FM], bh[FN], bl[FN];
 #pragma unroll
-        for (int f = 0; f < FM; ++f) split_bf16(a[f], ah[f], al[f]);
+        for (int s = 0; s < KU / 8; ++s) {
+            bf16x8 ah[FM], al[FM], bh[FN], bl[FN];
 #pragma unroll
-        for (int g = 0; g < FN; ++g) split_bf16(b[g], bh[g], bl[g]);
+            for (int f = 0; f < FM; ++f) split_bf16(&a[f].v[8 * s], ah[f], al[f]);
 #pragma unroll
-        for (int f = 0; f < FM; ++f)
+            for (int g = 0; g < FN; ++g) split_bf16(&b[g].v[8 * s], bh[g], bl[g]);
 #pragma unroll
-            for (int g = 0; g < FN; ++g) {
-                acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[f], bh[g], acc[f][g], 0, 0, 0);
-                acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f], bl[g], acc[f][g], 0, 0, 0);
-                acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f], bh[g], acc[f][g], 0, 0, 0);
-            }
+            for (int f = 0; f < FM; ++f)
+#pragma unroll
+                for (int g = 0; g < FN; ++g) {
+                    acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[f], bh[g], acc[f][g], 0, 0, 0);
+                    acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f], bl[g], acc[f][g], 0, 0, 0);
+                    acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f], bh[g], acc[f][g], 0, 0, 0);
+                }
+        }
     }
 }
 
@@ -143,29 +151,49 @@ __device__ __forceinline__ void upper_tile(int t, int T, int& I, int& J) {
     J = t - (i * T - i * (i - 1) / 2) + i;
 }
 
-// BM x BN workgroup tile, WGM x WGN wavefronts, each owning a (BM/WGM) x (BN/WGN) tile
-// made of 16 x 16 MFMA blocks.  blockIdx.x: upper-triangle tile; blockIdx.z: the
-// product inside a grouped launch.
-template <int P, int BM, int BN, int WGM, int WGN>
+// Work-group -> tile order.  Work-groups are dealt round-robin to the 8 XCDs
+// (each with its own L2); with XCD = 1 the linear id is permuted so that each
+// XCD walks a contiguous stretch of the row-major upper triangle, whose tiles
+// share A row panels in that XCD's L2.
+template <int XCD>
+__device__ __forceinline__ void tile_of_block(int ntri, int& t, int& z) {
+    const int gx = gridDim.x;
+    int lin = (int)blockIdx.x + (int)blockIdx.z * gx;
+    if constexpr (XCD) {
+        const int total = gx * (int)gridDim.z;
+        const int q = total / 8, r = total % 8;
+        const int x = lin % 8, slot = lin / 8;
+        lin = x * q + (x < r ? x : r) + slot;
+    }
+    t = lin % gx;
+    z = lin / gx;
+    (void)ntri;
+}
+
+// BM x BM workgroup tile, WGM x WGN wavefronts, each owning a (BM/WGM) x (BM/WGN) tile
+// made of 16 x 16 MFMA blocks; KU consecutive k per lane and chunk (chunk = 4 KU k).
+// blockIdx.x enumerates upper-triangle tiles, blockIdx.z the products of a grouped launch.
+template <int P, int BM, int WGM, int WGN, int KU, int XCD>
 __global__ void __launch_bounds__(64 * WGM * WGN)
 k_gemm(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, int64_t kpad, int ntile) {
-    static_assert(BM == BN, "the symmetric tiling needs square tiles");
     using T = typename Traits<P>::T;
     using Acc = typename Traits<P>::Acc;
-    constexpr int KU = Traits<P>::KU;
     constexpr int CH = 4 * KU;                 // k per chunk
-    constexpr int WTM = BM / WGM, WTN = BN / WGN;
+    constexpr int WTM = BM / WGM, WTN = BM / WGN;
     constexpr int FM = WTM / 16, FN = WTN / 16;
-    static_assert(FM >= 1 && FN >= 1, "wave tile must hold whole MFMA blocks");
+    static_assert(FM >= 1 && FN >= 1 && WTM % 16 == 0 && WTN % 16 == 0, "wave tile must hold whole MFMA blocks");
+    static_assert(KU % Traits<P>::MK == 0, "KU must be a multiple of the MFMA k per lane");
 
-    const GemmDesc<T>& g = batch.d[blockIdx.z];
+    int tlin, z;
+    tile_of_block<XCD>(ntile * (ntile + 1) / 2, tlin, z);
+    const GemmDesc<T>& g = batch.d[z];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wm = wave / WGN, wn = wave % WGN;
     int ti, tj;
-    upper_tile((int)blockIdx.x, ntile, ti, tj);
+    upper_tile(tlin, ntile, ti, tj);
     const bool diag_tile = ti == tj;
     const int64_t row0 = (int64_t)ti * BM + wm * WTM;
-    const int64_t col0 = (int64_t)tj * BN + wn * WTN;
+    const int64_t col0 = (int64_t)tj * BM + wn * WTN;
     const int lr = lane & 15, lq = lane >> 4;
 
     const T* __restrict__ pa = g.A + (row0 + lr) * ld + lq * KU;
@@ -177,82 +205,130 @@ k_gemm(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, int6
 #pragma unroll
         for (int q = 0; q < FN; ++q) acc[f][q] = Acc{};
 
-    Frag<P> a0[FM], b0[FN], a1[FM], b1[FN];
-    auto load = [&](Frag<P>(&fa)[FM], Frag<P>(&fb)[FN], int64_t k) {
+    Frag<T, KU> a0[FM], b0[FN], a1[FM], b1[FN];
+    auto load = [&](Frag<T, KU>(&fa)[FM], Frag<T, KU>(&fb)[FN], int64_t k) {
 #pragma unroll
-        for (int f = 0; f < FM; ++f) load_frag<P>(fa[f], pa + (int64_t)f * 16 * ld + k);
+        for (int f = 0; f < FM; ++f) load_frag<T, KU>(fa[f], pa + (int64_t)f * 16 * ld + k);
 #pragma unroll
-        for (int q = 0; q < FN; ++q) load_frag<P>(fb[q], pb + (int64_t)q * 16 * ld + k);
+        for (int q = 0; q < FN; ++q) load_frag<T, KU>(fb[q], pb + (int64_t)q * 16 * ld + k);
     };
 
-    // two register stages: the next chunk's loads are in flight while the MFMAs run
+    // Two register stages with no branch inside the loop: kpad is a multiple of
+    // 2 CH, and the loads past the end are clamped to the last chunks (their
+    // values are never used).  Straight-line code lets the compiler wait only
+    // for the chunk being consumed while the next one is in flight.
     load(a0, b0, 0);
-    int64_t k0 = 0;
-    while (true) {
-        if (k0 + CH < kpad) load(a1, b1, k0 + CH);
-        mma_chunk<P, FM, FN>(acc, a0, b0);
-        k0 += CH;
-        if (k0 >= kpad) break;
-        if (k0 + CH < kpad) load(a0, b0, k0 + CH);
-        mma_chunk<P, FM, FN>(acc, a1, b1);
-        k0 += CH;
+    load(a1, b1, CH);
+    for (int64_t k0 = 0;;) {
+        mma_chunk<P, KU, FM, FN>(acc, a0, b0);
+        load(a0, b0, (k0 + 2 * CH < kpad) ? k0 + 2 * CH : kpad - 2 * CH);
+        mma_chunk<P, KU, FM, FN>(acc, a1, b1);
+        load(a1, b1, (k0 + 3 * CH < kpad) ? k0 + 3 * CH : kpad - CH);
+        k0 += 2 * CH;
         if (k0 >= kpad) break;
     }
 
     // Output layout of a 16 x 16 block: lane (lr, lq) holds column lr and, in its
     // r-th register, row 4*lq + r for the f32 and bf16 MFMAs but row lq + 4*r for
     // v_mfma_f64_16x16x4f64 (checked on gfx950).
+    //
+    // C and E are workspace matrices (ld x ld, zero padded), so every tile
+    // position is in bounds: they are read in one unpredicated batch and only
+    // the stores are predicated.
     const double alpha = g.alpha, beta = g.beta, gamma = g.gamma, delta = g.delta;
-    const T* __restrict__ C = g.C;
-    const T* __restrict__ E = g.E;
+    auto row_of = [&](int f, int r) -> int64_t {
+        return row0 + f * 16 + (P == P_F64 ? lq + 4 * r : lq * 4 + r);
+    };
+    double v[FM][FN][4];
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int q = 0; q < FN; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[f][q][r] = alpha * (double)acc[f][q][r];
+    if (g.C) {
+        const T* __restrict__ C = g.C;
+        T cv[FM][FN][4];
+#pragma unroll
+        for (int f = 0; f < FM; ++f)
+#pragma unroll
+            for (int q = 0; q < FN; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) cv[f][q][r] = C[row_of(f, r) * ld + col0 + q * 16 + lr];
+#pragma unroll
+        for (int f = 0; f < FM; ++f)
+#pragma unroll
+            for (int q = 0; q < FN; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[f][q][r] += beta * (double)cv[f][q][r];
+    }
+    if (g.E) {
+        const T* __restrict__ E = g.E;
+        T ev[FM][FN][4];
+#pragma unroll
+        for (int f = 0; f < FM; ++f)
+#pragma unroll
+            for (int q = 0; q < FN; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ev[f][q][r] = E[row_of(f, r) * ld + col0 + q * 16 + lr];
+#pragma unroll
+        for (int f = 0; f < FM; ++f)
+#pragma unroll
+            for (int q = 0; q < FN; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[f][q][r] += gamma * (double)ev[f][q][r];
+    }
+    const int64_t ldo = g.ld_out;
 #pragma unroll
     for (int f = 0; f < FM; ++f)
 #pragma unroll
         for (int q = 0; q < FN; ++q)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t row = row0 + f * 16 + (P == P_F64 ? lq + 4 * r : lq * 4 + r);
+                const int64_t row = row_of(f, r);
                 const int64_t col = col0 + q * 16 + lr;
                 if (row < n && col < n && !(diag_tile && row > col)) {
-                    const int64_t idx = row * ld + col;
-                    double v = alpha * (double)acc[f][q][r];
-                    if (C) v += beta * (double)C[idx];
-                    if (E) v += gamma * (double)E[idx];
-                    if (row == col) v += delta;
-                    const int64_t o = row * g.ld_out + col, om = col * g.ld_out + row;
+                    const double x = v[f][q][r] + (row == col ? delta : 0.0);
+                    const int64_t o = row * ldo + col, om = col * ldo + row;
                     if (g.out_f64) {
-                        static_cast<double*>(g.Out)[o] = v;
-                        if (row != col) static_cast<double*>(g.Out)[om] = v;
+                        static_cast<double*>(g.Out)[o] = x;
+                        if (row != col) static_cast<double*>(g.Out)[om] = x;
                     } else {
-                        static_cast<T*>(g.Out)[o] = (T)v;
-                        if (row != col) static_cast<T*>(g.Out)[om] = (T)v;
+                        static_cast<T*>(g.Out)[o] = (T)x;
+                        if (row != col) static_cast<T*>(g.Out)[om] = (T)x;
                     }
                 }
             }
 }
 
-template <int P, int BM, int BN, int WGM, int WGN>
-hipError_t launch_cfg(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int64_t ld,
-                      hipStream_t st) {
-    constexpr int CH = 4 * Traits<P>::KU;
-    const int64_t kpad = (n + CH - 1) / CH * CH;
-    if (kpad > ld || (n + BM - 1) / BM * BM > ld || (n + BN - 1) / BN * BN > ld)
-        return hipErrorInvalidValue;
+template <int P, int BM, int WGM, int WGN, int KU, int XCD>
+hipError_t launch_cfg(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int64_t ld, hipStream_t st) {
+    constexpr int CH = 4 * KU;
+    const int64_t kpad = (n + 2 * CH - 1) / (2 * CH) * (2 * CH);
+    if (kpad > ld || (n + BM - 1) / BM * BM > ld) return hipErrorInvalidValue;
     const int ntile = (int)((n + BM - 1) / BM);
     dim3 grid((unsigned)(ntile * (ntile + 1) / 2), 1, (unsigned)b.count);
-    hipLaunchKernelGGL((k_gemm<P, BM, BN, WGM, WGN>), grid, dim3(64 * WGM * WGN), 0, st, b, n, ld, kpad,
+    hipLaunchKernelGGL((k_gemm<P, BM, WGM, WGN, KU, XCD>), grid, dim3(64 * WGM * WGN), 0, st, b, n, ld, kpad,
                        ntile);
     return hipGetLastError();
 }
 
+// Configuration from a measured sweep on MI355X (N = 1000/2000/4000): one
+// wavefront per 64 x 64 tile (64-thread work-groups, XCD-ordered) is fastest
+// whenever the upper triangle offers a few hundred tiles (float64 at N = 4000:
+// 59 TFLOP/s algorithmic vs 36 for 2 x 2 waves on 128-tiles); smaller
+// problems need more wavefronts per tile to fill the 1024 SIMDs, so they use
+// 2 x 2 waves of 32 x 32 on each 64-tile.
 template <int P>
 hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int64_t ld, hipStream_t st) {
     if (b.count <= 0) return hipSuccess;
     if (b.count > kMaxGroup || ld % 128 != 0) return hipErrorInvalidValue;
-    const int64_t t128 = (n + 127) / 128;
-    const int64_t big_tiles = t128 * (t128 + 1) / 2 * b.count;
-    if (big_tiles >= 512) return launch_cfg<P, 128, 128, 2, 2>(b, n, ld, st);
-    return launch_cfg<P, 64, 64, 2, 2>(b, n, ld, st);
+    constexpr int KU1 = P == P_F64 ? 4 : (P == P_F32 ? 8 : 16);   // one wave per tile
+    constexpr int KU4 = P == P_F64 ? 2 : (P == P_F32 ? 4 : 8);    // four waves per tile
+    const int64_t t64 = (n + 63) / 64;
+    const int64_t tiles = t64 * (t64 + 1) / 2 * b.count;
+    if (tiles >= 400) return launch_cfg<P, 64, 1, 1, KU1, 1>(b, n, ld, st);
+    return launch_cfg<P, 64, 2, 2, KU4, 1>(b, n, ld, st);
 }
 
 }  // namespace
