@@ -25,7 +25,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "density matrices/s and % MFMA peak at N=1000/4000 vs plain FP64 path"
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}   # dense MFMA peaks of MI355X
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}   # dense MFMA peaks of MI355X
 PEAK_HBM_GBS = 8000.0
 
 
@@ -64,7 +64,7 @@ def roofline_of(prof, prec):
     """Matrix-product kernel: algorithmic flops / summed launch time vs the MFMA peak."""
     if prof["gemm_ms"] <= 0:
         return None
-    flop = prof["gemm_flop"] * (3.0 if prec == "bf16x3" else 1.0)   # bf16x3 runs three bf16 products
+    flop = prof["gemm_flop"] * {"bf16x3": 3.0, "bf16x6": 6.0}.get(prec, 1.0)   # bf16 products per split product
     achieved = flop / (prof["gemm_ms"] * 1e-3) / 1e12
     peak = PEAK_TFLOPS[prec]
     return {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
@@ -109,7 +109,7 @@ def main():
     ap.add_argument("--n", type=int, default=4000)
     ap.add_argument("--order", type=int, default=512)
     ap.add_argument("--beta", type=float, default=100.0)
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
     ap.add_argument("--no-breakdown", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -146,7 +146,8 @@ def main():
         "metric": METRIC, "value": round(value, 4), "unit": "density matrices/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3 (f32 accumulate)"}[args.prec],
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3 (f32 accumulate)",
+                  "bf16x6": "bf16x6 (f32 accumulate)"}[args.prec],
         "data": "synthetic",
         "config": {"workload": f"mu search + density matrix, N={n}, order {order}, beta {beta:g}, "
                                f"N_e=N/2, H=Q diag(lam) Q^T with lam from a 6-Gaussian mixture",
@@ -165,7 +166,8 @@ def main():
 
     if not args.no_breakdown:
         rows = {}
-        cases = [(1000, "fp64"), (1000, "fp32"), (4000, "fp32"), (4000, "bf16x3"), (1000, "bf16x3")]
+        cases = [(1000, "fp64"), (1000, "fp32"), (4000, "fp32"), (4000, "bf16x3"), (4000, "bf16x6"),
+                 (1000, "bf16x3")]
         if args.prec != "fp64" or n != 4000:
             cases.append((4000, "fp64"))
         for nn, pr in cases:

@@ -46,8 +46,12 @@ typedef struct chebdm_ctx* chebdm_handle;
 enum chebdm_prec {
     CHEBDM_FP64 = 0,   /* float64 MFMA products, float64 matrices            */
     CHEBDM_FP32 = 1,   /* float32 MFMA products, float32 matrices            */
-    CHEBDM_BF16X3 = 2  /* float32 matrices, products as three bfloat16 MFMA  */
+    CHEBDM_BF16X3 = 2, /* float32 matrices, products as three bfloat16 MFMA  */
                        /* terms hi*hi + hi*lo + lo*hi, float32 accumulation  */
+                       /* (x = hi + lo; about 2^-16 relative per product)    */
+    CHEBDM_BF16X6 = 3  /* float32 matrices, x = hi + mid + lo in bfloat16,   */
+                       /* six MFMA terms down to 2^-16 (hh hm mh hl lh mm),  */
+                       /* float32 accumulation: about float32 accuracy       */
 };
 
 /* Order of the baby-step products T_2..T_k (both give the same matrices). */

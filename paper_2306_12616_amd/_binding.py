@@ -18,12 +18,12 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libchebdm.so")
 
-FP64, FP32, BF16X3 = 0, 1, 2
+FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
 COMPOSITION, POWER = 0, 1
 OK, WARN_NOCONV = 0, 1
 ERR_ARG, ERR_HIP, ERR_OOM, ERR_NONFINITE, ERR_BRACKET, ERR_UNSUPPORTED = -1, -2, -3, -4, -5, -6
 
-_PREC_NAMES = {"fp64": FP64, "f64": FP64, "fp32": FP32, "f32": FP32, "bf16x3": BF16X3}
+_PREC_NAMES = {"fp64": FP64, "f64": FP64, "fp32": FP32, "f32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6}
 _BABY_NAMES = {"auto": 0, "stages": 1, "sequential": 2}
 _FORM_NAMES = {"composition": COMPOSITION, "clenshaw": COMPOSITION, "power": POWER, "horner": POWER}
 

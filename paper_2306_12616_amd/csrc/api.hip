@@ -210,7 +210,7 @@ int check_opts(const chebdm_opts* o, Plan& pl) {
     chebdm_opts d;
     chebdm_default_opts(&d);
     if (!o) o = &d;
-    if (o->prec < CHEBDM_FP64 || o->prec > CHEBDM_BF16X3) return fail(CHEBDM_ERR_ARG, "unknown precision");
+    if (o->prec < CHEBDM_FP64 || o->prec > CHEBDM_BF16X6) return fail(CHEBDM_ERR_ARG, "unknown precision");
     if (o->giant_form != CHEBDM_GIANT_COMPOSITION && o->giant_form != CHEBDM_GIANT_POWER)
         return fail(CHEBDM_ERR_ARG, "unknown giant-step form");
     if (o->giant_form == CHEBDM_GIANT_POWER && o->prec != CHEBDM_FP64)
@@ -315,7 +315,8 @@ struct Chain {
         CHECK(prof_begin(h, PROF_GEMM, cnt, cnt * sym_product_flop(pl.n), 0.0, &ev));
         hipError_t e = hipSuccess;
         if (pl.elem == 8) e = launch_gemm_f64(b64, pl.n, pl.ld, h->stream);
-        else e = launch_gemm_f32(b32, pl.n, pl.ld, pl.prec == CHEBDM_BF16X3, h->stream);
+        else e = launch_gemm_f32(b32, pl.n, pl.ld,
+                                 pl.prec == CHEBDM_BF16X6 ? 2 : (pl.prec == CHEBDM_BF16X3 ? 1 : 0), h->stream);
         b64.count = 0;
         b32.count = 0;
         HIP_TRY(e);

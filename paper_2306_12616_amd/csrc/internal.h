@@ -91,7 +91,7 @@ hipError_t launch_gram(const T* const* lmats, int nl, const T* const* tmats, int
 
 // ---- matrix products (k_gemm.hip)
 hipError_t launch_gemm_f64(const GemmBatch<double>& b, int64_t n, int64_t ld, hipStream_t st);
-hipError_t launch_gemm_f32(const GemmBatch<float>& b, int64_t n, int64_t ld, int bf16x3,
-                           hipStream_t st);
+// split: 0 float32 MFMA, 1 bf16x3, 2 bf16x6
+hipError_t launch_gemm_f32(const GemmBatch<float>& b, int64_t n, int64_t ld, int split, hipStream_t st);
 
 }  // namespace chebdm

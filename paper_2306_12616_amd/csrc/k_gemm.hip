@@ -36,6 +36,8 @@
 //   bf16x3  v_mfma_f32_16x16x32_bf16 on hi/lo splits of float operands:
 //           x = hi + lo, hi = bf16(x), lo = bf16(x - hi); AB ~ hi*hi + hi*lo + lo*hi,
 //           float32 accumulation (lo*lo, ~2^-16 relative, is dropped).
+//   bf16x6  three-way split x = hi + mid + lo; the six products down to 2^-16
+//           relative (hh, hm, mh, hl, lh, mm) keep about float32 accuracy.
 #include "internal.h"
 
 namespace chebdm {
@@ -47,7 +49,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-enum { P_F64 = 0, P_F32 = 1, P_BF16X3 = 2 };
+enum { P_F64 = 0, P_F32 = 1, P_BF16X3 = 2, P_BF16X6 = 3 };
 
 template <int P> struct Traits;
 template <> struct Traits<P_F64> {
@@ -61,6 +63,11 @@ template <> struct Traits<P_F32> {
     static constexpr int MK = 1;
 };
 template <> struct Traits<P_BF16X3> {
+    using T = float;
+    using Acc = f32x4;
+    static constexpr int MK = 8;
+};
+template <> struct Traits<P_BF16X6> {
     using T = float;
     using Acc = f32x4;
     static constexpr int MK = 8;
@@ -99,6 +106,18 @@ __device__ __forceinline__ void split_bf16(const float* x, bf16x8& hi, bf16x8& l
     }
 }
 
+__device__ __forceinline__ void split3_bf16(const float* x, bf16x8& hi, bf16x8& mid, bf16x8& lo) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const __bf16 h = (__bf16)x[t];
+        const float r = x[t] - (float)h;
+        const __bf16 m = (__bf16)r;
+        hi[t] = h;
+        mid[t] = m;
+        lo[t] = (__bf16)(r - (float)m);
+    }
+}
+
 template <int P, int KU, int FM, int FN>
 __device__ __forceinline__ void mma_chunk(typename Traits<P>::Acc (&acc)[FM][FN],
                                           const Frag<typename Traits<P>::T, KU> (&a)[FM],
@@ -119,6 +138,27 @@ __device__ __forceinline__ void mma_chunk(typename Traits<P>::Acc (&acc)[FM][FN]
 #pragma unroll
                 for (int g = 0; g < FN; ++g)
                     acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[f].v[s], b[g].v[s], acc[f][g], 0, 0, 0);
+    } else if constexpr (P == P_BF16X6) {
+        // x = hi + mid + lo; keep every term down to 2^-16 relative, smallest first
+#pragma unroll
+        for (int s = 0; s < KU / 8; ++s) {
+            bf16x8 ah[FM], am[FM], al[FM], bh[FN], bm[FN], bl[FN];
+#pragma unroll
+            for (int f = 0; f < FM; ++f) split3_bf16(&a[f].v[8 * s], ah[f], am[f], al[f]);
+#pragma unroll
+            for (int g = 0; g < FN; ++g) split3_bf16(&b[g].v[8 * s], bh[g], bm[g], bl[g]);
+#pragma unroll
+            for (int f = 0; f < FM; ++f)
+#pragma unroll
+                for (int g = 0; g < FN; ++g) {
+                    acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[f], bh[g], acc[f][g], 0, 0, 0);
+                    acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f], bl[g], acc[f][g], 0, 0, 0);
+                    acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[f], bm[g], acc[f][g], 0, 0, 0);
+                    acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[f], bh[g], acc[f][g], 0, 0, 0);
+                    acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f], bm[g], acc[f][g], 0, 0, 0);
+                    acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f], bh[g], acc[f][g], 0, 0, 0);
+                }
+        }
     } else {
 #pragma unroll
         for (int s = 0; s < KU / 8; ++s) {
@@ -337,9 +377,10 @@ hipError_t launch_gemm_f64(const GemmBatch<double>& b, int64_t n, int64_t ld, hi
     return launch_any<P_F64>(b, n, ld, st);
 }
 
-hipError_t launch_gemm_f32(const GemmBatch<float>& b, int64_t n, int64_t ld, int bf16x3,
-                           hipStream_t st) {
-    return bf16x3 ? launch_any<P_BF16X3>(b, n, ld, st) : launch_any<P_F32>(b, n, ld, st);
+hipError_t launch_gemm_f32(const GemmBatch<float>& b, int64_t n, int64_t ld, int split, hipStream_t st) {
+    if (split == 2) return launch_any<P_BF16X6>(b, n, ld, st);
+    if (split == 1) return launch_any<P_BF16X3>(b, n, ld, st);
+    return launch_any<P_F32>(b, n, ld, st);
 }
 
 }  // namespace chebdm
