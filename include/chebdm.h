@@ -200,9 +200,54 @@ int chebdm_block_coeffs(chebdm_handle h, const double* c, int32_t order, int32_t
                         int32_t k_override, int32_t* k_out, int32_t* m_out, double* coef_out);
 
 /*
+ * Batched form: many Hamiltonians of different n with one common order, run
+ * as one HIP graph (captured on the first chebdm_batch_mu_search, replayed
+ * afterwards; the caller's pointers, beta and N_e are read from a table
+ * uploaded before each replay, so the graph is reused across calls).  Per
+ * problem it computes exactly what chebdm_mu_search computes (Gershgorin
+ * bounds, sequential baby steps, ladder and Gram moments, bisection,
+ * composition-form giant steps); every product step of all problems is one
+ * persistent launch over a list of (problem, tile) items.
+ *
+ * chebdm_batch_create: count problems of sizes n[p] (1..65535), order >= 2
+ *   (k, m >= 2); opts: prec any, giant_form must be COMPOSITION, n_quad 0;
+ *   max_quad caps the per-problem quadrature M (0 = 65536; a problem whose
+ *   rule asks for more reports CHEBDM_ERR_ARG in its status).  Allocates
+ *   sum_p (k+m) ld_p^2 workspace elements (ld_p = round_up(n_p, 128)).
+ * chebdm_batch_tune: the autotuner.  Times one product step for each
+ *   candidate schedule on the plan's workspace (tile edge 64 or 32 per size
+ *   bucket n <= 256 / 512 / 768 / larger; problems ordered by decreasing n or
+ *   as given) and keeps the fastest.  cache_path (nullable): a text file of
+ *   "key value" lines; a matching key is applied without timing, a new result
+ *   is appended.  report (nullable) receives a one-line summary.
+ * chebdm_batch_mu_search: host arrays of count entries: dH[p], dD[p] (device
+ *   float64 matrices, row-major), ldh[p], ldd[p], beta[p] > 0,
+ *   0 < n_elec[p] < n[p]; outputs mu_out[p] and optional status_out[p]
+ *   (chebdm_status of that problem), iters_out[p], trace_out[p] (tr D).
+ *   Synchronises.  Returns the worst status (a negative one if any problem
+ *   failed; the others are still valid).
+ * chebdm_batch_info: k, m, products per problem, (problem, tile) items per
+ *   product step, algorithmic flops of all products of one run.
+ */
+typedef struct chebdm_batch_ctx* chebdm_batch;
+
+int chebdm_batch_create(chebdm_handle h, int32_t count, const int64_t* n, int32_t order,
+                        const chebdm_opts* opts, int64_t max_quad, chebdm_batch* out);
+int chebdm_batch_destroy(chebdm_batch b);
+int chebdm_batch_tune(chebdm_batch b, const char* cache_path, char* report, int32_t report_len);
+int chebdm_batch_mu_search(chebdm_batch b, const double* const* dH, const int64_t* ldh,
+                           const double* beta, const double* n_elec, double* const* dD,
+                           const int64_t* ldd, double* mu_out, int32_t* status_out,
+                           int32_t* iters_out, double* trace_out);
+int chebdm_batch_info(chebdm_batch b, int32_t* k, int32_t* m, int32_t* products_per_problem,
+                      int64_t* tiles_per_step, double* flop_per_run);
+
+/*
  * Launch timing.  While enabled, the library records a HIP event pair on its
  * stream around every launch of the matrix-product kernel (one pair per
- * grouped launch), of the block-sum pass and of the Gram contraction.
+ * grouped launch or batched product step), of the block-sum pass and of the
+ * Gram contraction; a batched run then executes eagerly on the handle's
+ * stream instead of replaying its graph.
  * chebdm_profile_read synchronises the stream, sums the elapsed times since
  * the last read (or enable) and clears them.  Algorithmic work counted:
  *   gemm_flop   n^2 (n+1) per product (the n(n+1)/2 distinct outputs of a

@@ -88,6 +88,20 @@ _SIGNATURES = {
     "chebdm_block_coeffs": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                            ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
+    "chebdm_batch_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                           ctypes.c_int32, ctypes.POINTER(Opts), ctypes.c_int64,
+                                           ctypes.POINTER(ctypes.c_void_p)]),
+    "chebdm_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "chebdm_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_int32]),
+    "chebdm_batch_mu_search": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_void_p),
+                                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_double)]),
+    "chebdm_batch_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
     "chebdm_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "chebdm_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Profile)]),
 }
@@ -271,3 +285,89 @@ def chebdm_profile_read(h: Handle):
     p = Profile()
     _check(load_library().chebdm_profile_read(h.ptr, ctypes.byref(p)))
     return p.as_dict()
+
+
+def _arr(ctype, values):
+    a = (ctype * len(values))()
+    for i, v in enumerate(values):
+        a[i] = v
+    return a
+
+
+class Batch:
+    """A batched plan (``chebdm_batch``): many Hamiltonians of different n, one order, one graph."""
+
+    def __init__(self, handle: Handle, sizes, order: int, opts: Optional[Opts] = None, max_quad: int = 0):
+        self.handle = handle
+        self.sizes = [int(v) for v in sizes]
+        self.order = int(order)
+        b = ctypes.c_void_p()
+        _check(load_library().chebdm_batch_create(handle.ptr, len(self.sizes), _arr(ctypes.c_int64, self.sizes),
+                                                  self.order, ctypes.byref(opts) if opts is not None else None,
+                                                  int(max_quad), ctypes.byref(b)))
+        self._b = b
+
+    def tune(self, cache_path: Optional[str] = None) -> str:
+        buf = ctypes.create_string_buffer(1024)
+        _check(load_library().chebdm_batch_tune(self._b, cache_path.encode() if cache_path else None, buf, 1024))
+        return buf.value.decode()
+
+    def info(self):
+        k, m, pp = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        tiles, flop = ctypes.c_int64(), ctypes.c_double()
+        _check(load_library().chebdm_batch_info(self._b, ctypes.byref(k), ctypes.byref(m), ctypes.byref(pp),
+                                                ctypes.byref(tiles), ctypes.byref(flop)))
+        return {"k": k.value, "m": m.value, "products_per_problem": pp.value, "tiles_per_step": tiles.value,
+                "flop_per_run": flop.value}
+
+    def mu_search(self, Hs, betas, n_elecs, Ds=None, allow_errors: bool = False):
+        import torch
+
+        count = len(self.sizes)
+        if len(Hs) != count or len(betas) != count or len(n_elecs) != count:
+            raise ValueError("one H, beta and n_elec per problem")
+        hp, hl = [], []
+        for H, n in zip(Hs, self.sizes):
+            p, nn, ld = _matrix_args(H, "H")
+            if nn != n:
+                raise ValueError("H size does not match the plan")
+            hp.append(p.value)
+            hl.append(ld)
+        if Ds is None:
+            Ds = [torch.empty((n, n), dtype=torch.float64, device=H.device) for H, n in zip(Hs, self.sizes)]
+        dp, dl = [], []
+        for D, n in zip(Ds, self.sizes):
+            p, nn, ld = _matrix_args(D, "D")
+            if nn != n:
+                raise ValueError("D size does not match the plan")
+            dp.append(p.value)
+            dl.append(ld)
+        mu = (ctypes.c_double * count)()
+        status = (ctypes.c_int32 * count)()
+        iters = (ctypes.c_int32 * count)()
+        trace = (ctypes.c_double * count)()
+        self.handle.ptr   # follow torch's current stream
+        rc = load_library().chebdm_batch_mu_search(self._b, _arr(ctypes.c_void_p, hp), _arr(ctypes.c_int64, hl),
+                                                   _arr(ctypes.c_double, [float(v) for v in betas]),
+                                                   _arr(ctypes.c_double, [float(v) for v in n_elecs]),
+                                                   _arr(ctypes.c_void_p, dp), _arr(ctypes.c_int64, dl), mu, status,
+                                                   iters, trace)
+        if rc < 0 and not allow_errors:
+            _check(rc)
+        return (np.array(mu[:]), Ds, np.array(status[:], dtype=np.int32), np.array(iters[:], dtype=np.int32),
+                np.array(trace[:]))
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            load_library().chebdm_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def chebdm_batch_create(h: Handle, sizes, order: int, opts: Optional[Opts] = None, max_quad: int = 0) -> Batch:
+    return Batch(h, sizes, order, opts, max_quad)

@@ -14,11 +14,13 @@
 #include <string>
 #include <vector>
 
+#include "cheb_dev.h"
+#include "ctx.h"
 #include "internal.h"
 
 using namespace chebdm;
 
-namespace {
+namespace chebdm {
 
 thread_local std::string g_last_error;
 
@@ -27,18 +29,40 @@ int fail(int code, const std::string& msg) {
     return code;
 }
 
-#define HIP_TRY(expr)                                                                        \
-    do {                                                                                     \
-        hipError_t e_ = (expr);                                                              \
-        if (e_ != hipSuccess)                                                                \
-            return fail(CHEBDM_ERR_HIP, std::string(#expr) + " failed: " + hipGetErrorString(e_)); \
-    } while (0)
+// Opens a timed region on the handle's stream (no-op unless profiling is on).
+int prof_begin(chebdm_handle h, int kind, int products, double flop, double bytes, size_t* idx) {
+    *idx = (size_t)-1;
+    if (!h->prof) return 0;
+    if (h->ev_used == h->ev.size()) {
+        chebdm_ctx::Ev e;
+        HIP_TRY(hipEventCreate(&e.a));
+        HIP_TRY(hipEventCreate(&e.b));
+        h->ev.push_back(e);
+    }
+    chebdm_ctx::Ev& e = h->ev[h->ev_used];
+    e.kind = kind;
+    e.products = products;
+    e.flop = flop;
+    e.bytes = bytes;
+    HIP_TRY(hipEventRecord(e.a, h->stream));
+    *idx = h->ev_used++;
+    return 0;
+}
 
-#define CHECK(call)                 \
-    do {                            \
-        int rc_ = (call);           \
-        if (rc_ < 0) return rc_;    \
-    } while (0)
+int prof_end(chebdm_handle h, size_t idx) {
+    if (idx == (size_t)-1) return 0;
+    HIP_TRY(hipEventRecord(h->ev[idx].b, h->stream));
+    return 0;
+}
+
+// Algorithmic flops of one symmetric product: n(n+1)/2 distinct outputs, 2n flops each.
+double sym_product_flop(int64_t n) { return (double)n * (double)n * (double)(n + 1); }
+
+}  // namespace chebdm
+
+namespace {
+
+
 
 constexpr int64_t kMaxN = 65535;            // grid rows of the element-wise kernels
 constexpr int64_t kSmallVec = 48 * 48 + 64; // c, block coefficients, tau
@@ -58,34 +82,7 @@ struct Plan {
 
 }  // namespace
 
-struct chebdm_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    // matrix workspace: T_1..T_k then R_0..R_{m-1}, each ld x ld
-    void* mats = nullptr;
-    size_t mats_bytes = 0;
-    int64_t lay_n = -1, lay_ld = -1, lay_count = -1;
-    size_t lay_elem = 0;
-    // small device buffers
-    void* small = nullptr;
-    size_t small_bytes = 0;
-    int64_t small_M = 0;
-    DevScalars* scal = nullptr;
-    double *c = nullptr, *coef = nullptr, *tau = nullptr, *trb = nullptr, *gram = nullptr, *trD = nullptr;
-    double *ftab = nullptr, *xtab = nullptr, *w = nullptr, *partial = nullptr;
-    // pinned host mirror for read-backs
-    DevScalars* h_scal = nullptr;
-    double* h_trD = nullptr;
-    // optional launch timing: HIP events recorded on the handle's stream
-    struct Ev {
-        hipEvent_t a = nullptr, b = nullptr;
-        int kind = 0, products = 0;
-        double flop = 0.0, bytes = 0.0;
-    };
-    bool prof = false;
-    std::vector<Ev> ev;
-    size_t ev_used = 0;
-};
+
 
 namespace {
 
@@ -156,36 +153,7 @@ int ensure_mats(chebdm_handle h, const Plan& pl, int64_t count) {
     return 0;
 }
 
-enum { PROF_GEMM = 0, PROF_COMBINE = 1, PROF_GRAM = 2 };
 
-// Opens a timed region on the handle's stream (no-op unless profiling is on).
-int prof_begin(chebdm_handle h, int kind, int products, double flop, double bytes, size_t* idx) {
-    *idx = (size_t)-1;
-    if (!h->prof) return 0;
-    if (h->ev_used == h->ev.size()) {
-        chebdm_ctx::Ev e;
-        HIP_TRY(hipEventCreate(&e.a));
-        HIP_TRY(hipEventCreate(&e.b));
-        h->ev.push_back(e);
-    }
-    chebdm_ctx::Ev& e = h->ev[h->ev_used];
-    e.kind = kind;
-    e.products = products;
-    e.flop = flop;
-    e.bytes = bytes;
-    HIP_TRY(hipEventRecord(e.a, h->stream));
-    *idx = h->ev_used++;
-    return 0;
-}
-
-int prof_end(chebdm_handle h, size_t idx) {
-    if (idx == (size_t)-1) return 0;
-    HIP_TRY(hipEventRecord(h->ev[idx].b, h->stream));
-    return 0;
-}
-
-// Algorithmic flops of one symmetric product: n(n+1)/2 distinct outputs, 2n flops each.
-double sym_product_flop(int64_t n) { return (double)n * (double)n * (double)(n + 1); }
 
 // matrix slot s (0-based) of the workspace
 void* slot(chebdm_handle h, const Plan& pl, int64_t s) {
@@ -199,12 +167,7 @@ int read_scalars(chebdm_handle h) {
     return 0;
 }
 
-int quadrature_rule(int order, double beta_s) {
-    const double need = std::fmax(2.0 * (order + 1), 0.5 * order + 7.0 * beta_s + 64.0);
-    const double lg = std::ceil(std::log2(need));
-    if (!(lg < 30.0)) return -1;
-    return 1 << (int)lg;
-}
+int quadrature_rule(int order, double beta_s) { return (int)quad_rule(order, beta_s); }
 
 int check_opts(const chebdm_opts* o, Plan& pl) {
     chebdm_opts d;

@@ -95,3 +95,60 @@ hipError_t launch_gemm_f64(const GemmBatch<double>& b, int64_t n, int64_t ld, hi
 hipError_t launch_gemm_f32(const GemmBatch<float>& b, int64_t n, int64_t ld, int split, hipStream_t st);
 
 }  // namespace chebdm
+
+// ======================================================================
+// Batched (many uneven-n problems) path: plan-time geometry and run-time
+// problem table, shared by k_batch.hip and api_batch.hip.
+namespace chebdm {
+
+struct BatchProblem {      // filled by the host before every run (caller's pointers)
+    const double* H;
+    double* D;
+    int64_t ldh, ldd;
+    double beta, n_elec;
+};
+
+struct BatchGeom {         // fixed for a plan
+    int64_t n, ld;         // size and leading dimension (multiple of 128) of the workspace matrices
+    int64_t off;           // element offset of the problem's slot 0 in the batch workspace
+    int64_t col_off;       // offset of the problem's column sums in the bounds scratch
+    int32_t tile;          // product tile edge: 64 or 32 (chosen by the tuner)
+    int32_t ntile;         // ceil(n / tile)
+};
+
+struct TileItem {          // one tile of one problem's product in a step
+    int32_t p;             // problem
+    int32_t t;             // linear index in the problem's upper triangle of tiles
+};
+
+// Batched product step: every listed tile of descs[p] (one descriptor per problem).
+// prec: CHEBDM_FP64 / FP32 / BF16X3 / BF16X6 (descs point to double or float GemmDescs).
+hipError_t launch_batch_gemm(int prec, const void* descs, const BatchGeom* geo, const TileItem* items, int nitems,
+                             int* counter, int grid, hipStream_t st);
+int batch_gemm_grid(int prec);   // resident 64-thread work-groups for the persistent step kernel
+
+struct BatchDims {         // shared sizes of a plan
+    int count, order, k, m, lmax;
+    int64_t nmax, ldmax, mcap;
+    int prec;
+};
+hipError_t launch_batch_zero(int* p, int n, hipStream_t st);
+hipError_t launch_batch_bounds(const BatchDims& d, const BatchProblem* tab, const BatchGeom* geo, double* colsum,
+                               DevScalars* s, hipStream_t st);
+hipError_t launch_batch_setup(const BatchDims& d, const BatchProblem* tab, const BatchGeom* geo, DevScalars* s,
+                              int64_t* mq, double tol, int max_iter, hipStream_t st);
+hipError_t launch_batch_shift(const BatchDims& d, const BatchProblem* tab, const BatchGeom* geo, const DevScalars* s,
+                              void* mats, hipStream_t st);
+hipError_t launch_batch_patch(const BatchDims& d, const BatchProblem* tab, void* final_descs, hipStream_t st);
+hipError_t launch_batch_moments(const BatchDims& d, const BatchGeom* geo, const void* mats, double* trb,
+                                double* partial, int gram_blocks, double* gram, double* tau, hipStream_t st);
+hipError_t launch_batch_bisect(const BatchDims& d, const double* tau, const int64_t* mq, double* w, double* x,
+                               DevScalars* s, hipStream_t st);
+hipError_t launch_batch_coeffs(const BatchDims& d, const int64_t* mq, const DevScalars* s, double* ftab, double* c,
+                               double* coef, hipStream_t st);
+hipError_t launch_batch_combine(const BatchDims& d, const BatchGeom* geo, const double* coef, void* mats,
+                                hipStream_t st);
+hipError_t launch_batch_finish(const BatchDims& d, const BatchProblem* tab, const BatchGeom* geo, DevScalars* s,
+                               double* mu, double* trD, hipStream_t st);
+
+}  // namespace chebdm

@@ -11,22 +11,13 @@
 // with q = n (2j+1) mod 4M, so every cosine is a correctly reduced cospi.
 #include <cmath>
 
+#include "cheb_dev.h"
 #include "internal.h"
 #include "reduce.h"
 
 namespace chebdm {
 
 namespace {
-
-__device__ inline double node_cos(int64_t q, int64_t M) {
-    // cos(pi q / (2M)); q / (2M) is exact because 2M is a power of two.
-    return cospi((double)q / (double)(2 * M));
-}
-
-__device__ inline double fermi_scaled(double x, double beta_s, double mu_s) {
-    // 1 / (1 + exp(beta'(x - mu~)))  (eq. "fermifunc" in scaled variables)
-    return 1.0 / (1.0 + exp(beta_s * (x - mu_s)));
-}
 
 __global__ void k_set_scalars(DevScalars* s, double emin, double emax, double beta, double mu,
                               int has_mu, double n_elec, double tol, int max_iter) {
@@ -192,11 +183,6 @@ __device__ double trace_at(double mu_s, const double* __restrict__ w, const doub
     double acc = 0.0;
     for (int64_t j = threadIdx.x; j < M; j += kBisectThreads) acc += fermi_scaled(x[j], beta_s, mu_s) * w[j];
     return block_sum<kBisectThreads>(acc, smem) / (double)M;
-}
-
-__device__ inline double ulp_spacing(double v) {
-    const double a = v != 0.0 ? fabs(v) : 1e-300;
-    return nextafter(a, INFINITY) - a;
 }
 
 __global__ void __launch_bounds__(kBisectThreads)

@@ -38,158 +38,11 @@
 //           float32 accumulation (lo*lo, ~2^-16 relative, is dropped).
 //   bf16x6  three-way split x = hi + mid + lo; the six products down to 2^-16
 //           relative (hh, hm, mh, hl, lh, mm) keep about float32 accuracy.
-#include "internal.h"
+#include "gemm_tile.h"
 
 namespace chebdm {
 
 namespace {
-
-typedef double f64x2 __attribute__((ext_vector_type(2)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-enum { P_F64 = 0, P_F32 = 1, P_BF16X3 = 2, P_BF16X6 = 3 };
-
-template <int P> struct Traits;
-template <> struct Traits<P_F64> {
-    using T = double;
-    using Acc = f64x4;
-    static constexpr int MK = 1;   // k per MFMA and lane
-};
-template <> struct Traits<P_F32> {
-    using T = float;
-    using Acc = f32x4;
-    static constexpr int MK = 1;
-};
-template <> struct Traits<P_BF16X3> {
-    using T = float;
-    using Acc = f32x4;
-    static constexpr int MK = 8;
-};
-template <> struct Traits<P_BF16X6> {
-    using T = float;
-    using Acc = f32x4;
-    static constexpr int MK = 8;
-};
-
-// KU consecutive k of one row per lane, loaded as 16-byte vectors.
-template <typename T, int KU>
-struct Frag {
-    T v[KU];
-};
-
-template <typename T, int KU>
-__device__ __forceinline__ void load_frag(Frag<T, KU>& f, const T* p) {
-    constexpr int PER = 16 / sizeof(T);
-    static_assert(KU % PER == 0, "KU must fill 16-byte loads");
-#pragma unroll
-    for (int c = 0; c < KU / PER; ++c) {
-        if constexpr (sizeof(T) == 8) {
-            const f64x2 x = *reinterpret_cast<const f64x2*>(p + c * PER);
-            f.v[c * 2] = x[0];
-            f.v[c * 2 + 1] = x[1];
-        } else {
-            const f32x4 x = *reinterpret_cast<const f32x4*>(p + c * PER);
-#pragma unroll
-            for (int t = 0; t < 4; ++t) f.v[c * 4 + t] = x[t];
-        }
-    }
-}
-
-__device__ __forceinline__ void split_bf16(const float* x, bf16x8& hi, bf16x8& lo) {
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const __bf16 h = (__bf16)x[t];
-        hi[t] = h;
-        lo[t] = (__bf16)(x[t] - (float)h);
-    }
-}
-
-__device__ __forceinline__ void split3_bf16(const float* x, bf16x8& hi, bf16x8& mid, bf16x8& lo) {
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const __bf16 h = (__bf16)x[t];
-        const float r = x[t] - (float)h;
-        const __bf16 m = (__bf16)r;
-        hi[t] = h;
-        mid[t] = m;
-        lo[t] = (__bf16)(r - (float)m);
-    }
-}
-
-template <int P, int KU, int FM, int FN>
-__device__ __forceinline__ void mma_chunk(typename Traits<P>::Acc (&acc)[FM][FN],
-                                          const Frag<typename Traits<P>::T, KU> (&a)[FM],
-                                          const Frag<typename Traits<P>::T, KU> (&b)[FN]) {
-    if constexpr (P == P_F64) {
-#pragma unroll
-        for (int s = 0; s < KU; ++s)
-#pragma unroll
-            for (int f = 0; f < FM; ++f)
-#pragma unroll
-                for (int g = 0; g < FN; ++g)
-                    acc[f][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[f].v[s], b[g].v[s], acc[f][g], 0, 0, 0);
-    } else if constexpr (P == P_F32) {
-#pragma unroll
-        for (int s = 0; s < KU; ++s)
-#pragma unroll
-            for (int f = 0; f < FM; ++f)
-#pragma unroll
-                for (int g = 0; g < FN; ++g)
-                    acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[f].v[s], b[g].v[s], acc[f][g], 0, 0, 0);
-    } else if constexpr (P == P_BF16X6) {
-        // x = hi + mid + lo; keep every term down to 2^-16 relative, smallest first
-#pragma unroll
-        for (int s = 0; s < KU / 8; ++s) {
-            bf16x8 ah[FM], am[FM], al[FM], bh[FN], bm[FN], bl[FN];
-#pragma unroll
-            for (int f = 0; f < FM; ++f) split3_bf16(&a[f].v[8 * s], ah[f], am[f], al[f]);
-#pragma unroll
-            for (int g = 0; g < FN; ++g) split3_bf16(&b[g].v[8 * s], bh[g], bm[g], bl[g]);
-#pragma unroll
-            for (int f = 0; f < FM; ++f)
-#pragma unroll
-                for (int g = 0; g < FN; ++g) {
-                    acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[f], bh[g], acc[f][g], 0, 0, 0);
-                    acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f], bl[g], acc[f][g], 0, 0, 0);
-                    acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[f], bm[g], acc[f][g], 0, 0, 0);
-                    acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[f], bh[g], acc[f][g], 0, 0, 0);
-                    acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f], bm[g], acc[f][g], 0, 0, 0);
-                    acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f], bh[g], acc[f][g], 0, 0, 0);
-                }
-        }
-    } else {
-#pragma unroll
-        for (int s = 0; s < KU / 8; ++s) {
-            bf16x8 ah[FM], al[FM], bh[FN], bl[FN];
-#pragma unroll
-            for (int f = 0; f < FM; ++f) split_bf16(&a[f].v[8 * s], ah[f], al[f]);
-#pragma unroll
-            for (int g = 0; g < FN; ++g) split_bf16(&b[g].v[8 * s], bh[g], bl[g]);
-#pragma unroll
-            for (int f = 0; f < FM; ++f)
-#pragma unroll
-                for (int g = 0; g < FN; ++g) {
-                    acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[f], bh[g], acc[f][g], 0, 0, 0);
-                    acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f], bl[g], acc[f][g], 0, 0, 0);
-                    acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f], bh[g], acc[f][g], 0, 0, 0);
-                }
-        }
-    }
-}
-
-// Tile (I, J), I <= J, of linear index t in the row-major upper triangle of a
-// T x T tile grid; row I starts at I*T - I*(I-1)/2.
-__device__ __forceinline__ void upper_tile(int t, int T, int& I, int& J) {
-    const double b = 2.0 * T + 1.0;
-    int i = (int)floor(0.5 * (b - sqrt(b * b - 8.0 * (double)t)));
-    if (i < 0) i = 0;
-    while (i > 0 && i * T - i * (i - 1) / 2 > t) --i;
-    while (i + 1 < T && (i + 1) * T - (i + 1) * i / 2 <= t) ++i;
-    I = i;
-    J = t - (i * T - i * (i - 1) / 2) + i;
-}
 
 // Work-group -> tile order.  Work-groups are dealt round-robin to the 8 XCDs
 // (each with its own L2); with XCD = 1 the linear id is permuted so that each
@@ -210,135 +63,16 @@ __device__ __forceinline__ void tile_of_block(int ntri, int& t, int& z) {
     (void)ntri;
 }
 
-// BM x BM workgroup tile, WGM x WGN wavefronts, each owning a (BM/WGM) x (BM/WGN) tile
-// made of 16 x 16 MFMA blocks; KU consecutive k per lane and chunk (chunk = 4 KU k).
-// blockIdx.x enumerates upper-triangle tiles, blockIdx.z the products of a grouped launch.
+// BM x BM workgroup tiles, blockIdx.x enumerating the upper triangle, blockIdx.z
+// the products of a grouped launch.
 template <int P, int BM, int WGM, int WGN, int KU, int XCD>
 __global__ void __launch_bounds__(64 * WGM * WGN)
 k_gemm(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, int64_t kpad, int ntile) {
-    using T = typename Traits<P>::T;
-    using Acc = typename Traits<P>::Acc;
-    constexpr int CH = 4 * KU;                 // k per chunk
-    constexpr int WTM = BM / WGM, WTN = BM / WGN;
-    constexpr int FM = WTM / 16, FN = WTN / 16;
-    static_assert(FM >= 1 && FN >= 1 && WTM % 16 == 0 && WTN % 16 == 0, "wave tile must hold whole MFMA blocks");
-    static_assert(KU % Traits<P>::MK == 0, "KU must be a multiple of the MFMA k per lane");
-
     int tlin, z;
     tile_of_block<XCD>(ntile * (ntile + 1) / 2, tlin, z);
-    const GemmDesc<T>& g = batch.d[z];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int wm = wave / WGN, wn = wave % WGN;
     int ti, tj;
     upper_tile(tlin, ntile, ti, tj);
-    const bool diag_tile = ti == tj;
-    const int64_t row0 = (int64_t)ti * BM + wm * WTM;
-    const int64_t col0 = (int64_t)tj * BM + wn * WTN;
-    const int lr = lane & 15, lq = lane >> 4;
-
-    const T* __restrict__ pa = g.A + (row0 + lr) * ld + lq * KU;
-    const T* __restrict__ pb = g.B + (col0 + lr) * ld + lq * KU;
-
-    Acc acc[FM][FN];
-#pragma unroll
-    for (int f = 0; f < FM; ++f)
-#pragma unroll
-        for (int q = 0; q < FN; ++q) acc[f][q] = Acc{};
-
-    Frag<T, KU> a0[FM], b0[FN], a1[FM], b1[FN];
-    auto load = [&](Frag<T, KU>(&fa)[FM], Frag<T, KU>(&fb)[FN], int64_t k) {
-#pragma unroll
-        for (int f = 0; f < FM; ++f) load_frag<T, KU>(fa[f], pa + (int64_t)f * 16 * ld + k);
-#pragma unroll
-        for (int q = 0; q < FN; ++q) load_frag<T, KU>(fb[q], pb + (int64_t)q * 16 * ld + k);
-    };
-
-    // Two register stages with no branch inside the loop: kpad is a multiple of
-    // 2 CH, and the loads past the end are clamped to the last chunks (their
-    // values are never used).  Straight-line code lets the compiler wait only
-    // for the chunk being consumed while the next one is in flight.
-    load(a0, b0, 0);
-    load(a1, b1, CH);
-    for (int64_t k0 = 0;;) {
-        mma_chunk<P, KU, FM, FN>(acc, a0, b0);
-        load(a0, b0, (k0 + 2 * CH < kpad) ? k0 + 2 * CH : kpad - 2 * CH);
-        mma_chunk<P, KU, FM, FN>(acc, a1, b1);
-        load(a1, b1, (k0 + 3 * CH < kpad) ? k0 + 3 * CH : kpad - CH);
-        k0 += 2 * CH;
-        if (k0 >= kpad) break;
-    }
-
-    // Output layout of a 16 x 16 block: lane (lr, lq) holds column lr and, in its
-    // r-th register, row 4*lq + r for the f32 and bf16 MFMAs but row lq + 4*r for
-    // v_mfma_f64_16x16x4f64 (checked on gfx950).
-    //
-    // C and E are workspace matrices (ld x ld, zero padded), so every tile
-    // position is in bounds: they are read in one unpredicated batch and only
-    // the stores are predicated.
-    const double alpha = g.alpha, beta = g.beta, gamma = g.gamma, delta = g.delta;
-    auto row_of = [&](int f, int r) -> int64_t {
-        return row0 + f * 16 + (P == P_F64 ? lq + 4 * r : lq * 4 + r);
-    };
-    double v[FM][FN][4];
-#pragma unroll
-    for (int f = 0; f < FM; ++f)
-#pragma unroll
-        for (int q = 0; q < FN; ++q)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) v[f][q][r] = alpha * (double)acc[f][q][r];
-    if (g.C) {
-        const T* __restrict__ C = g.C;
-        T cv[FM][FN][4];
-#pragma unroll
-        for (int f = 0; f < FM; ++f)
-#pragma unroll
-            for (int q = 0; q < FN; ++q)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) cv[f][q][r] = C[row_of(f, r) * ld + col0 + q * 16 + lr];
-#pragma unroll
-        for (int f = 0; f < FM; ++f)
-#pragma unroll
-            for (int q = 0; q < FN; ++q)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) v[f][q][r] += beta * (double)cv[f][q][r];
-    }
-    if (g.E) {
-        const T* __restrict__ E = g.E;
-        T ev[FM][FN][4];
-#pragma unroll
-        for (int f = 0; f < FM; ++f)
-#pragma unroll
-            for (int q = 0; q < FN; ++q)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) ev[f][q][r] = E[row_of(f, r) * ld + col0 + q * 16 + lr];
-#pragma unroll
-        for (int f = 0; f < FM; ++f)
-#pragma unroll
-            for (int q = 0; q < FN; ++q)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) v[f][q][r] += gamma * (double)ev[f][q][r];
-    }
-    const int64_t ldo = g.ld_out;
-#pragma unroll
-    for (int f = 0; f < FM; ++f)
-#pragma unroll
-        for (int q = 0; q < FN; ++q)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = row_of(f, r);
-                const int64_t col = col0 + q * 16 + lr;
-                if (row < n && col < n && !(diag_tile && row > col)) {
-                    const double x = v[f][q][r] + (row == col ? delta : 0.0);
-                    const int64_t o = row * ldo + col, om = col * ldo + row;
-                    if (g.out_f64) {
-                        static_cast<double*>(g.Out)[o] = x;
-                        if (row != col) static_cast<double*>(g.Out)[om] = x;
-                    } else {
-                        static_cast<T*>(g.Out)[o] = (T)x;
-                        if (row != col) static_cast<T*>(g.Out)[om] = (T)x;
-                    }
-                }
-            }
+    gemm_tile<P, BM, WGM, WGN, KU>(batch.d[z], n, ld, kpad, ti, tj);
 }
 
 template <int P, int BM, int WGM, int WGN, int KU, int XCD>
