@@ -101,6 +101,45 @@ def cpu_baseline(h_np, beta, n_elec, order, budget_s=10.0, max_reps=3):
                       f"(oracle route: LAPACK eigh of H, moments, bisection, Q p(lam) Q^T), {dt:.1f} s"}
 
 
+def batch_row(cd, handle, torch, prec="fp32", order=256, reps=3):
+    """Batched form: 512 Hamiltonians, n uniform on {96..1024}, beta on [30, 200], one graph per batch."""
+    import numpy as np
+
+    import synth
+
+    sizes, betas = synth.batch_problems(512, seed=3000)
+    log("batch512: generating 512 Hamiltonians")
+    Hs = [torch.from_numpy(synth.hamiltonian(int(n), "uniform", seed=3000 + i)[0]).to("cuda:0")
+          for i, n in enumerate(sizes)]
+    nes = [0.5 * n for n in sizes]
+    Ds = [torch.empty((int(n), int(n)), dtype=torch.float64, device="cuda:0") for n in sizes]
+    b = cd.Batch(handle, sizes, order, cd.make_opts(prec))
+    tune = b.tune()
+    log("batch512 tune: " + tune)
+    b.mu_search(Hs, betas, nes, Ds)                      # captures the graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        mu, _, status, iters, trace = b.mu_search(Hs, betas, nes, Ds)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    cd.chebdm_profile_enable(handle, True)
+    b.mu_search(Hs, betas, nes, Ds)                      # eager run with launch timing
+    prof = cd.chebdm_profile_read(handle)
+    cd.chebdm_profile_enable(handle, False)
+    info = b.info()
+    b.close()
+    r = roofline_of(prof, prec)
+    return {"workload": f"512 Hamiltonians, n uniform on {{96..1024}} step 32, beta on [30,200], N_e=n/2, "
+                        f"order {order}, {prec}, one graph per batch",
+            "batches_per_s": round(1.0 / dt, 3), "dm_per_s": round(512 / dt, 1), "ms_per_batch": round(1e3 * dt, 2),
+            "all_ok": bool(np.all(status == 0)), "products_per_problem": info["products_per_problem"],
+            "gemm_tflops": r["achieved"] if r else None, "gemm_frac_of_peak": r["frac"] if r else None,
+            "phases_ms_eager": {"gemm": round(prof["gemm_ms"], 2), "gram": round(prof["gram_ms"], 2),
+                                "combine": round(prof["combine_ms"], 2)},
+            "tuner": tune}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,6 +225,9 @@ def main():
                                                               rows.get("n4000_fp64", {}).get("dm_per_s"))
             row["speedup_vs_fp64"] = round(row["dm_per_s"] / base, 3) if base else None
         result["breakdown"] = rows
+
+    if not args.no_breakdown:
+        result["batch512"] = batch_row(cd, handle, torch)
 
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on host cores")

@@ -243,6 +243,61 @@ int chebdm_batch_info(chebdm_batch b, int32_t* k, int32_t* m, int32_t* products_
                       int64_t* tiles_per_step, double* flop_per_run);
 
 /*
+ * Moments-only runs: chebdm_batch_mu_search with dD == NULL (ldd ignored)
+ * stops after the chemical-potential search (bounds, baby steps, ladder and
+ * Gram moments, search); trace_out then receives the quadrature trace
+ * t(mu~) at the returned mu.  It is captured as a graph of its own.
+ *
+ * chebdm_batch_set_search: how the per-problem search on the trace
+ * function t(mu~) of Sec. 3 proceeds in later runs.
+ *   mode 0  bisection on [-1, 1] (the default; what chebdm_mu_search does);
+ *   mode 1  safeguarded Newton on [-1, 1] from mu~ = 0, with t' from the
+ *           same quadrature (a step leaving the bracket is a bisection step);
+ *   mode 2  learned start: the network (chebdm_mlp_*) with device weights dW
+ *           (float32, chebdm_mlp_num_params() of them, read at every run,
+ *           not copied; they must stay valid) maps the moments to a guess g;
+ *           if t(g - delta) < N_e < t(g + delta) the safeguarded Newton search
+ *           runs inside that bracket, otherwise plain bisection on [-1, 1]
+ *           (the fallback).  0 < delta <= 2.
+ *   Every mode ends on |t - N_e| < tol, a bracket under 4 ulp or max_iter.
+ *   Drops the captured graphs.  ERR_ARG on a bad mode, NULL dW or delta.
+ * chebdm_batch_stats: after a run, per problem (each output nullable, host,
+ *   count entries): evaluations of t (bracket checks included), whether the
+ *   learned bracket was taken (0/1), the scaled mu~ and beta' = beta a.
+ * chebdm_batch_features: after a run, writes the network inputs of every
+ *   problem to dfeat (device float32, count x 64 row-major): tau_1..tau_62
+ *   divided by n, N_e / n, log(beta') / 4 (moments past the order are 0).
+ */
+int chebdm_batch_set_search(chebdm_batch b, int32_t mode, const float* dW, double delta);
+int chebdm_batch_stats(chebdm_batch b, int32_t* evals, int32_t* learned, double* mu_s, double* beta_s);
+int chebdm_batch_features(chebdm_batch b, float* dfeat);
+
+/*
+ * The learned chemical-potential network (not part of the paper: a start
+ * guess for the search of Sec. 3).  y = w3 . relu(W2 relu(W1 x + b1) + b2) + b3
+ * with x in R^64, 256 units per hidden layer, float32.  Flat parameter
+ * vector (device, float32): W1 (256 x 64 row-major), b1 (256), W2 (256 x 256),
+ * b2 (256), w3 (256), b3 (1): chebdm_mlp_num_params() = 82689 floats.
+ * All run on the handle's stream; the handle keeps a workspace of
+ * 4 batch x 256 + 2 batch + 1 floats (grown on demand).
+ *
+ * chebdm_mlp_forward: dX (batch x 64), dY (batch).  Does not synchronise.
+ * chebdm_mlp_backward: loss = mean_b (y_b - dT[b])^2 and its gradient with
+ *   respect to every parameter into dGrad (same layout as dW, overwritten).
+ *   loss_out (host, nullable): if given, the call synchronises and stores
+ *   the loss.
+ * chebdm_mlp_adam: one Adam update (Kingma and Ba) of dW with moment buffers
+ *   dM, dV (zero before step 1), step >= 1, 0 <= beta1, beta2 < 1, lr > 0,
+ *   eps >= 0.  Does not synchronise.
+ */
+int chebdm_mlp_num_params(void);
+int chebdm_mlp_forward(chebdm_handle h, const float* dW, const float* dX, int32_t batch, float* dY);
+int chebdm_mlp_backward(chebdm_handle h, const float* dW, const float* dX, const float* dT,
+                        int32_t batch, float* dGrad, float* loss_out);
+int chebdm_mlp_adam(chebdm_handle h, float* dW, const float* dGrad, float* dM, float* dV,
+                    int32_t step, float lr, float beta1, float beta2, float eps);
+
+/*
  * Launch timing.  While enabled, the library records a HIP event pair on its
  * stream around every launch of the matrix-product kernel (one pair per
  * grouped launch or batched product step), of the block-sum pass and of the

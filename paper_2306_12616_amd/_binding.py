@@ -102,6 +102,19 @@ _SIGNATURES = {
     "chebdm_batch_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
+    "chebdm_batch_set_search": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_double]),
+    "chebdm_batch_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double)]),
+    "chebdm_batch_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "chebdm_mlp_num_params": (ctypes.c_int, []),
+    "chebdm_mlp_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                          ctypes.c_void_p]),
+    "chebdm_mlp_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
+    "chebdm_mlp_adam": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                                       ctypes.c_float, ctypes.c_float]),
     "chebdm_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "chebdm_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Profile)]),
 }
@@ -306,6 +319,8 @@ class Batch:
                                                   self.order, ctypes.byref(opts) if opts is not None else None,
                                                   int(max_quad), ctypes.byref(b)))
         self._b = b
+        self.search_mode = 0
+        self._weights = None
 
     def tune(self, cache_path: Optional[str] = None) -> str:
         buf = ctypes.create_string_buffer(1024)
@@ -320,7 +335,46 @@ class Batch:
         return {"k": k.value, "m": m.value, "products_per_problem": pp.value, "tiles_per_step": tiles.value,
                 "flop_per_run": flop.value}
 
+    SEARCH_MODES = {"bisection": 0, "newton": 1, "learned": 2}
+
+    def set_search(self, mode="bisection", weights=None, delta: float = 0.02):
+        """Search mode for later runs; ``weights`` (device float32, kept alive here) for "learned"."""
+        m = self.SEARCH_MODES[mode] if isinstance(mode, str) else int(mode)
+        ptr = None
+        if weights is not None:
+            if weights.dtype != _torch().float32 or not weights.is_contiguous() or \
+                    weights.numel() != chebdm_mlp_num_params():
+                raise ValueError("weights must be a contiguous float32 vector of chebdm_mlp_num_params() entries")
+            ptr = weights.data_ptr()
+        _check(load_library().chebdm_batch_set_search(self._b, m, ptr, float(delta)))
+        self._weights = weights
+        self.search_mode = m
+
+    def stats(self):
+        """Per problem: evaluations of t, learned bracket taken, mu~ and beta' of the last run."""
+        count = len(self.sizes)
+        ev, le = (ctypes.c_int32 * count)(), (ctypes.c_int32 * count)()
+        mus, bs = (ctypes.c_double * count)(), (ctypes.c_double * count)()
+        _check(load_library().chebdm_batch_stats(self._b, ev, le, mus, bs))
+        return (np.array(ev[:], dtype=np.int32), np.array(le[:], dtype=np.int32), np.array(mus[:]),
+                np.array(bs[:]))
+
+    def features(self, device="cuda"):
+        """Network inputs of the last run (count x 64, device float32)."""
+        torch = _torch()
+        out = torch.empty((len(self.sizes), 64), dtype=torch.float32, device=device)
+        _check(load_library().chebdm_batch_features(self._b, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def mu_only(self, Hs, betas, n_elecs, allow_errors: bool = False):
+        """Moments and mu search only (no density); returns (mu, status, iters, t(mu))."""
+        return self._run(Hs, betas, n_elecs, None, allow_errors, with_density=False)
+
     def mu_search(self, Hs, betas, n_elecs, Ds=None, allow_errors: bool = False):
+        mu, Ds, status, iters, trace = self._run(Hs, betas, n_elecs, Ds, allow_errors, with_density=True)
+        return mu, Ds, status, iters, trace
+
+    def _run(self, Hs, betas, n_elecs, Ds, allow_errors, with_density):
         import torch
 
         count = len(self.sizes)
@@ -333,15 +387,16 @@ class Batch:
                 raise ValueError("H size does not match the plan")
             hp.append(p.value)
             hl.append(ld)
-        if Ds is None:
-            Ds = [torch.empty((n, n), dtype=torch.float64, device=H.device) for H, n in zip(Hs, self.sizes)]
         dp, dl = [], []
-        for D, n in zip(Ds, self.sizes):
-            p, nn, ld = _matrix_args(D, "D")
-            if nn != n:
-                raise ValueError("D size does not match the plan")
-            dp.append(p.value)
-            dl.append(ld)
+        if with_density:
+            if Ds is None:
+                Ds = [torch.empty((n, n), dtype=torch.float64, device=H.device) for H, n in zip(Hs, self.sizes)]
+            for D, n in zip(Ds, self.sizes):
+                p, nn, ld = _matrix_args(D, "D")
+                if nn != n:
+                    raise ValueError("D size does not match the plan")
+                dp.append(p.value)
+                dl.append(ld)
         mu = (ctypes.c_double * count)()
         status = (ctypes.c_int32 * count)()
         iters = (ctypes.c_int32 * count)()
@@ -350,12 +405,14 @@ class Batch:
         rc = load_library().chebdm_batch_mu_search(self._b, _arr(ctypes.c_void_p, hp), _arr(ctypes.c_int64, hl),
                                                    _arr(ctypes.c_double, [float(v) for v in betas]),
                                                    _arr(ctypes.c_double, [float(v) for v in n_elecs]),
-                                                   _arr(ctypes.c_void_p, dp), _arr(ctypes.c_int64, dl), mu, status,
+                                                   _arr(ctypes.c_void_p, dp) if with_density else None,
+                                                   _arr(ctypes.c_int64, dl) if with_density else None, mu, status,
                                                    iters, trace)
         if rc < 0 and not allow_errors:
             _check(rc)
-        return (np.array(mu[:]), Ds, np.array(status[:], dtype=np.int32), np.array(iters[:], dtype=np.int32),
-                np.array(trace[:]))
+        out = (np.array(mu[:]), np.array(status[:], dtype=np.int32), np.array(iters[:], dtype=np.int32),
+               np.array(trace[:]))
+        return (out[0], Ds) + out[1:] if with_density else out
 
     def close(self):
         if getattr(self, "_b", None) is not None and self._b.value:
@@ -371,3 +428,58 @@ class Batch:
 
 def chebdm_batch_create(h: Handle, sizes, order: int, opts: Optional[Opts] = None, max_quad: int = 0) -> Batch:
     return Batch(h, sizes, order, opts, max_quad)
+
+
+# ---- the learned chemical-potential network --------------------------------------------------
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _f32_dev(t, name, numel=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must hold {numel} entries")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def chebdm_mlp_num_params() -> int:
+    return int(load_library().chebdm_mlp_num_params())
+
+
+def chebdm_mlp_forward(h: Handle, W, X):
+    """y = net(X) for X (batch x 64); returns a new float32 tensor of batch entries."""
+    torch = _torch()
+    if X.dim() != 2 or X.shape[1] != 64:
+        raise ValueError("X must be batch x 64")
+    Y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    _check(load_library().chebdm_mlp_forward(h.ptr, _f32_dev(W, "W", chebdm_mlp_num_params()), _f32_dev(X, "X"),
+                                             int(X.shape[0]), _f32_dev(Y, "Y")))
+    return Y
+
+
+def chebdm_mlp_backward(h: Handle, W, X, T, grad=None, want_loss: bool = True):
+    """(gradient of the mean squared error, loss or None); ``grad`` is reused when given."""
+    torch = _torch()
+    if X.dim() != 2 or X.shape[1] != 64 or T.numel() != X.shape[0]:
+        raise ValueError("X must be batch x 64 and T hold batch entries")
+    if grad is None:
+        grad = torch.empty_like(W)
+    loss = ctypes.c_float()
+    _check(load_library().chebdm_mlp_backward(h.ptr, _f32_dev(W, "W", chebdm_mlp_num_params()), _f32_dev(X, "X"),
+                                              _f32_dev(T, "T"), int(X.shape[0]),
+                                              _f32_dev(grad, "grad", chebdm_mlp_num_params()),
+                                              ctypes.byref(loss) if want_loss else None))
+    return grad, (loss.value if want_loss else None)
+
+
+def chebdm_mlp_adam(h: Handle, W, G, M, V, step: int, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+                    eps: float = 1e-8) -> None:
+    n = chebdm_mlp_num_params()
+    _check(load_library().chebdm_mlp_adam(h.ptr, _f32_dev(W, "W", n), _f32_dev(G, "G", n), _f32_dev(M, "M", n),
+                                          _f32_dev(V, "V", n), int(step), float(lr), float(beta1), float(beta2),
+                                          float(eps)))

@@ -482,6 +482,7 @@ int chebdm_destroy(chebdm_handle h) {
     }
     if (h->mats) (void)hipFree(h->mats);
     if (h->small) (void)hipFree(h->small);
+    if (h->mlp_work) (void)hipFree(h->mlp_work);
     if (h->h_scal) (void)hipHostFree(h->h_scal);
     delete h;
     return CHEBDM_OK;

@@ -69,9 +69,15 @@ struct chebdm_batch_ctx {
     BatchProblem* h_tab = nullptr;
     DevScalars* h_scal = nullptr;
     double *h_mu = nullptr, *h_trD = nullptr;
-    // graph
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // chemical-potential search: 0 bisection, 1 safeguarded Newton, 2 network guess + Newton
+    int search_mode = 0;
+    const float* mlp_w = nullptr;
+    double mlp_delta = 0.02;
+    float *feat = nullptr, *mu_hat = nullptr, *mlp_work = nullptr;
+    // graphs: [0] with the density, [1] moments and mu only
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    bool have_run = false;
 };
 
 namespace {
@@ -83,10 +89,12 @@ void* slot_ptr(chebdm_batch_ctx* b, int p, int64_t s) {
 }
 
 void drop_graph(chebdm_batch_ctx* b) {
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    b->exec = nullptr;
-    b->graph = nullptr;
+    for (int i = 0; i < 2; ++i) {
+        if (b->exec[i]) (void)hipGraphExecDestroy(b->exec[i]);
+        if (b->graph[i]) (void)hipGraphDestroy(b->graph[i]);
+        b->exec[i] = nullptr;
+        b->graph[i] = nullptr;
+    }
 }
 
 // Geometry (tile edges) and the shared item list for the current schedule.
@@ -181,10 +189,10 @@ int gemm_step(chebdm_batch_ctx* b, int s, hipStream_t st, bool prof) {
 
 // The whole batched hot path, enqueued on st (captured into the graph, or run
 // eagerly with launch timing when the handle's profiling is on).
-int enqueue(chebdm_batch_ctx* b, hipStream_t st, bool prof) {
+int enqueue(chebdm_batch_ctx* b, hipStream_t st, bool prof, bool with_density) {
     const BatchDims& d = b->d;
     HIP_TRY(launch_batch_zero(b->counters, b->steps, st));
-    HIP_TRY(launch_batch_patch(d, b->tab, const_cast<void*>(step_descs(b, b->steps - 1)), st));
+    if (with_density) HIP_TRY(launch_batch_patch(d, b->tab, const_cast<void*>(step_descs(b, b->steps - 1)), st));
     HIP_TRY(launch_batch_bounds(d, b->tab, b->geo, b->colsum, b->scal, st));
     HIP_TRY(launch_batch_setup(d, b->tab, b->geo, b->scal, b->mq, b->tol, b->max_iter, st));
     HIP_TRY(launch_batch_shift(d, b->tab, b->geo, b->scal, b->mats, st));
@@ -197,7 +205,15 @@ int enqueue(chebdm_batch_ctx* b, hipStream_t st, bool prof) {
     }
     HIP_TRY(launch_batch_moments(d, b->geo, b->mats, b->trb, b->partial, kGramBlocks, b->gram, b->tau, st));
     if (prof) CHECK(prof_end(b->h, ev));
-    HIP_TRY(launch_batch_bisect(d, b->tau, b->mq, b->w, b->x, b->scal, st));
+    if (b->search_mode == 2) {
+        HIP_TRY(launch_batch_features(d, b->geo, b->tau, b->scal, b->feat, st));
+        HIP_TRY(launch_mlp_forward(b->mlp_w, b->feat, d.count, b->mu_hat, b->mlp_work, st));
+    }
+    HIP_TRY(launch_batch_search(d, b->tau, b->mq, b->w, b->x, b->scal, b->search_mode, b->mu_hat, b->mlp_delta, st));
+    if (!with_density) {
+        HIP_TRY(launch_batch_finish(d, b->tab, b->geo, b->scal, b->mu, b->trD, 0, st));
+        return 0;
+    }
     HIP_TRY(launch_batch_coeffs(d, b->mq, b->scal, b->ftab, b->c, b->coef, st));
     if (prof) {
         double bytes = 0.0;
@@ -207,7 +223,7 @@ int enqueue(chebdm_batch_ctx* b, hipStream_t st, bool prof) {
     HIP_TRY(launch_batch_combine(d, b->geo, b->coef, b->mats, st));
     if (prof) CHECK(prof_end(b->h, ev));
     for (int s = b->steps_pre; s < b->steps; ++s) CHECK(gemm_step(b, s, st, prof));
-    HIP_TRY(launch_batch_finish(d, b->tab, b->geo, b->scal, b->mu, b->trD, st));
+    HIP_TRY(launch_batch_finish(d, b->tab, b->geo, b->scal, b->mu, b->trD, 1, st));
     return 0;
 }
 
@@ -353,6 +369,8 @@ int chebdm_batch_create(chebdm_handle h, int32_t count, const int64_t* n, int32_
     const size_t o_x = take(sizeof(double) * C * mcap), o_f = take(sizeof(double) * C * mcap);
     const size_t o_c = take(sizeof(double) * C * L1), o_coef = take(sizeof(double) * C * K * M);
     const size_t o_mu = take(sizeof(double) * C), o_trd = take(sizeof(double) * C);
+    const size_t o_feat = take(sizeof(float) * C * 64), o_muh = take(sizeof(float) * C);
+    const size_t o_mlpw = take(sizeof(float) * C * 512);
     if (hipMalloc(&b->dev, bytes) != hipSuccess) {
         b->dev = nullptr;
         (void)hipGetLastError();
@@ -377,6 +395,9 @@ int chebdm_batch_create(chebdm_handle h, int32_t count, const int64_t* n, int32_
     b->coef = (double*)(base + o_coef);
     b->mu = (double*)(base + o_mu);
     b->trD = (double*)(base + o_trd);
+    b->feat = (float*)(base + o_feat);
+    b->mu_hat = (float*)(base + o_muh);
+    b->mlp_work = (float*)(base + o_mlpw);
     const size_t hbytes = sizeof(BatchProblem) * C + sizeof(DevScalars) * C + 2 * sizeof(double) * C + 256;
     if (hipHostMalloc(&b->host, hbytes, hipHostMallocDefault) != hipSuccess) {
         b->host = nullptr;
@@ -480,27 +501,32 @@ int chebdm_batch_tune(chebdm_batch b, const char* cache_path, char* report, int3
 int chebdm_batch_mu_search(chebdm_batch b, const double* const* dH, const int64_t* ldh, const double* beta,
                            const double* n_elec, double* const* dD, const int64_t* ldd, double* mu_out,
                            int32_t* status_out, int32_t* iters_out, double* trace_out) {
-    if (!b || !dH || !ldh || !beta || !n_elec || !dD || !ldd || !mu_out)
+    if (!b || !dH || !ldh || !beta || !n_elec || !mu_out || (dD && !ldd))
         return fail(CHEBDM_ERR_ARG, "NULL argument");
     chebdm_handle h = b->h;
     HIP_TRY(hipSetDevice(h->device));
     const int count = b->d.count;
+    const bool with_density = dD != nullptr;
     for (int p = 0; p < count; ++p) {
-        if (!dH[p] || !dD[p]) return fail(CHEBDM_ERR_ARG, "NULL matrix in the batch");
-        if (ldh[p] < b->n[p] || ldd[p] < b->n[p]) return fail(CHEBDM_ERR_ARG, "leading dimension smaller than n");
-        b->h_tab[p] = BatchProblem{dH[p], dD[p], ldh[p], ldd[p], beta[p], n_elec[p]};
+        if (!dH[p] || (with_density && !dD[p])) return fail(CHEBDM_ERR_ARG, "NULL matrix in the batch");
+        if (ldh[p] < b->n[p] || (with_density && ldd[p] < b->n[p]))
+            return fail(CHEBDM_ERR_ARG, "leading dimension smaller than n");
+        b->h_tab[p] = BatchProblem{dH[p], with_density ? dD[p] : nullptr, ldh[p], with_density ? ldd[p] : 0,
+                                   beta[p], n_elec[p]};
     }
+    if (b->search_mode == 2 && !b->mlp_w) return fail(CHEBDM_ERR_ARG, "network search mode without weights");
+    const int gi = with_density ? 0 : 1;
     hipStream_t st;
     if (h->prof) {
         // eager run on the handle's stream with launch timing
         st = h->stream;
         HIP_TRY(hipMemcpyAsync(b->tab, b->h_tab, sizeof(BatchProblem) * count, hipMemcpyHostToDevice, st));
-        CHECK(enqueue(b, st, true));
+        CHECK(enqueue(b, st, true, with_density));
     } else {
         st = b->bs;
-        if (!b->exec) {
+        if (!b->exec[gi]) {
             HIP_TRY(hipStreamBeginCapture(b->bs, hipStreamCaptureModeThreadLocal));
-            const int rc = enqueue(b, b->bs, false);
+            const int rc = enqueue(b, b->bs, false, with_density);
             hipGraph_t g = nullptr;
             const hipError_t ec = hipStreamEndCapture(b->bs, &g);
             if (rc < 0) {
@@ -508,19 +534,20 @@ int chebdm_batch_mu_search(chebdm_batch b, const double* const* dH, const int64_
                 return rc;
             }
             HIP_TRY(ec);
-            b->graph = g;
-            HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+            b->graph[gi] = g;
+            HIP_TRY(hipGraphInstantiate(&b->exec[gi], b->graph[gi], nullptr, nullptr, 0));
         }
         // the caller's H was written on the handle's stream
         HIP_TRY(hipEventRecord(b->ready, h->stream));
         HIP_TRY(hipStreamWaitEvent(b->bs, b->ready, 0));
         HIP_TRY(hipMemcpyAsync(b->tab, b->h_tab, sizeof(BatchProblem) * count, hipMemcpyHostToDevice, b->bs));
-        HIP_TRY(hipGraphLaunch(b->exec, b->bs));
+        HIP_TRY(hipGraphLaunch(b->exec[gi], b->bs));
     }
     HIP_TRY(hipMemcpyAsync(b->h_scal, b->scal, sizeof(DevScalars) * count, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(b->h_mu, b->mu, sizeof(double) * count, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(b->h_trD, b->trD, sizeof(double) * count, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    b->have_run = true;
     int worst = CHEBDM_OK;
     for (int p = 0; p < count; ++p) {
         const int s = b->h_scal[p].status;
@@ -533,6 +560,40 @@ int chebdm_batch_mu_search(chebdm_batch b, const double* const* dH, const int64_
     }
     if (worst < 0) return fail(worst, "at least one problem of the batch failed (see status_out)");
     return worst;
+}
+
+int chebdm_batch_set_search(chebdm_batch b, int32_t mode, const float* dW, double delta) {
+    if (!b) return fail(CHEBDM_ERR_ARG, "batch is NULL");
+    if (mode < 0 || mode > 2) return fail(CHEBDM_ERR_ARG, "unknown search mode");
+    if (mode == 2 && (!dW || !(delta > 0.0) || !(delta <= 2.0)))
+        return fail(CHEBDM_ERR_ARG, "the network mode needs weights and 0 < delta <= 2");
+    b->search_mode = mode;
+    b->mlp_w = mode == 2 ? dW : nullptr;
+    b->mlp_delta = mode == 2 ? delta : 0.0;
+    drop_graph(b);
+    return CHEBDM_OK;
+}
+
+int chebdm_batch_stats(chebdm_batch b, int32_t* evals, int32_t* learned, double* mu_s, double* beta_s) {
+    if (!b) return fail(CHEBDM_ERR_ARG, "batch is NULL");
+    if (!b->have_run) return fail(CHEBDM_ERR_ARG, "no run yet");
+    for (int p = 0; p < b->d.count; ++p) {
+        if (evals) evals[p] = b->h_scal[p].evals;
+        if (learned) learned[p] = b->h_scal[p].learned;
+        if (mu_s) mu_s[p] = b->h_scal[p].mu_s;
+        if (beta_s) beta_s[p] = b->h_scal[p].beta_s;
+    }
+    return CHEBDM_OK;
+}
+
+int chebdm_batch_features(chebdm_batch b, float* dfeat) {
+    if (!b || !dfeat) return fail(CHEBDM_ERR_ARG, "NULL argument");
+    if (!b->have_run) return fail(CHEBDM_ERR_ARG, "no run yet");
+    HIP_TRY(hipSetDevice(b->h->device));
+    HIP_TRY(launch_batch_features(b->d, b->geo, b->tau, b->scal, b->feat, b->bs));
+    HIP_TRY(hipMemcpyAsync(dfeat, b->feat, sizeof(float) * 64 * (size_t)b->d.count, hipMemcpyDeviceToDevice, b->bs));
+    HIP_TRY(hipStreamSynchronize(b->bs));
+    return CHEBDM_OK;
 }
 
 int chebdm_batch_info(chebdm_batch b, int32_t* k, int32_t* m, int32_t* products_per_problem, int64_t* tiles_per_step,

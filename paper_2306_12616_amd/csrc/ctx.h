@@ -35,6 +35,9 @@ struct chebdm_ctx {
     bool prof = false;
     std::vector<Ev> ev;
     size_t ev_used = 0;
+    // activations of the chemical-potential network
+    float* mlp_work = nullptr;
+    int64_t mlp_work_floats = 0;
 };
 
 namespace chebdm {

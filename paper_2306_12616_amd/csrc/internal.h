@@ -25,6 +25,8 @@ struct DevScalars {
     int32_t status;       // CHEBDM_OK / WARN_NOCONV / ERR_BRACKET
     int32_t iters;        // bisection sweeps
     int32_t max_iter;
+    int32_t evals;        // evaluations of t(mu~) in the search (bracket checks included)
+    int32_t learned;      // 1: the network's bracket held; 0: plain search (or fallback)
 };
 
 constexpr int kMaxGroup = 32;   // GEMMs per grouped launch (one Algorithm-1 stage)
@@ -149,6 +151,24 @@ hipError_t launch_batch_coeffs(const BatchDims& d, const int64_t* mq, const DevS
 hipError_t launch_batch_combine(const BatchDims& d, const BatchGeom* geo, const double* coef, void* mats,
                                 hipStream_t st);
 hipError_t launch_batch_finish(const BatchDims& d, const BatchProblem* tab, const BatchGeom* geo, DevScalars* s,
-                               double* mu, double* trD, hipStream_t st);
+                               double* mu, double* trD, int with_density, hipStream_t st);
 
+}  // namespace chebdm
+
+// ---- learned chemical potential (k_mlp.hip): 64 -> 256 -> 256 -> 1, ReLU, float32
+namespace chebdm {
+int64_t mlp_nparams();
+// work: 4 * B * 256 + 2 * B + 1 floats for backward (2 * B * 256 for forward)
+hipError_t launch_mlp_forward(const float* w, const float* X, int Bn, float* y, float* work, hipStream_t st);
+hipError_t launch_mlp_backward(const float* w, const float* X, const float* t, int Bn, float* g, float* work,
+                               float* loss, hipStream_t st);
+hipError_t launch_mlp_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                           float eps, float bc1, float bc2, hipStream_t st);
+// batched features for the network (k_batch.hip) and the search modes:
+// mode 0 bisection on [-1, 1]; 1 safeguarded Newton on [-1, 1]; 2 network guess mu_hat:
+// verify [mu_hat - delta, mu_hat + delta], Newton inside it, else bisection on [-1, 1]
+hipError_t launch_batch_features(const BatchDims& d, const BatchGeom* geo, const double* tau, const DevScalars* s,
+                                 float* feat, hipStream_t st);
+hipError_t launch_batch_search(const BatchDims& d, const double* tau, const int64_t* mq, double* w, double* x,
+                               DevScalars* s, int mode, const float* mu_hat, double delta, hipStream_t st);
 }  // namespace chebdm

@@ -211,7 +211,29 @@ k_batch_gram(const BatchGeom* __restrict__ geo, const T* __restrict__ mats, int 
     for (int f = 0; f < FM; ++f)
 #pragma unroll
         for (int g = 0; g < FN; ++g) acc[f][g] = f64x4{0.0, 0.0, 0.0, 0.0};
-    for (int64_t c = c0; c < c1; ++c) {
+    // four chunks per iteration: all their loads are issued before the first MFMA
+    constexpr int U = 4;
+    int64_t c = c0;
+    for (; c + U <= c1; c += U) {
+        f64x2b a[U][FM], b[U][FN];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int f = 0; f < FM; ++f) a[u][f] = ld2(pa[f] + (c + u) * 8);
+#pragma unroll
+            for (int g = 0; g < FN; ++g) b[u][g] = ld2(pb[g] + (c + u) * 8);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int f = 0; f < FM; ++f)
+#pragma unroll
+                    for (int g = 0; g < FN; ++g)
+                        acc[f][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][f][s], b[u][g][s], acc[f][g], 0, 0, 0);
+    }
+    for (; c < c1; ++c) {
         const int64_t e = c * 8;
         f64x2b a[FM], b[FN];
 #pragma unroll
@@ -297,18 +319,29 @@ k_batch_dct3(const double* __restrict__ tau, int order, const int64_t* __restric
 
 constexpr int kBisect = 512;
 
-__device__ double batch_trace_at(double mu_s, const double* __restrict__ w, const double* __restrict__ x, int64_t M,
-                                 double beta_s, double* smem) {
-    double acc = 0.0;
-    for (int64_t j = threadIdx.x; j < M; j += kBisect) acc += fermi_scaled(x[j], beta_s, mu_s) * w[j];
-    return block_sum<kBisect>(acc, smem) / (double)M;
+// t(mu~) = (1/M) sum_j f(x_j; mu~) w_j and its derivative, in one pass
+__device__ void batch_trace2(double mu_s, const double* __restrict__ w, const double* __restrict__ x, int64_t M,
+                             double beta_s, double* smem, double& t, double& dt) {
+    double acc = 0.0, accd = 0.0;
+    for (int64_t j = threadIdx.x; j < M; j += kBisect) {
+        const double f = fermi_scaled(x[j], beta_s, mu_s);
+        acc += f * w[j];
+        accd += beta_s * f * (1.0 - f) * w[j];
+    }
+    t = block_sum<kBisect>(acc, smem) / (double)M;
+    dt = block_sum<kBisect>(accd, smem) / (double)M;
 }
 
-// same rule as the single-problem bisection: bracket [-1, 1], midpoint, stop at
-// |t - N_e| < tol, at a bracket below 4 ulp, or after max_iter sweeps
+// Chemical-potential search, one work-group per problem.
+//   mode 0: bisection on [-1, 1] (midpoint rule, same stopping rule as the single-problem search)
+//   mode 1: safeguarded Newton on [-1, 1] from mu~ = 0 (a step leaving the bracket is a bisection step)
+//   mode 2: network guess g: if t(g - delta) < N_e < t(g + delta), safeguarded Newton from g inside that
+//           bracket; otherwise plain bisection on [-1, 1] (the fallback)
+// Every mode stops at |t - N_e| < tol, at a bracket narrower than 4 ulp, or after max_iter steps.
 __global__ void __launch_bounds__(kBisect)
-k_batch_bisect(const int64_t* __restrict__ mq, int64_t mcap, const double* __restrict__ w,
-               const double* __restrict__ x, DevScalars* s) {
+k_batch_search(const int64_t* __restrict__ mq, int64_t mcap, const double* __restrict__ w,
+               const double* __restrict__ x, DevScalars* s, int mode, const float* __restrict__ mu_hat,
+               double delta) {
     __shared__ double smem[kBisect / 64];
     const int p = blockIdx.x;
     DevScalars& d = s[p];
@@ -318,18 +351,47 @@ k_batch_bisect(const int64_t* __restrict__ mq, int64_t mcap, const double* __res
     const double* xp = x + p * mcap;
     const double beta_s = d.beta_s, ne = d.n_elec, tol = d.tol;
     const int max_iter = d.max_iter;
-    double lo = -1.0, hi = 1.0;
-    const double t_lo = batch_trace_at(lo, wp, xp, M, beta_s, smem);
-    const double t_hi = batch_trace_at(hi, wp, xp, M, beta_s, smem);
-    int status = CHEBDM_WARN_NOCONV, iters = 0;
+    int evals = 0, learned = 0, iters = 0, status = CHEBDM_WARN_NOCONV;
+    double lo = -1.0, hi = 1.0, mu0 = 0.0, t_lo, t_hi, dtmp;
+    bool bracketed = false;
+    if (mode == 2) {
+        double g = (double)mu_hat[p];
+        if (!isfinite(g)) g = 0.0;
+        g = fmin(fmax(g, -1.0), 1.0);
+        lo = fmax(-1.0, g - delta);
+        hi = fmin(1.0, g + delta);
+        batch_trace2(lo, wp, xp, M, beta_s, smem, t_lo, dtmp);
+        batch_trace2(hi, wp, xp, M, beta_s, smem, t_hi, dtmp);
+        evals += 2;
+        if (t_lo < ne && ne < t_hi) {
+            bracketed = true;
+            learned = 1;
+            mu0 = g;
+        }
+    }
     double mid = 0.0, t_mid = NAN;
-    if (!(t_lo < ne && ne < t_hi)) {
-        status = CHEBDM_ERR_BRACKET;
-        mid = NAN;
-    } else {
+    if (!bracketed) {
+        lo = -1.0;
+        hi = 1.0;
+        batch_trace2(lo, wp, xp, M, beta_s, smem, t_lo, dtmp);
+        batch_trace2(hi, wp, xp, M, beta_s, smem, t_hi, dtmp);
+        evals += 2;
+        if (!(t_lo < ne && ne < t_hi)) {
+            if (threadIdx.x == 0) {
+                d.mu_s = NAN;
+                d.trace = NAN;
+                d.iters = 0;
+                d.evals = evals;
+                d.learned = 0;
+                d.status = CHEBDM_ERR_BRACKET;
+            }
+            return;
+        }
+    }
+    if (mode == 0 || (mode == 2 && !learned)) {
         for (int it = 1; it <= max_iter; ++it) {
             mid = 0.5 * (lo + hi);
-            t_mid = batch_trace_at(mid, wp, xp, M, beta_s, smem);
+            batch_trace2(mid, wp, xp, M, beta_s, smem, t_mid, dtmp);
             iters = it;
             if (fabs(t_mid - ne) < tol) {
                 status = CHEBDM_OK;
@@ -339,15 +401,47 @@ k_batch_bisect(const int64_t* __restrict__ mq, int64_t mcap, const double* __res
             else hi = mid;
             if (hi - lo < 4.0 * ulp_spacing(mid)) break;
         }
+    } else {
+        mid = mu0;
+        for (int it = 1; it <= max_iter; ++it) {
+            double dt;
+            batch_trace2(mid, wp, xp, M, beta_s, smem, t_mid, dt);
+            iters = it;
+            if (fabs(t_mid - ne) < tol) {
+                status = CHEBDM_OK;
+                break;
+            }
+            if (t_mid < ne) lo = mid;
+            else hi = mid;
+            double cand = mid - (t_mid - ne) / dt;
+            if (!(dt > 0.0) || !(cand > lo && cand < hi)) cand = 0.5 * (lo + hi);
+            if (hi - lo < 4.0 * ulp_spacing(mid)) break;
+            mid = cand;
+        }
     }
+    evals += iters;
     if (threadIdx.x == 0) {
         d.mu_s = mid;
         d.trace = t_mid;
         d.iters = iters;
+        d.evals = evals;
+        d.learned = learned;
         d.status = status;
         d.lo = lo;
         d.hi = hi;
     }
+}
+
+// network inputs of problem p: tau_1..tau_62 / n, N_e / n, log(beta') / 4
+__global__ void k_batch_features(const BatchGeom* __restrict__ geo, const double* __restrict__ tau, int order,
+                                 const DevScalars* __restrict__ s, float* __restrict__ feat) {
+    const int p = blockIdx.x, j = threadIdx.x;
+    const double n = (double)geo[p].n;
+    double v;
+    if (j < 62) v = (j + 1 <= order) ? tau[(int64_t)p * (order + 1) + j + 1] / n : 0.0;
+    else if (j == 62) v = s[p].n_elec / n;
+    else v = log(s[p].beta_s > 0.0 ? s[p].beta_s : 1.0) / 4.0;
+    feat[(int64_t)p * 64 + j] = (float)v;
 }
 
 // ---- coefficients at the found mu~ and the composition-form block coefficients
@@ -401,33 +495,53 @@ k_batch_cform(const double* __restrict__ c, int order, int k, int m, double* __r
     for (int idx = tid; idx < k * m; idx += 64) coef[(int64_t)p * k * m + idx] = e[idx / k][idx % k];
 }
 
-// ---- block sums R_l = sum_i e_{l,i} T_i (T_0 = I), all l of a problem in one pass
+// ---- block sums R_l = sum_i e_{l,i} T_i (T_0 = I), all l of a problem in one pass,
+// 16-byte vectors along full padded rows (zero padding in, zero padding out)
+template <typename T> struct BVec;
+template <> struct BVec<double> { typedef double V __attribute__((ext_vector_type(2))); static constexpr int W = 2; };
+template <> struct BVec<float> { typedef float V __attribute__((ext_vector_type(4))); static constexpr int W = 4; };
+
 template <typename T, int MB>
 __global__ void __launch_bounds__(256)
 k_batch_combine(const BatchGeom* __restrict__ geo, const double* __restrict__ coef, int k, int m, int l0,
                 T* __restrict__ mats) {
+    using V = typename BVec<T>::V;
+    constexpr int W = BVec<T>::W;
     const int p = blockIdx.z;
     const int64_t n = geo[p].n, ld = geo[p].ld, stride = ld * ld;
     const int64_t row = blockIdx.y;
-    const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t col = ((int64_t)blockIdx.x * 256 + threadIdx.x) * W;
     if (row >= n || col >= ld) return;
     const T* tb = mats + geo[p].off;
     T* rb = mats + geo[p].off + (int64_t)k * stride;
     const double* cf = coef + (int64_t)p * k * m;
     const int lcount = (m - l0) < MB ? (m - l0) : MB;
     const int64_t off = row * ld + col;
-    double acc[MB];
+    double acc[MB][W];
 #pragma unroll
-    for (int l = 0; l < MB; ++l) acc[l] = (l < lcount && col == row) ? cf[(int64_t)(l0 + l) * k] : 0.0;
+    for (int l = 0; l < MB; ++l) {
+        const double c0 = l < lcount ? cf[(int64_t)(l0 + l) * k] : 0.0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) acc[l][w] = (col + w == row) ? c0 : 0.0;
+    }
     for (int i = 1; i < k; ++i) {
-        const double t = (double)tb[(int64_t)(i - 1) * stride + off];
+        const V t = *reinterpret_cast<const V*>(tb + (int64_t)(i - 1) * stride + off);
 #pragma unroll
-        for (int l = 0; l < MB; ++l)
-            if (l < lcount) acc[l] += cf[(int64_t)(l0 + l) * k + i] * t;
+        for (int l = 0; l < MB; ++l) {
+            const double c = l < lcount ? cf[(int64_t)(l0 + l) * k + i] : 0.0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) acc[l][w] += c * (double)t[w];
+        }
     }
 #pragma unroll
-    for (int l = 0; l < MB; ++l)
-        if (l < lcount) rb[(int64_t)(l0 + l) * stride + off] = (T)acc[l];
+    for (int l = 0; l < MB; ++l) {
+        if (l < lcount) {
+            V o;
+#pragma unroll
+            for (int w = 0; w < W; ++w) o[w] = (T)acc[l][w];
+            *reinterpret_cast<V*>(rb + (int64_t)(l0 + l) * stride + off) = o;
+        }
+    }
 }
 
 // ---- results: tr D, mu, and D = (N_e/n) I for a scalar H
@@ -443,15 +557,19 @@ k_batch_scalar_fill(const BatchProblem* __restrict__ tab, const BatchGeom* __res
 
 __global__ void __launch_bounds__(256)
 k_batch_finish(const BatchProblem* __restrict__ tab, const BatchGeom* __restrict__ geo, DevScalars* s,
-               double* __restrict__ mu, double* __restrict__ trD) {
+               double* __restrict__ mu, double* __restrict__ trD, int with_density) {
     __shared__ double smem[4];
     const int p = blockIdx.x;
     const int64_t n = geo[p].n;
-    const double* D = tab[p].D;
-    const int64_t ldd = tab[p].ldd;
     double acc = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 256) acc += D[i * ldd + i];
-    acc = block_sum<256>(acc, smem);
+    if (with_density) {
+        const double* D = tab[p].D;
+        const int64_t ldd = tab[p].ldd;
+        for (int64_t i = threadIdx.x; i < n; i += 256) acc += D[i * ldd + i];
+        acc = block_sum<256>(acc, smem);
+    } else {
+        acc = s[p].status == 2 ? s[p].n_elec : s[p].trace;   // t(mu~) of the search
+    }
     if (threadIdx.x == 0) {
         trD[p] = acc;
         DevScalars& d = s[p];
@@ -468,7 +586,8 @@ k_batch_finish(const BatchProblem* __restrict__ tab, const BatchGeom* __restrict
 
 template <typename T>
 hipError_t combine_all(const BatchDims& d, const BatchGeom* geo, const double* coef, T* mats, hipStream_t st) {
-    dim3 grid((unsigned)((d.ldmax + 255) / 256), (unsigned)d.nmax, (unsigned)d.count);
+    const int64_t per = 256 * BVec<T>::W;
+    dim3 grid((unsigned)((d.ldmax + per - 1) / per), (unsigned)d.nmax, (unsigned)d.count);
     for (int l0 = 0; l0 < d.m; l0 += 24) {
         const int cnt = (d.m - l0) < 24 ? (d.m - l0) : 24;
         if (cnt <= 8)
@@ -598,10 +717,21 @@ hipError_t launch_batch_moments(const BatchDims& d, const BatchGeom* geo, const 
 
 hipError_t launch_batch_bisect(const BatchDims& d, const double* tau, const int64_t* mq, double* w, double* x,
                                DevScalars* s, hipStream_t st) {
+    return launch_batch_search(d, tau, mq, w, x, s, 0, nullptr, 0.0, st);
+}
+
+hipError_t launch_batch_search(const BatchDims& d, const double* tau, const int64_t* mq, double* w, double* x,
+                               DevScalars* s, int mode, const float* mu_hat, double delta, hipStream_t st) {
     hipLaunchKernelGGL(k_batch_dct3, dim3((unsigned)((d.mcap + 255) / 256), (unsigned)d.count), dim3(256),
                        sizeof(double) * (size_t)(d.order + 1), st, tau, d.order, mq, d.mcap, w, x);
-    hipLaunchKernelGGL(k_batch_bisect, dim3((unsigned)d.count), dim3(kBisect), 0, st, mq, d.mcap, (const double*)w,
-                       (const double*)x, s);
+    hipLaunchKernelGGL(k_batch_search, dim3((unsigned)d.count), dim3(kBisect), 0, st, mq, d.mcap, (const double*)w,
+                       (const double*)x, s, mode, mu_hat, delta);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_features(const BatchDims& d, const BatchGeom* geo, const double* tau, const DevScalars* s,
+                                 float* feat, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_features, dim3((unsigned)d.count), dim3(64), 0, st, geo, tau, d.order, s, feat);
     return hipGetLastError();
 }
 
@@ -623,10 +753,12 @@ hipError_t launch_batch_combine(const BatchDims& d, const BatchGeom* geo, const 
 }
 
 hipError_t launch_batch_finish(const BatchDims& d, const BatchProblem* tab, const BatchGeom* geo, DevScalars* s,
-                               double* mu, double* trD, hipStream_t st) {
-    hipLaunchKernelGGL(k_batch_scalar_fill, dim3((unsigned)((d.nmax + 255) / 256), (unsigned)d.nmax, (unsigned)d.count),
-                       dim3(256), 0, st, tab, geo, (const DevScalars*)s);
-    hipLaunchKernelGGL(k_batch_finish, dim3((unsigned)d.count), dim3(256), 0, st, tab, geo, s, mu, trD);
+                               double* mu, double* trD, int with_density, hipStream_t st) {
+    if (with_density)
+        hipLaunchKernelGGL(k_batch_scalar_fill, dim3((unsigned)((d.nmax + 255) / 256), (unsigned)d.nmax,
+                                                     (unsigned)d.count),
+                           dim3(256), 0, st, tab, geo, (const DevScalars*)s);
+    hipLaunchKernelGGL(k_batch_finish, dim3((unsigned)d.count), dim3(256), 0, st, tab, geo, s, mu, trD, with_density);
     return hipGetLastError();
 }
 

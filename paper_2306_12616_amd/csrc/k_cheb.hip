@@ -216,6 +216,8 @@ k_bisect(const double* __restrict__ w, const double* __restrict__ x, int64_t M, 
         s->mu_s = mid;
         s->trace = t_mid;
         s->iters = iters;
+        s->evals = iters + 2;
+        s->learned = 0;
         s->status = status;
         s->lo = lo;
         s->hi = hi;

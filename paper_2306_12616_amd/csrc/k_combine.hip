@@ -114,7 +114,29 @@ k_gram_partial(const PtrList<T> lm, int nl, const PtrList<T> tm, int nt, int64_t
 #pragma unroll
         for (int g = 0; g < FN; ++g) acc[f][g] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-    for (int64_t c = c_begin; c < c_end; ++c) {
+    // four chunks per iteration: all their loads are issued before the first MFMA
+    constexpr int U = 4;
+    int64_t c = c_begin;
+    for (; c + U <= c_end; c += U) {
+        f64x2 a[U][FM], b[U][FN];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int f = 0; f < FM; ++f) a[u][f] = load2(pa[f] + (c + u) * CH);
+#pragma unroll
+            for (int g = 0; g < FN; ++g) b[u][g] = load2(pb[g] + (c + u) * CH);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int f = 0; f < FM; ++f)
+#pragma unroll
+                    for (int g = 0; g < FN; ++g)
+                        acc[f][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][f][s], b[u][g][s], acc[f][g], 0, 0, 0);
+    }
+    for (; c < c_end; ++c) {
         const int64_t e = c * CH;
         f64x2 a[FM], b[FN];
 #pragma unroll

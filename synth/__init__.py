@@ -84,3 +84,68 @@ def batch_problems(count: int, seed: int = 3000, n_lo: int = 96, n_hi: int = 102
     sizes = rng.integers(0, (n_hi - n_lo) // step + 1, size=count) * step + n_lo
     betas = rng.uniform(beta_lo, beta_hi, size=count)
     return sizes.astype(np.int64), betas
+
+
+def hamiltonians_torch(sizes, law: str = "uniform", seed: int = 0, device="cuda"):
+    """Many Hamiltonians assembled on ``device`` with torch (same recipe, faster at scale).
+
+    The eigenvalues come from numpy's PCG64 (``seed``), in the order of
+    ``sizes``; the Gaussian matrices from a torch generator on ``device``
+    seeded with ``seed``, drawn size group by size group in increasing n.
+    Q = qr(G) with the signs of diag(R) folded in, H = (Q * lam) Q^T in
+    float64, symmetrised exactly.  Returns a list of ``(H, lam)`` with H a
+    contiguous float64 device tensor and lam a numpy array.
+    """
+    import torch
+
+    sizes = [int(n) for n in sizes]
+    rng = np.random.default_rng(seed)
+    lams = [eigenvalues(law, n, rng) for n in sizes]
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    out = [None] * len(sizes)
+    for n in sorted(set(sizes)):
+        idx = [i for i, v in enumerate(sizes) if v == n]
+        g = torch.randn((len(idx), n, n), generator=gen, device=device, dtype=torch.float64)
+        q, r = torch.linalg.qr(g)
+        del g
+        q = q * torch.sign(torch.diagonal(r, dim1=-2, dim2=-1)).unsqueeze(-2)
+        del r
+        lam = torch.from_numpy(np.stack([lams[i] for i in idx])).to(device)
+        h = torch.matmul(q * lam.unsqueeze(-2), q.transpose(-1, -2).contiguous())
+        h = 0.5 * (h + h.transpose(-1, -2))
+        for j, i in enumerate(idx):
+            out[i] = (h[j].contiguous(), lams[i])
+        del q, h, lam
+    return out
+
+
+def mu_problems(sizes, seed: int, device="cuda"):
+    """Problems of the learned-mu workload for the given sizes.
+
+    Per problem: eigenvalue law uniform over ``LAWS``, beta ~ U[30, 200],
+    electron fraction f ~ U[0.3, 0.7] with N_e = round(f n) + 1/2.  The
+    Hamiltonians come from :func:`hamiltonians_torch` (one seed per law).
+    Returns ``(Hs, lams, betas, n_elecs)``.
+    """
+    sizes = [int(n) for n in sizes]
+    count = len(sizes)
+    rng = np.random.default_rng(seed)
+    law_of = rng.integers(0, len(LAWS), size=count)
+    betas = rng.uniform(30.0, 200.0, size=count)
+    frac = rng.uniform(0.3, 0.7, size=count)
+    n_elecs = [float(np.round(f * n)) + 0.5 for f, n in zip(frac, sizes)]
+    Hs, lams = [None] * count, [None] * count
+    for li, law in enumerate(LAWS):
+        idx = [i for i in range(count) if law_of[i] == li]
+        if not idx:
+            continue
+        made = hamiltonians_torch([sizes[i] for i in idx], law, seed=8 * seed + li, device=device)
+        for i, (h, lam) in zip(idx, made):
+            Hs[i], lams[i] = h, lam
+    return Hs, lams, betas, n_elecs
+
+
+def mu_training_sizes(count: int, seed: int = 100):
+    """Training sizes of the learned-mu workload: n ~ U{64, 80, ..., 512}."""
+    return 64 + 16 * np.random.default_rng(seed).integers(0, 29, size=count)
