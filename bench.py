@@ -108,9 +108,8 @@ def batch_row(cd, handle, torch, prec="fp32", order=256, reps=3):
     import synth
 
     sizes, betas = synth.batch_problems(512, seed=3000)
-    log("batch512: generating 512 Hamiltonians")
-    Hs = [torch.from_numpy(synth.hamiltonian(int(n), "uniform", seed=3000 + i)[0]).to("cuda:0")
-          for i, n in enumerate(sizes)]
+    log("batch512: generating 512 Hamiltonians on the device")
+    Hs = [h for h, _ in synth.hamiltonians_torch(sizes, "uniform", seed=3000, device="cuda:0")]
     nes = [0.5 * n for n in sizes]
     Ds = [torch.empty((int(n), int(n)), dtype=torch.float64, device="cuda:0") for n in sizes]
     b = cd.Batch(handle, sizes, order, cd.make_opts(prec))
@@ -138,6 +137,64 @@ def batch_row(cd, handle, torch, prec="fp32", order=256, reps=3):
             "phases_ms_eager": {"gemm": round(prof["gemm_ms"], 2), "gram": round(prof["gram_ms"], 2),
                                 "combine": round(prof["combine_ms"], 2)},
             "tuner": tune}
+
+
+def learned_row(cd, handle, torch, order=256, chunks=20, chunk=1024, eval_count=1024, eval_n=500, epochs=40):
+    """Learned mu start: train on method-generated data, then compare search modes on 1024 x N=500."""
+    import numpy as np
+
+    import synth
+    from paper_2306_12616_amd.learned_mu import MuNet, collect_samples, delta_from_residuals, search_report
+
+    t0 = time.perf_counter()
+    sizes0 = synth.mu_training_sizes(chunk)
+    plan = cd.Batch(handle, sizes0, order)
+
+    def draw(c):
+        Hs, _, betas, nes = synth.mu_problems(sizes0, seed=200 + c, device="cuda:0")
+        return Hs, betas, nes
+
+    X, T = collect_samples(plan, draw, chunks, log=lambda m: log("learned: " + m))
+    plan.close()
+    t_data = time.perf_counter() - t0
+    nval = 1024
+    net = MuNet(handle, seed=0)
+    t1 = time.perf_counter()
+    net.train(X[nval:], T[nval:], epochs=epochs, batch=256, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    res = (net.predict(X[:nval]) - T[:nval]).cpu().numpy()
+    delta = delta_from_residuals(res)
+    log(f"learned: {X.shape[0]} samples in {t_data:.1f} s, trained in {t_train:.1f} s, "
+        f"validation rms {np.sqrt(np.mean(res ** 2)):.2e}, delta {delta:.2e}")
+    Hs, _, betas, nes = synth.mu_problems([eval_n] * eval_count, seed=7, device="cuda:0")
+    ev = cd.Batch(handle, [eval_n] * eval_count, order)
+    modes = {}
+    for mode in ("bisection", "newton", "learned"):
+        if mode == "learned":
+            ev.set_search(mode, net.W, delta)
+        else:
+            ev.set_search(mode)
+        ev.mu_only(Hs, betas, nes, allow_errors=True)        # capture
+        cd.chebdm_profile_enable(handle, True)
+        ev.mu_only(Hs, betas, nes, allow_errors=True)        # eager, launch-timed
+        cd.chebdm_profile_read(handle)
+        cd.chebdm_profile_enable(handle, False)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        mu, status, iters, t = ev.mu_only(Hs, betas, nes, allow_errors=True)
+        torch.cuda.synchronize()
+        row = search_report(ev, status, iters, t, nes)
+        row["ms_per_batch_mu_only"] = round(1e3 * (time.perf_counter() - ta), 2)
+        modes[mode] = row
+        log(f"learned: {mode} {row}")
+    ev.close()
+    return {"workload": f"train: {X.shape[0]} problems (n on {{64..512}} step 16, N_e/n on [0.3,0.7], beta on "
+                        f"[30,200], three spectrum laws, order {order}, bisection targets); evaluate: "
+                        f"{eval_count} x n={eval_n}",
+            "train_samples": int(X.shape[0] - nval), "data_s": round(t_data, 1), "train_s": round(t_train, 1),
+            "epochs": epochs, "validation_rms_mu_scaled": float(np.sqrt(np.mean(res ** 2))), "delta": delta,
+            "modes": modes}
 
 
 def main():
@@ -228,6 +285,7 @@ def main():
 
     if not args.no_breakdown:
         result["batch512"] = batch_row(cd, handle, torch)
+        result["learned_mu"] = learned_row(cd, handle, torch)
 
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on host cores")

@@ -156,8 +156,12 @@ __device__ __forceinline__ void upper_tile(int t, int T, int& I, int& J) {
 }
 
 // One BM x BM tile (ti, tj), ti <= tj, of the symmetric product g, computed by
-// WGM x WGN wavefronts of the calling work-group (each (BM/WGM) x (BM/WGN)).
-template <int P, int BM, int WGM, int WGN, int KU>
+// WGM x WGN x SK wavefronts of the calling work-group: WGM x WGN wave tiles of
+// (BM/WGM) x (BM/WGN), each split over SK wavefronts along K (contiguous K
+// ranges in units of two chunks) whose partial sums are added through LDS in
+// a fixed order (deterministic) before the epilogue.  With SK > 1 the routine
+// ends in a work-group barrier, so every thread of the work-group must call it.
+template <int P, int BM, int WGM, int WGN, int KU, int SK = 1>
 __device__ __forceinline__ void gemm_tile(const GemmDesc<typename Traits<P>::T>& g, int64_t n, int64_t ld,
                                           int64_t kpad, int ti, int tj) {
     using T = typename Traits<P>::T;
@@ -167,8 +171,10 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<typename Traits<P>::T>&
     constexpr int FM = WTM / 16, FN = WTN / 16;
     static_assert(FM >= 1 && FN >= 1 && WTM % 16 == 0 && WTN % 16 == 0, "wave tile must hold whole MFMA blocks");
     static_assert(KU % Traits<P>::MK == 0, "KU must be a multiple of the MFMA k per lane");
+    static_assert(SK >= 1 && SK <= 8, "K split of 1..8 wavefronts");
 
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave_all = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int ks = wave_all / (WGM * WGN), wave = wave_all % (WGM * WGN);
     const int wm = wave / WGN, wn = wave % WGN;
     const bool diag_tile = ti == tj;
     const int64_t row0 = (int64_t)ti * BM + wm * WTM;
@@ -196,15 +202,41 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<typename Traits<P>::T>&
     // 2 CH, and the loads past the end are clamped to the last chunks (their
     // values are never used).  Straight-line code lets the compiler wait only
     // for the chunk being consumed while the next one is in flight.
-    load(a0, b0, 0);
-    load(a1, b1, CH);
-    for (int64_t k0 = 0;;) {
-        mma_chunk<P, KU, FM, FN>(acc, a0, b0);
-        load(a0, b0, (k0 + 2 * CH < kpad) ? k0 + 2 * CH : kpad - 2 * CH);
-        mma_chunk<P, KU, FM, FN>(acc, a1, b1);
-        load(a1, b1, (k0 + 3 * CH < kpad) ? k0 + 3 * CH : kpad - CH);
-        k0 += 2 * CH;
-        if (k0 >= kpad) break;
+    int64_t kbeg = 0, kend = kpad;
+    if constexpr (SK > 1) {
+        const int64_t units = kpad / (2 * CH);
+        kbeg = units * ks / SK * (2 * CH);
+        kend = units * (ks + 1) / SK * (2 * CH);
+    }
+    if (kend > kbeg) {
+        load(a0, b0, kbeg);
+        load(a1, b1, kbeg + CH);
+        for (int64_t k0 = kbeg;;) {
+            mma_chunk<P, KU, FM, FN>(acc, a0, b0);
+            load(a0, b0, (k0 + 2 * CH < kend) ? k0 + 2 * CH : kend - 2 * CH);
+            mma_chunk<P, KU, FM, FN>(acc, a1, b1);
+            load(a1, b1, (k0 + 3 * CH < kend) ? k0 + 3 * CH : kend - CH);
+            k0 += 2 * CH;
+            if (k0 >= kend) break;
+        }
+    }
+    if constexpr (SK > 1) {
+        // partial sums of the K slices 1..SK-1 through LDS, added in slice order
+        __shared__ Acc red[SK - 1][WGM * WGN][FM * FN][64];
+        if (ks > 0) {
+#pragma unroll
+            for (int f = 0; f < FM; ++f)
+#pragma unroll
+                for (int q = 0; q < FN; ++q) red[ks - 1][wave][f * FN + q][lane] = acc[f][q];
+        }
+        __syncthreads();
+        if (ks > 0) return;
+#pragma unroll
+        for (int j = 0; j < SK - 1; ++j)
+#pragma unroll
+            for (int f = 0; f < FM; ++f)
+#pragma unroll
+                for (int q = 0; q < FN; ++q) acc[f][q] += red[j][wave][f * FN + q][lane];
     }
 
     // Output layout of a 16 x 16 block: lane (lr, lq) holds column lr and, in its
