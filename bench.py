@@ -60,6 +60,39 @@ def run_steps(cd, handle, H, beta, n_elec, order, opts, steps, warmup, want_dens
     return dt, prof, info
 
 
+GEMM_SOURCES = ("paper_2306_12616_amd/csrc/gemm_tile.h", "paper_2306_12616_amd/csrc/k_gemm.hip")
+
+
+def gemm_sources_sha256():
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in GEMM_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_of(prec, n, order):
+    """HBM bytes per product-kernel launch from the committed counter summary, if it still applies.
+
+    The summary (``profiles/traffic_k_gemm_<prec>_n<n>_order<order>.txt``) holds a line
+    ``traffic-json: {...}`` written from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of
+    ``bench.py --copy-probe-mib``; it is used only while the product kernel's sources hash to
+    the recorded value (otherwise the counters describe another kernel and traffic is null).
+    """
+    path = os.path.join(ROOT, "profiles", f"traffic_k_gemm_{prec}_n{n}_order{order}.txt")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("traffic-json:"):
+                rec = json.loads(line.split(":", 1)[1])
+                if rec.get("kernel_sources_sha256") == gemm_sources_sha256():
+                    return rec.get("bytes_per_launch")
+    return None
+
+
 def roofline_of(prof, prec):
     """Matrix-product kernel: algorithmic flops / summed launch time vs the MFMA peak."""
     if prof["gemm_ms"] <= 0:
@@ -80,7 +113,7 @@ def hbm_of(ms, nbytes):
     return round(nbytes / (ms * 1e-3) / 1e9, 1)
 
 
-def cpu_baseline(h_np, beta, n_elec, order, budget_s=10.0, max_reps=3):
+def cpu_baseline(h_np, beta, n_elec, order, budget_s=10.0, max_reps=50):
     from oracle import chebyshev as ch
 
     try:
@@ -90,6 +123,7 @@ def cpu_baseline(h_np, beta, n_elec, order, budget_s=10.0, max_reps=3):
     except Exception:
         cores = os.cpu_count() or 1
     reps, t0 = 0, time.perf_counter()
+    max_reps = max(max_reps, 1)
     while reps < max_reps:
         ch.mu_search_density(h_np, beta, n_elec, order)
         reps += 1
@@ -178,7 +212,7 @@ def learned_row(cd, handle, torch, order=256, chunks=20, chunk=1024, eval_count=
         ev.mu_only(Hs, betas, nes, allow_errors=True)        # capture
         cd.chebdm_profile_enable(handle, True)
         ev.mu_only(Hs, betas, nes, allow_errors=True)        # eager, launch-timed
-        cd.chebdm_profile_read(handle)
+        prof = cd.chebdm_profile_read(handle)
         cd.chebdm_profile_enable(handle, False)
         torch.cuda.synchronize()
         ta = time.perf_counter()
@@ -186,6 +220,7 @@ def learned_row(cd, handle, torch, order=256, chunks=20, chunk=1024, eval_count=
         torch.cuda.synchronize()
         row = search_report(ev, status, iters, t, nes)
         row["ms_per_batch_mu_only"] = round(1e3 * (time.perf_counter() - ta), 2)
+        row["search_ms_eager"] = round(prof["search_ms"], 3)
         modes[mode] = row
         log(f"learned: {mode} {row}")
     ev.close()
@@ -208,6 +243,9 @@ def main():
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
     ap.add_argument("--no-breakdown", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before timing, run one plain device copy of this many MiB (the calibration "
+                         "kernel for rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -231,12 +269,22 @@ def main():
     h_np = make_h(n, "gaussmix6", 2002)
     H = torch.from_numpy(h_np).to("cuda:0")
     opts = cd.make_opts(args.prec)
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib * (1 << 18), dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
+        del src, dst
 
     log(f"timing {args.steps} steps (warmup {args.warmup}) of mu search + density, prec={args.prec}")
     dt, prof, info = run_steps(cd, handle, H, beta, n_elec, order, opts, args.steps, args.warmup)
     value = args.steps / dt
     log(f"  {value:.3f} DM/s, {1e3 * dt / args.steps:.2f} ms/step, gemm {prof['gemm_ms'] / args.steps:.2f} ms/step")
     roof = roofline_of(prof, args.prec)
+    if roof is not None:
+        roof["traffic"] = traffic_of(args.prec, n, order)
 
     result = {
         "metric": METRIC, "value": round(value, 4), "unit": "density matrices/s", "n_gpus": 1,

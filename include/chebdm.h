@@ -300,9 +300,11 @@ int chebdm_mlp_adam(chebdm_handle h, float* dW, const float* dGrad, float* dM, f
 /*
  * Launch timing.  While enabled, the library records a HIP event pair on its
  * stream around every launch of the matrix-product kernel (one pair per
- * grouped launch or batched product step), of the block-sum pass and of the
- * Gram contraction; a batched run then executes eagerly on the handle's
- * stream instead of replaying its graph.
+ * grouped launch or batched product step), of the block-sum pass, of the
+ * Gram contraction and of the chemical-potential search (DCT-III of the
+ * moments and the search; in a batched run with the learned start, also the
+ * feature and network passes); a batched run then executes eagerly on the
+ * handle's stream instead of replaying its graph.
  * chebdm_profile_read synchronises the stream, sums the elapsed times since
  * the last read (or enable) and clears them.  Algorithmic work counted:
  *   gemm_flop   n^2 (n+1) per product (the n(n+1)/2 distinct outputs of a
@@ -321,6 +323,8 @@ typedef struct {
     double combine_ms, combine_bytes;
     int64_t gram_calls;
     double gram_ms, gram_bytes;
+    int64_t search_calls;    /* DCT-III + mu search (+ network forward) passes   */
+    double search_ms;
 } chebdm_profile;
 
 /* Turn launch timing on (enable != 0) or off; clears the counters. */

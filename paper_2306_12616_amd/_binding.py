@@ -48,7 +48,7 @@ class Profile(ctypes.Structure):
     _fields_ = [("gemm_launches", ctypes.c_int64), ("gemm_products", ctypes.c_int64), ("gemm_ms", ctypes.c_double),
                 ("gemm_flop", ctypes.c_double), ("combine_calls", ctypes.c_int64), ("combine_ms", ctypes.c_double),
                 ("combine_bytes", ctypes.c_double), ("gram_calls", ctypes.c_int64), ("gram_ms", ctypes.c_double),
-                ("gram_bytes", ctypes.c_double)]
+                ("gram_bytes", ctypes.c_double), ("search_calls", ctypes.c_int64), ("search_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -630,8 +630,11 @@ int chebdm_mu_search(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, 
     HIP_TRY(launch_shift(dH, n, ldh, h->scal, tslot(h, pl, 1), pl.ld, pl.prec, h->stream));
     CHECK(baby_steps(h, pl, &pl.n_gemm));
     CHECK(moments_on_device(h, pl, &pl.n_gemm));
+    size_t ev = (size_t)-1;
+    if (h->prof) CHECK(prof_begin(h, PROF_SEARCH, 0, 0.0, 0.0, &ev));
     HIP_TRY(launch_dct3(h->tau, order, pl.M, h->w, h->xtab, h->stream));
     HIP_TRY(launch_bisect(h->w, h->xtab, pl.M, h->scal, h->stream));
+    if (h->prof) CHECK(prof_end(h, ev));
     if (dD) {
         HIP_TRY(launch_fermi_coeffs(order, pl.M, h->scal, h->ftab, h->c, h->stream));
         HIP_TRY(launch_block_coeffs(h->c, order, pl.k, pl.m, pl.form, h->coef, h->stream));
@@ -705,10 +708,13 @@ int chebdm_profile_read(chebdm_handle h, chebdm_profile* out) {
             out->combine_calls += 1;
             out->combine_ms += ms;
             out->combine_bytes += e.bytes;
-        } else {
+        } else if (e.kind == PROF_GRAM) {
             out->gram_calls += 1;
             out->gram_ms += ms;
             out->gram_bytes += e.bytes;
+        } else {
+            out->search_calls += 1;
+            out->search_ms += ms;
         }
     }
     h->ev_used = 0;

@@ -45,7 +45,7 @@ namespace chebdm {
 // Sets the thread-local message of chebdm_last_error and returns code.
 int fail(int code, const std::string& msg);
 
-enum { PROF_GEMM = 0, PROF_COMBINE = 1, PROF_GRAM = 2 };
+enum { PROF_GEMM = 0, PROF_COMBINE = 1, PROF_GRAM = 2, PROF_SEARCH = 3 };
 // Timed region on the handle's stream (no-op unless profiling is on).
 int prof_begin(chebdm_handle h, int kind, int products, double flop, double bytes, size_t* idx);
 int prof_end(chebdm_handle h, size_t idx);
