@@ -302,32 +302,41 @@ def main():
         "phases_ms_per_step": {"gemm": round(prof["gemm_ms"] / args.steps, 3),
                                "combine": round(prof["combine_ms"] / args.steps, 3),
                                "gram": round(prof["gram_ms"] / args.steps, 3),
+                               "search": round(prof["search_ms"] / args.steps, 3),
                                "other": round(1e3 * dt / args.steps - (prof["gemm_ms"] + prof["combine_ms"]
-                                                                       + prof["gram_ms"]) / args.steps, 3)},
+                                                                       + prof["gram_ms"] + prof["search_ms"])
+                                              / args.steps, 3)},
         "hbm_GBs": {"combine": hbm_of(prof["combine_ms"], prof["combine_bytes"]),
                     "gram": hbm_of(prof["gram_ms"], prof["gram_bytes"]), "peak": PEAK_HBM_GBS},
     }
 
     if not args.no_breakdown:
         rows = {}
-        cases = [(1000, "fp64"), (1000, "fp32"), (4000, "fp32"), (4000, "bf16x3"), (4000, "bf16x6"),
-                 (1000, "bf16x3")]
+        cases = [(1000, "fp64", "bisection"), (1000, "fp64", "newton"), (1000, "fp32", "bisection"),
+                 (2000, "fp64", "bisection"), (2000, "fp32", "bisection"), (4000, "fp32", "bisection"),
+                 (4000, "bf16x3", "bisection"), (4000, "bf16x6", "bisection"), (1000, "bf16x3", "bisection"),
+                 (4000, "fp64", "newton")]
         if args.prec != "fp64" or n != 4000:
-            cases.append((4000, "fp64"))
-        for nn, pr in cases:
-            log(f"breakdown n={nn} prec={pr}")
-            hh = H if nn == n else torch.from_numpy(make_h(nn, "gaussmix6", 2000 if nn == 1000 else 2002)).to("cuda:0")
-            steps = 20 if nn <= 1000 else 5
-            d2, p2, i2 = run_steps(cd, handle, hh, beta, nn / 2.0, order, cd.make_opts(pr), steps, 2)
+            cases.append((4000, "fp64", "bisection"))
+        seeds = {1000: 2000, 2000: 2001, 4000: 2002}
+        hs = {n: H}
+        for nn, pr, se in cases:
+            log(f"breakdown n={nn} prec={pr} search={se}")
+            if nn not in hs:
+                hs[nn] = torch.from_numpy(make_h(nn, "gaussmix6", seeds.get(nn, 2000))).to("cuda:0")
+            steps = 20 if nn <= 1000 else (10 if nn <= 2000 else 5)
+            d2, p2, i2 = run_steps(cd, handle, hs[nn], beta, nn / 2.0, order, cd.make_opts(pr, search=se), steps, 2)
             r2 = roofline_of(p2, pr)
-            rows[f"n{nn}_{pr}"] = {"dm_per_s": round(steps / d2, 3), "ms_per_step": round(1e3 * d2 / steps, 3),
-                                   "gemm_frac_of_peak": r2["frac"] if r2 else None,
-                                   "gemm_tflops": r2["achieved"] if r2 else None}
+            key = f"n{nn}_{pr}" + ("" if se == "bisection" else f"_{se}")
+            rows[key] = {"dm_per_s": round(steps / d2, 3), "ms_per_step": round(1e3 * d2 / steps, 3),
+                         "gemm_frac_of_peak": r2["frac"] if r2 else None,
+                         "gemm_tflops": r2["achieved"] if r2 else None,
+                         "search_ms": round(p2["search_ms"] / steps, 3), "search_evals": i2["iters"]}
+        del hs
             # fixed-mu density only (no ladder / moments / bisection)
-        fp64_1000 = rows.get("n1000_fp64", {}).get("dm_per_s")
         for key, row in rows.items():
-            base = fp64_1000 if key.startswith("n1000") else (value if args.prec == "fp64" and n == 4000 else
-                                                              rows.get("n4000_fp64", {}).get("dm_per_s"))
+            nn = key.split("_")[0]
+            base = value if (nn == f"n{n}" and args.prec == "fp64") else rows.get(f"{nn}_fp64", {}).get("dm_per_s")
             row["speedup_vs_fp64"] = round(row["dm_per_s"] / base, 3) if base else None
         result["breakdown"] = rows
 

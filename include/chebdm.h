@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define CHEBDM_ABI_VERSION 1
+#define CHEBDM_ABI_VERSION 2
 
 typedef struct chebdm_ctx* chebdm_handle;
 
@@ -69,6 +69,14 @@ enum chebdm_giant {
     CHEBDM_GIANT_POWER = 1        /* paper's sum_j T_k^j S_j by Horner (eq. "ansatz") */
 };
 
+/* How chebdm_mu_search finds mu~ on the quadrature trace t(mu~) (both stop
+ * at |t - N_e| < tol, at a bracket under 4 ulp, or after max_iter steps). */
+enum chebdm_search {
+    CHEBDM_SEARCH_BISECTION = 0, /* midpoint rule on [-1, 1]                          */
+    CHEBDM_SEARCH_NEWTON = 1     /* safeguarded Newton from 0 with t' from the same   */
+                                 /* quadrature; a step leaving the bracket bisects   */
+};
+
 enum chebdm_status {
     CHEBDM_OK = 0,
     CHEBDM_WARN_NOCONV = 1,       /* bisection stopped before |tr D - N_e| < tol */
@@ -87,6 +95,7 @@ typedef struct {
     int32_t n_quad;      /* quadrature nodes M for c_n; 0 = automatic rule         */
     int32_t max_iter;    /* bisection sweep cap; 0 = 200                           */
     int32_t baby_steps;  /* enum chebdm_baby, default CHEBDM_BABY_AUTO                */
+    int32_t search;      /* enum chebdm_search of chebdm_mu_search, default BISECTION */
     double tol;          /* target |tr D - N_e| of the mu search; 0 = 1e-10        */
 } chebdm_opts;
 
@@ -210,7 +219,8 @@ int chebdm_block_coeffs(chebdm_handle h, const double* c, int32_t order, int32_t
  * persistent launch over a list of (problem, tile) items.
  *
  * chebdm_batch_create: count problems of sizes n[p] (1..65535), order >= 2
- *   (k, m >= 2); opts: prec any, giant_form must be COMPOSITION, n_quad 0;
+ *   (k, m >= 2); opts: prec any, giant_form must be COMPOSITION, n_quad 0,
+ *   search sets the initial search mode (0 or 1, see chebdm_batch_set_search);
  *   max_quad caps the per-problem quadrature M (0 = 65536; a problem whose
  *   rule asks for more reports CHEBDM_ERR_ARG in its status).  Allocates
  *   sum_p (k+m) ld_p^2 workspace elements (ld_p = round_up(n_p, 128)).

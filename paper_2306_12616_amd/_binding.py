@@ -31,7 +31,7 @@ _FORM_NAMES = {"composition": COMPOSITION, "clenshaw": COMPOSITION, "power": POW
 class Opts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("giant_form", ctypes.c_int32), ("k_override", ctypes.c_int32),
                 ("n_quad", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("baby_steps", ctypes.c_int32),
-                ("tol", ctypes.c_double)]
+                ("search", ctypes.c_int32), ("tol", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -146,8 +146,11 @@ def _check(rc: int, allow_warn: bool = False) -> int:
     return rc
 
 
+_SEARCH_NAMES = {"bisection": 0, "newton": 1}
+
+
 def make_opts(prec="fp64", giant="composition", k_override: int = 0, n_quad: int = 0,
-              max_iter: int = 0, tol: float = 0.0, baby="auto") -> Opts:
+              max_iter: int = 0, tol: float = 0.0, baby="auto", search="bisection") -> Opts:
     o = Opts()
     load_library().chebdm_default_opts(ctypes.byref(o))
     o.prec = _PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
@@ -155,6 +158,7 @@ def make_opts(prec="fp64", giant="composition", k_override: int = 0, n_quad: int
     o.k_override = int(k_override)
     o.n_quad = int(n_quad)
     o.baby_steps = _BABY_NAMES[baby] if isinstance(baby, str) else int(baby)
+    o.search = _SEARCH_NAMES[search] if isinstance(search, str) else int(search)
     if max_iter:
         o.max_iter = int(max_iter)
     if tol:
@@ -319,7 +323,7 @@ class Batch:
                                                   self.order, ctypes.byref(opts) if opts is not None else None,
                                                   int(max_quad), ctypes.byref(b)))
         self._b = b
-        self.search_mode = 0
+        self.search_mode = int(opts.search) if opts is not None else 0
         self._weights = None
 
     def tune(self, cache_path: Optional[str] = None) -> str:

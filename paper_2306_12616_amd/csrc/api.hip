@@ -75,6 +75,7 @@ struct Plan {
     int order = 0, k = 1, m = 1, M = 0;
     int prec = CHEBDM_FP64, form = CHEBDM_GIANT_COMPOSITION, baby = CHEBDM_BABY_STAGES;
     int max_iter = 200;
+    int search = CHEBDM_SEARCH_BISECTION;
     double tol = 1e-10;
     size_t elem = 8;
     int n_gemm = 0;
@@ -183,6 +184,9 @@ int check_opts(const chebdm_opts* o, Plan& pl) {
         return fail(CHEBDM_ERR_ARG, "negative option");
     if (o->baby_steps < CHEBDM_BABY_AUTO || o->baby_steps > CHEBDM_BABY_SEQUENTIAL)
         return fail(CHEBDM_ERR_ARG, "unknown baby-step schedule");
+    if (o->search != CHEBDM_SEARCH_BISECTION && o->search != CHEBDM_SEARCH_NEWTON)
+        return fail(CHEBDM_ERR_ARG, "unknown mu search");
+    pl.search = o->search;
     pl.baby = o->baby_steps != CHEBDM_BABY_AUTO
                   ? o->baby_steps
                   : (o->prec == CHEBDM_FP64 ? CHEBDM_BABY_STAGES : CHEBDM_BABY_SEQUENTIAL);
@@ -633,7 +637,7 @@ int chebdm_mu_search(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, 
     size_t ev = (size_t)-1;
     if (h->prof) CHECK(prof_begin(h, PROF_SEARCH, 0, 0.0, 0.0, &ev));
     HIP_TRY(launch_dct3(h->tau, order, pl.M, h->w, h->xtab, h->stream));
-    HIP_TRY(launch_bisect(h->w, h->xtab, pl.M, h->scal, h->stream));
+    HIP_TRY(launch_bisect(h->w, h->xtab, pl.M, h->scal, pl.search, h->stream));
     if (h->prof) CHECK(prof_end(h, ev));
     if (dD) {
         HIP_TRY(launch_fermi_coeffs(order, pl.M, h->scal, h->ftab, h->c, h->stream));

@@ -299,6 +299,8 @@ int chebdm_batch_create(chebdm_handle h, int32_t count, const int64_t* n, int32_
     if (o.giant_form != CHEBDM_GIANT_COMPOSITION)
         return fail(CHEBDM_ERR_UNSUPPORTED, "the batched path uses the composition form only");
     if (o.n_quad != 0) return fail(CHEBDM_ERR_UNSUPPORTED, "the batched path sizes the quadrature per problem");
+    if (o.search != CHEBDM_SEARCH_BISECTION && o.search != CHEBDM_SEARCH_NEWTON)
+        return fail(CHEBDM_ERR_ARG, "unknown mu search");
     if (order < 2) return fail(CHEBDM_ERR_ARG, "the batched path needs order >= 2");
     int64_t k = o.k_override;
     if (k <= 0) {
@@ -323,6 +325,7 @@ int chebdm_batch_create(chebdm_handle h, int32_t count, const int64_t* n, int32_
     b->elem = o.prec == CHEBDM_FP64 ? 8 : 4;
     b->tol = o.tol > 0.0 ? o.tol : 1e-10;
     b->max_iter = o.max_iter > 0 ? o.max_iter : 200;
+    b->search_mode = o.search;
     int lmax = (order - 1) / (int)k;
     if (lmax > (int)m - 1) lmax = (int)m - 1;
     b->d = BatchDims{count, order, (int)k, (int)m, lmax, nmax, 0, mcap, o.prec};

@@ -78,7 +78,7 @@ hipError_t launch_assemble_moments(const double* tr_baby, const double* gram, in
                                    int order, int64_t n, double* tau, hipStream_t st);
 hipError_t launch_dct3(const double* tau, int order, int M, double* w, double* x_tab,
                        hipStream_t st);
-hipError_t launch_bisect(const double* w, const double* x_tab, int M, DevScalars* s,
+hipError_t launch_bisect(const double* w, const double* x_tab, int M, DevScalars* s, int mode,
                          hipStream_t st);
 
 // ---- block sums and Gram contractions (k_combine.hip)

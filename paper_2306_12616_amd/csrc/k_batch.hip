@@ -15,6 +15,7 @@
 #include "cheb_dev.h"
 #include "gemm_tile.h"
 #include "reduce.h"
+#include "search_dev.h"
 
 namespace chebdm {
 
@@ -319,25 +320,8 @@ k_batch_dct3(const double* __restrict__ tau, int order, const int64_t* __restric
 
 constexpr int kBisect = 512;
 
-// t(mu~) = (1/M) sum_j f(x_j; mu~) w_j and its derivative, in one pass
-__device__ void batch_trace2(double mu_s, const double* __restrict__ w, const double* __restrict__ x, int64_t M,
-                             double beta_s, double* smem, double& t, double& dt) {
-    double acc = 0.0, accd = 0.0;
-    for (int64_t j = threadIdx.x; j < M; j += kBisect) {
-        const double f = fermi_scaled(x[j], beta_s, mu_s);
-        acc += f * w[j];
-        accd += beta_s * f * (1.0 - f) * w[j];
-    }
-    t = block_sum<kBisect>(acc, smem) / (double)M;
-    dt = block_sum<kBisect>(accd, smem) / (double)M;
-}
-
-// Chemical-potential search, one work-group per problem.
-//   mode 0: bisection on [-1, 1] (midpoint rule, same stopping rule as the single-problem search)
-//   mode 1: safeguarded Newton on [-1, 1] from mu~ = 0 (a step leaving the bracket is a bisection step)
-//   mode 2: network guess g: if t(g - delta) < N_e < t(g + delta), safeguarded Newton from g inside that
-//           bracket; otherwise plain bisection on [-1, 1] (the fallback)
-// Every mode stops at |t - N_e| < tol, at a bracket narrower than 4 ulp, or after max_iter steps.
+// Chemical-potential search, one work-group per problem (modes as in search_dev.h; mode 2 takes
+// the network's guess mu_hat[p]).
 __global__ void __launch_bounds__(kBisect)
 k_batch_search(const int64_t* __restrict__ mq, int64_t mcap, const double* __restrict__ w,
                const double* __restrict__ x, DevScalars* s, int mode, const float* __restrict__ mu_hat,
@@ -346,90 +330,8 @@ k_batch_search(const int64_t* __restrict__ mq, int64_t mcap, const double* __res
     const int p = blockIdx.x;
     DevScalars& d = s[p];
     if (d.status != 0) return;
-    const int64_t M = mq[p];
-    const double* wp = w + p * mcap;
-    const double* xp = x + p * mcap;
-    const double beta_s = d.beta_s, ne = d.n_elec, tol = d.tol;
-    const int max_iter = d.max_iter;
-    int evals = 0, learned = 0, iters = 0, status = CHEBDM_WARN_NOCONV;
-    double lo = -1.0, hi = 1.0, mu0 = 0.0, t_lo, t_hi, dtmp;
-    bool bracketed = false;
-    if (mode == 2) {
-        double g = (double)mu_hat[p];
-        if (!isfinite(g)) g = 0.0;
-        g = fmin(fmax(g, -1.0), 1.0);
-        lo = fmax(-1.0, g - delta);
-        hi = fmin(1.0, g + delta);
-        batch_trace2(lo, wp, xp, M, beta_s, smem, t_lo, dtmp);
-        batch_trace2(hi, wp, xp, M, beta_s, smem, t_hi, dtmp);
-        evals += 2;
-        if (t_lo < ne && ne < t_hi) {
-            bracketed = true;
-            learned = 1;
-            mu0 = g;
-        }
-    }
-    double mid = 0.0, t_mid = NAN;
-    if (!bracketed) {
-        lo = -1.0;
-        hi = 1.0;
-        batch_trace2(lo, wp, xp, M, beta_s, smem, t_lo, dtmp);
-        batch_trace2(hi, wp, xp, M, beta_s, smem, t_hi, dtmp);
-        evals += 2;
-        if (!(t_lo < ne && ne < t_hi)) {
-            if (threadIdx.x == 0) {
-                d.mu_s = NAN;
-                d.trace = NAN;
-                d.iters = 0;
-                d.evals = evals;
-                d.learned = 0;
-                d.status = CHEBDM_ERR_BRACKET;
-            }
-            return;
-        }
-    }
-    if (mode == 0 || (mode == 2 && !learned)) {
-        for (int it = 1; it <= max_iter; ++it) {
-            mid = 0.5 * (lo + hi);
-            batch_trace2(mid, wp, xp, M, beta_s, smem, t_mid, dtmp);
-            iters = it;
-            if (fabs(t_mid - ne) < tol) {
-                status = CHEBDM_OK;
-                break;
-            }
-            if (t_mid < ne) lo = mid;
-            else hi = mid;
-            if (hi - lo < 4.0 * ulp_spacing(mid)) break;
-        }
-    } else {
-        mid = mu0;
-        for (int it = 1; it <= max_iter; ++it) {
-            double dt;
-            batch_trace2(mid, wp, xp, M, beta_s, smem, t_mid, dt);
-            iters = it;
-            if (fabs(t_mid - ne) < tol) {
-                status = CHEBDM_OK;
-                break;
-            }
-            if (t_mid < ne) lo = mid;
-            else hi = mid;
-            double cand = mid - (t_mid - ne) / dt;
-            if (!(dt > 0.0) || !(cand > lo && cand < hi)) cand = 0.5 * (lo + hi);
-            if (hi - lo < 4.0 * ulp_spacing(mid)) break;
-            mid = cand;
-        }
-    }
-    evals += iters;
-    if (threadIdx.x == 0) {
-        d.mu_s = mid;
-        d.trace = t_mid;
-        d.iters = iters;
-        d.evals = evals;
-        d.learned = learned;
-        d.status = status;
-        d.lo = lo;
-        d.hi = hi;
-    }
+    const double guess = mode == 2 ? (double)mu_hat[p] : 0.0;
+    mu_search_one<kBisect>(mq[p], w + p * mcap, x + p * mcap, d, mode, guess, delta, smem);
 }
 
 // network inputs of problem p: tau_1..tau_62 / n, N_e / n, log(beta') / 4

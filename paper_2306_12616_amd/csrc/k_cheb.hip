@@ -14,6 +14,7 @@
 #include "cheb_dev.h"
 #include "internal.h"
 #include "reduce.h"
+#include "search_dev.h"
 
 namespace chebdm {
 
@@ -178,50 +179,11 @@ k_dct3(const double* __restrict__ tau, int order, int64_t M, double* __restrict_
 
 constexpr int kBisectThreads = 1024;
 
-__device__ double trace_at(double mu_s, const double* __restrict__ w, const double* __restrict__ x,
-                           int64_t M, double beta_s, double* smem) {
-    double acc = 0.0;
-    for (int64_t j = threadIdx.x; j < M; j += kBisectThreads) acc += fermi_scaled(x[j], beta_s, mu_s) * w[j];
-    return block_sum<kBisectThreads>(acc, smem) / (double)M;
-}
-
+// mu search of one problem (modes 0 bisection / 1 safeguarded Newton, search_dev.h)
 __global__ void __launch_bounds__(kBisectThreads)
-k_bisect(const double* __restrict__ w, const double* __restrict__ x, int64_t M, DevScalars* s) {
+k_bisect(const double* __restrict__ w, const double* __restrict__ x, int64_t M, DevScalars* s, int mode) {
     __shared__ double smem[kBisectThreads / 64];
-    const double beta_s = s->beta_s, ne = s->n_elec, tol = s->tol;
-    const int max_iter = s->max_iter;
-    double lo = -1.0, hi = 1.0;
-    const double t_lo = trace_at(lo, w, x, M, beta_s, smem);
-    const double t_hi = trace_at(hi, w, x, M, beta_s, smem);
-    int status = CHEBDM_WARN_NOCONV, iters = 0;
-    double mid = 0.0, t_mid = NAN;
-    if (!(t_lo < ne && ne < t_hi)) {
-        status = CHEBDM_ERR_BRACKET;
-        mid = NAN;
-    } else {
-        for (int it = 1; it <= max_iter; ++it) {
-            mid = 0.5 * (lo + hi);
-            t_mid = trace_at(mid, w, x, M, beta_s, smem);
-            iters = it;
-            if (fabs(t_mid - ne) < tol) {
-                status = CHEBDM_OK;
-                break;
-            }
-            if (t_mid < ne) lo = mid;
-            else hi = mid;
-            if (hi - lo < 4.0 * ulp_spacing(mid)) break;
-        }
-    }
-    if (threadIdx.x == 0) {
-        s->mu_s = mid;
-        s->trace = t_mid;
-        s->iters = iters;
-        s->evals = iters + 2;
-        s->learned = 0;
-        s->status = status;
-        s->lo = lo;
-        s->hi = hi;
-    }
+    mu_search_one<kBisectThreads>(M, w, x, *s, mode, 0.0, 0.0, smem);
 }
 
 }  // namespace
@@ -263,9 +225,10 @@ hipError_t launch_dct3(const double* tau, int order, int M, double* w, double* x
     return hipGetLastError();
 }
 
-hipError_t launch_bisect(const double* w, const double* x_tab, int M, DevScalars* s,
+hipError_t launch_bisect(const double* w, const double* x_tab, int M, DevScalars* s, int mode,
                          hipStream_t st) {
-    hipLaunchKernelGGL(k_bisect, dim3(1), dim3(kBisectThreads), 0, st, w, x_tab, (int64_t)M, s);
+    if (mode < 0 || mode > 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bisect, dim3(1), dim3(kBisectThreads), 0, st, w, x_tab, (int64_t)M, s, mode);
     return hipGetLastError();
 }
 

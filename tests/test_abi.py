@@ -38,9 +38,11 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version_and_defaults(lib):
-    assert lib.chebdm_abi_version() == 1
+    assert lib.chebdm_abi_version() == 2
     o = chebdm.make_opts()
-    assert (o.prec, o.giant_form, o.k_override, o.n_quad, o.max_iter, o.baby_steps, o.tol) == (0, 0, 0, 0, 200, 0, 1e-10)
+    assert (o.prec, o.giant_form, o.k_override, o.n_quad, o.max_iter, o.baby_steps, o.search, o.tol) == \
+        (0, 0, 0, 0, 200, 0, 0, 1e-10)
+    assert chebdm.make_opts(search="newton").search == 1
 
 
 def _dbl():

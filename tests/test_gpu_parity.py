@@ -213,20 +213,27 @@ def test_moments_match_oracle(cd, handle, n, order, kov):
 # ------------------------------------------------------------------ mu search
 
 MU_CASES = [
-    # n, law, order, beta, n_elec, form
-    (256, "uniform", 128, 50.0, 128.0, "composition"),     # the N = 256 reference workload
-    (256, "uniform", 128, 50.0, 128.0, "power"),
-    (300, "gaussmix6", 200, 80.0, 101.5, "composition"),
-    (520, "highdos", 255, 60.0, 260.0, "composition"),
+    # n, law, order, beta, n_elec, form, search
+    (256, "uniform", 128, 50.0, 128.0, "composition", "bisection"),     # the N = 256 reference workload
+    (256, "uniform", 128, 50.0, 128.0, "power", "bisection"),
+    (300, "gaussmix6", 200, 80.0, 101.5, "composition", "bisection"),
+    (520, "highdos", 255, 60.0, 260.0, "composition", "bisection"),
+    (300, "gaussmix6", 200, 80.0, 101.5, "composition", "newton"),
+    (520, "highdos", 255, 60.0, 260.0, "composition", "newton"),
 ]
 
 
-@pytest.mark.parametrize("case", MU_CASES, ids=[f"n{c[0]}-L{c[2]}-{c[5]}" for c in MU_CASES])
+@pytest.mark.parametrize("case", MU_CASES, ids=[f"n{c[0]}-L{c[2]}-{c[5]}-{c[6]}" for c in MU_CASES])
 def test_mu_search_matches_oracle(cd, handle, case):
-    n, law, order, beta, ne, form = case
+    n, law, order, beta, ne, form, search = case
     _say(f"mu_search {case}")
     h, q, lam = synth.hamiltonian(n, law, seed=2000 + n)
-    mu, D, info = cd.chebdm_mu_search(handle, _dev(h), beta, ne, order, cd.make_opts("fp64", form))
+    mu, D, info = cd.chebdm_mu_search(handle, _dev(h), beta, ne, order, cd.make_opts("fp64", form, search=search))
+    if search == "newton":
+        _, _, info_b = cd.chebdm_mu_search(handle, _dev(h), beta, ne, order, cd.make_opts("fp64", form),
+                                           want_density=False)
+        _say(f"  evaluations: newton {info['iters']} vs bisection {info_b['iters']}")
+        assert info["iters"] < info_b["iters"]
     torch.cuda.synchronize()
     assert info["status"] == 0, info
     emin, emax = info["emin"], info["emax"]
@@ -254,6 +261,8 @@ def test_mu_search_symmetric_spectrum_first_sweep(cd, handle):
     lam = synth.symmetric_pairs_spectrum(n, seed=4)
     h, q, lam = synth.hamiltonian(n, lam=lam, seed=4)
     mu, D, info = cd.chebdm_mu_search(handle, _dev(h), 30.0, n / 2, 64, None, -1.5, 1.5)
+    assert info["iters"] == 1 and mu == 0.0
+    mu, D, info = cd.chebdm_mu_search(handle, _dev(h), 30.0, n / 2, 64, cd.make_opts(search="newton"), -1.5, 1.5)
     assert info["iters"] == 1 and mu == 0.0
 
 
