@@ -35,29 +35,52 @@ k_gersh_partial(const double* __restrict__ H, int64_t n, int64_t ldh, int64_t ro
     partial[(int64_t)blockIdx.y * n + j] = s;
 }
 
-constexpr int kFinalThreads = 1024;
+constexpr int kColThreads = 256;
 
-__global__ void __launch_bounds__(kFinalThreads)
-k_gersh_final(const double* __restrict__ H, int64_t n, int64_t ldh,
-              const double* __restrict__ partial, int nsplit, DevScalars* s) {
-    __shared__ double smem[kFinalThreads / 64];
-    double lo = INFINITY, hi = -INFINITY;
-    int bad = 0;
-    for (int64_t j = threadIdx.x; j < n; j += kFinalThreads) {
+// Per column j: r_j = sum of the split partials (fixed order), the disc [d - r_j, d + r_j]
+// with d = H[j][j]; per work-group: min, max and a non-finite flag, written to out[3][nb].
+__global__ void __launch_bounds__(kColThreads)
+k_gersh_cols(const double* __restrict__ H, int64_t n, int64_t ldh, const double* __restrict__ partial, int nsplit,
+             double* __restrict__ out, int nb) {
+    __shared__ double smem[kColThreads / 64];
+    const int64_t j = (int64_t)blockIdx.x * kColThreads + threadIdx.x;
+    double lo = INFINITY, hi = -INFINITY, bad = 0.0;
+    if (j < n) {
         double r = 0.0;
         for (int sp = 0; sp < nsplit; ++sp) r += partial[(int64_t)sp * n + j];
         const double d = H[j * ldh + j];
-        if (!isfinite(r) || !isfinite(d)) bad = 1;
-        lo = fmin(lo, d - r);
-        hi = fmax(hi, d + r);
+        if (!isfinite(r) || !isfinite(d)) bad = 1.0;
+        lo = d - r;
+        hi = d + r;
     }
-    const double badsum = block_sum<kFinalThreads>((double)bad, smem);
+    bad = block_sum<kColThreads>(bad, smem);
+    lo = block_min<kColThreads>(lo, smem);
+    hi = block_max<kColThreads>(hi, smem);
+    if (threadIdx.x == 0) {
+        out[blockIdx.x] = lo;
+        out[nb + blockIdx.x] = hi;
+        out[2 * nb + blockIdx.x] = bad;
+    }
+}
+
+constexpr int kFinalThreads = 256;
+
+__global__ void __launch_bounds__(kFinalThreads)
+k_gersh_final(const double* __restrict__ part, int nb, DevScalars* s) {
+    __shared__ double smem[kFinalThreads / 64];
+    double lo = INFINITY, hi = -INFINITY, bad = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kFinalThreads) {
+        lo = fmin(lo, part[b]);
+        hi = fmax(hi, part[nb + b]);
+        bad += part[2 * nb + b];
+    }
+    bad = block_sum<kFinalThreads>(bad, smem);
     lo = block_min<kFinalThreads>(lo, smem);
     hi = block_max<kFinalThreads>(hi, smem);
     if (threadIdx.x == 0) {
         s->emin = lo;
         s->emax = hi;
-        s->nonfinite = badsum > 0.0 ? 1 : 0;
+        s->nonfinite = bad > 0.0 ? 1 : 0;
     }
 }
 
@@ -129,14 +152,17 @@ hipError_t launch_gershgorin(const double* H, int64_t n, int64_t ldh, double* pa
     const int64_t max_split = (n + 31) / 32;
     if (nsplit > max_split) nsplit = max_split;
     if (nsplit < 1) nsplit = 1;
-    while (nsplit > 1 && nsplit * n > partial_cap) nsplit >>= 1;
-    if (nsplit * n > partial_cap) return hipErrorInvalidValue;
+    const int64_t nb = (n + kColThreads - 1) / kColThreads;
+    while (nsplit > 1 && nsplit * n + 3 * nb > partial_cap) nsplit >>= 1;
+    if (nsplit * n + 3 * nb > partial_cap) return hipErrorInvalidValue;
     const int64_t rows_per_split = (n + nsplit - 1) / nsplit;
     nsplit = (n + rows_per_split - 1) / rows_per_split;
+    double* part2 = partial + nsplit * n;
     hipLaunchKernelGGL(k_gersh_partial, dim3((unsigned)col_blocks, (unsigned)nsplit), dim3(kColsPerBlock),
                        0, st, H, n, ldh, rows_per_split, partial);
-    hipLaunchKernelGGL(k_gersh_final, dim3(1), dim3(kFinalThreads), 0, st, H, n, ldh,
-                       (const double*)partial, (int)nsplit, s);
+    hipLaunchKernelGGL(k_gersh_cols, dim3((unsigned)nb), dim3(kColThreads), 0, st, H, n, ldh,
+                       (const double*)partial, (int)nsplit, part2, (int)nb);
+    hipLaunchKernelGGL(k_gersh_final, dim3(1), dim3(kFinalThreads), 0, st, (const double*)part2, (int)nb, s);
     return hipGetLastError();
 }
 

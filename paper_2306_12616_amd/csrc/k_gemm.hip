@@ -87,22 +87,39 @@ hipError_t launch_cfg(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
     return hipGetLastError();
 }
 
-// Configuration from a measured sweep on MI355X (N = 1000/2000/4000): one
-// wavefront per 64 x 64 tile (64-thread work-groups, XCD-ordered) is fastest
-// whenever the upper triangle offers a few hundred tiles (float64 at N = 4000:
-// 59 TFLOP/s algorithmic vs 36 for 2 x 2 waves on 128-tiles); smaller
-// problems need more wavefronts per tile to fill the 1024 SIMDs, so they use
-// 2 x 2 waves of 32 x 32 on each 64-tile.
+// Launch configuration, from a measured sweep on MI355X (N = 1000 / 2000 / 4000, one and
+// four products per launch).  One wavefront per tile in every choice (64-thread work-groups
+// per K slice), XCD-ordered.  What decides is how well the launch fills the 1024 SIMDs:
+// these kernels hold one wavefront per SIMD (their accumulators and two register stages
+// take more than half of the 512 registers), so a launch of W wavefronts runs in
+// ceil(W / 1024) waves of work.  With few 64-tiles (W64 = upper-triangle 64-tiles x
+// products) smaller 48-tiles and K split over 2 or 4 wavefronts (summed through LDS) fill the
+// chip better; with many, 64-tiles without a split are fastest.  Measured (algorithmic
+// TFLOP/s, float64): N = 1000 single product 16 -> 31 (48-tiles, K split 4); N = 1000 four
+// products 28 -> 42 (48-tiles); N = 2000 single 28 -> 45 (48-tiles); N = 4000: 64-tiles.
+// 48-tiles need ceil(n/48)*48 <= ld; otherwise 64-tiles are used.
 template <int P>
 hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int64_t ld, hipStream_t st) {
     if (b.count <= 0) return hipSuccess;
     if (b.count > kMaxGroup || ld % 128 != 0) return hipErrorInvalidValue;
-    constexpr int KU1 = P == P_F64 ? 4 : (P == P_F32 ? 8 : 16);   // one wave per tile
-    constexpr int KU4 = P == P_F64 ? 2 : (P == P_F32 ? 4 : 8);    // four waves per tile
+    constexpr int KU = P == P_F64 ? 4 : (P == P_F32 ? 8 : 16);
     const int64_t t64 = (n + 63) / 64;
-    const int64_t tiles = t64 * (t64 + 1) / 2 * b.count;
-    if (tiles >= 400) return launch_cfg<P, 64, 1, 1, KU1, 1>(b, n, ld, st);
-    return launch_cfg<P, 64, 2, 2, KU4, 1>(b, n, ld, st);
+    const int64_t w64 = t64 * (t64 + 1) / 2 * b.count;
+    const bool fits48 = (n + 47) / 48 * 48 <= ld;
+    if constexpr (P == P_F64) {
+        if (fits48 && w64 < 300) return launch_cfg<P, 48, 1, 1, KU, 1, 4>(b, n, ld, st);
+        if (fits48 && w64 < 1800) return launch_cfg<P, 48, 1, 1, KU, 1, 1>(b, n, ld, st);
+        if (w64 >= 1800 && n <= 2500) return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st);
+        if (w64 < 400) return launch_cfg<P, 64, 1, 1, KU, 1, 4>(b, n, ld, st);
+        return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st);
+    } else if constexpr (P == P_F32) {
+        if (fits48 && w64 < 1800) return launch_cfg<P, 48, 1, 1, KU, 1, 2>(b, n, ld, st);
+        if (w64 < 1800 || n <= 2500) return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st);
+        return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st);
+    } else {
+        if (w64 < 300) return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st);
+        return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st);
+    }
 }
 
 }  // namespace

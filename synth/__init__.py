@@ -86,15 +86,32 @@ def batch_problems(count: int, seed: int = 3000, n_lo: int = 96, n_hi: int = 102
     return sizes.astype(np.int64), betas
 
 
+def _cholesky_qr2(torch, g):
+    """Orthogonal factor of G (positive-diagonal R) by two Cholesky QR passes; None on failure."""
+    q = g
+    for _ in range(2):
+        a = torch.matmul(q.transpose(-1, -2).contiguous(), q)
+        low, info = torch.linalg.cholesky_ex(a)
+        if bool((info != 0).any()):
+            return None
+        q = torch.linalg.solve_triangular(low.transpose(-1, -2).contiguous(), q, upper=True, left=False)
+    return q
+
+
 def hamiltonians_torch(sizes, law: str = "uniform", seed: int = 0, device="cuda"):
     """Many Hamiltonians assembled on ``device`` with torch (same recipe, faster at scale).
 
     The eigenvalues come from numpy's PCG64 (``seed``), in the order of
     ``sizes``; the Gaussian matrices from a torch generator on ``device``
     seeded with ``seed``, drawn size group by size group in increasing n.
-    Q = qr(G) with the signs of diag(R) folded in, H = (Q * lam) Q^T in
-    float64, symmetrised exactly.  Returns a list of ``(H, lam)`` with H a
-    contiguous float64 device tensor and lam a numpy array.
+    Q is the orthogonal factor of G with a positive diagonal R (the Haar
+    measure, as in :func:`haar_orthogonal`), computed by Cholesky QR applied
+    twice (R^T R = G^T G, Q = G R^-1, then once more on Q: orthogonal to
+    rounding, and much faster on a GPU than a Householder QR of many small
+    matrices); a group whose Cholesky factorisation fails falls back to
+    Householder QR.  H = (Q * lam) Q^T in float64, symmetrised exactly.
+    Returns a list of ``(H, lam)`` with H a contiguous float64 device tensor
+    and lam a numpy array.
     """
     import torch
 
@@ -107,10 +124,12 @@ def hamiltonians_torch(sizes, law: str = "uniform", seed: int = 0, device="cuda"
     for n in sorted(set(sizes)):
         idx = [i for i, v in enumerate(sizes) if v == n]
         g = torch.randn((len(idx), n, n), generator=gen, device=device, dtype=torch.float64)
-        q, r = torch.linalg.qr(g)
+        q = _cholesky_qr2(torch, g)
+        if q is None:
+            q, r = torch.linalg.qr(g)
+            q = q * torch.sign(torch.diagonal(r, dim1=-2, dim2=-1)).unsqueeze(-2)
+            del r
         del g
-        q = q * torch.sign(torch.diagonal(r, dim1=-2, dim2=-1)).unsqueeze(-2)
-        del r
         lam = torch.from_numpy(np.stack([lams[i] for i in idx])).to(device)
         h = torch.matmul(q * lam.unsqueeze(-2), q.transpose(-1, -2).contiguous())
         h = 0.5 * (h + h.transpose(-1, -2))
