@@ -93,6 +93,26 @@ def traffic_of(prec, n, order):
     return None
 
 
+def run_density_steps(cd, handle, H, beta, mu, order, opts, steps, warmup):
+    """Density at a given mu (no moments, no search): chebdm_density on a resident H."""
+    import torch
+
+    D = torch.empty_like(H)
+    for _ in range(warmup):
+        cd.chebdm_density(handle, H, beta, mu, order, opts, D=D)
+    torch.cuda.synchronize()
+    cd.chebdm_profile_enable(handle, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        cd.chebdm_density(handle, H, beta, mu, order, opts, D=D)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = cd.chebdm_profile_read(handle)
+    cd.chebdm_profile_enable(handle, False)
+    return dt, prof
+
+
 def roofline_of(prof, prec):
     """Matrix-product kernel: algorithmic flops / summed launch time vs the MFMA peak."""
     if prof["gemm_ms"] <= 0:
@@ -332,6 +352,18 @@ def main():
                          "gemm_frac_of_peak": r2["frac"] if r2 else None,
                          "gemm_tflops": r2["achieved"] if r2 else None,
                          "search_ms": round(p2["search_ms"] / steps, 3), "search_evals": i2["iters"]}
+        fixed = {}
+        for nn, pr in ((1000, "fp64"), (4000, "fp64"), (4000, "fp32")):
+            log(f"fixed mu: n={nn} prec={pr}")
+            hh = hs[nn]
+            mu_nn, _, _ = cd.chebdm_mu_search(handle, hh, beta, nn / 2.0, order, cd.make_opts(pr), want_density=False)
+            steps = 20 if nn <= 1000 else 5
+            d3, p3 = run_density_steps(cd, handle, hh, beta, mu_nn, order, cd.make_opts(pr), steps, 2)
+            r3 = roofline_of(p3, pr)
+            fixed[f"n{nn}_{pr}"] = {"dm_per_s": round(steps / d3, 3), "ms_per_step": round(1e3 * d3 / steps, 3),
+                                    "products": p3["gemm_products"] // steps,
+                                    "gemm_frac_of_peak": r3["frac"] if r3 else None}
+        result["fixed_mu"] = fixed
         del hs
             # fixed-mu density only (no ladder / moments / bisection)
         for key, row in rows.items():

@@ -155,6 +155,123 @@ __device__ __forceinline__ void upper_tile(int t, int T, int& I, int& J) {
     J = t - (i * T - i * (i - 1) / 2) + i;
 }
 
+// Tile (I, J), I <= J, of linear index t in a blocked order of the upper
+// triangle of a T x T tile grid: G x G super-blocks (those on or above the
+// diagonal) in row-major order, row-major tiles inside each (the diagonal
+// super-blocks hold only their upper triangle).  Consecutive indices then
+// cover a compact 2-D region, so tiles that run together on one XCD share
+// both their A row panels and their B panels in that XCD's L2.
+__device__ __forceinline__ void blocked_tile(int t, int T, int G, int& I, int& J) {
+    const int TS = (T + G - 1) / G;
+    for (int si = 0; si < TS; ++si) {
+        const int rows = T - si * G < G ? T - si * G : G;
+        const int diag = rows * (rows + 1) / 2;
+        if (t < diag) {
+            int i, j;
+            upper_tile(t, rows, i, j);
+            I = si * G + i;
+            J = si * G + j;
+            return;
+        }
+        t -= diag;
+        const int rest = rows * (T - (si + 1) * G > 0 ? T - (si + 1) * G : 0);   // super-blocks right of it
+        if (t < rest) {
+            // the row band's off-diagonal part, ordered super-block by super-block
+            for (int sj = si + 1; sj < TS; ++sj) {
+                const int cols = T - sj * G < G ? T - sj * G : G;
+                if (t < rows * cols) {
+                    I = si * G + t / cols;
+                    J = sj * G + t % cols;
+                    return;
+                }
+                t -= rows * cols;
+            }
+        }
+        t -= rest;
+    }
+    I = J = 0;   // not reached for t < T (T + 1) / 2
+}
+
+// Epilogue of one wave tile (FM x FN blocks of 16 x 16 at row0, col0):
+// Out = alpha*acc + beta*C + gamma*E + delta*I in float64, stored at (i, j) and (j, i).
+template <int P, int FM, int FN>
+__device__ __forceinline__ void tile_epilogue(const GemmDesc<typename Traits<P>::T>& g,
+                                              const typename Traits<P>::Acc (&acc)[FM][FN], int64_t n, int64_t ld,
+                                              int64_t row0, int64_t col0, bool diag_tile, int lr, int lq) {
+    using T = typename Traits<P>::T;
+    // Output layout of a 16 x 16 block: lane (lr, lq) holds column lr and, in its
+    // r-th register, row 4*lq + r for the f32 and bf16 MFMAs but row lq + 4*r for
+    // v_mfma_f64_16x16x4f64 (checked on gfx950).
+    //
+    // C and E are workspace matrices (ld x ld, zero padded), so every tile
+    // position is in bounds: they are read in one unpredicated batch and only
+    // the stores are predicated.
+    const double alpha = g.alpha, beta = g.beta, gamma = g.gamma, delta = g.delta;
+    auto row_of = [&](int f, int r) -> int64_t {
+        return row0 + f * 16 + (P == P_F64 ? lq + 4 * r : lq * 4 + r);
+    };
+    double v[FM][FN][4];
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int q = 0; q < FN; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[f][q][r] = alpha * (double)acc[f][q][r];
+    if (g.C) {
+        const T* __restrict__ C = g.C;
+        T cv[FM][FN][4];
+#pragma unroll
+        for (int f = 0; f < FM; ++f)
+#pragma unroll
+            for (int q = 0; q < FN; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) cv[f][q][r] = C[row_of(f, r) * ld + col0 + q * 16 + lr];
+#pragma unroll
+        for (int f = 0; f < FM; ++f)
+#pragma unroll
+            for (int q = 0; q < FN; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[f][q][r] += beta * (double)cv[f][q][r];
+    }
+    if (g.E) {
+        const T* __restrict__ E = g.E;
+        T ev[FM][FN][4];
+#pragma unroll
+        for (int f = 0; f < FM; ++f)
+#pragma unroll
+            for (int q = 0; q < FN; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ev[f][q][r] = E[row_of(f, r) * ld + col0 + q * 16 + lr];
+#pragma unroll
+        for (int f = 0; f < FM; ++f)
+#pragma unroll
+            for (int q = 0; q < FN; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[f][q][r] += gamma * (double)ev[f][q][r];
+    }
+    const int64_t ldo = g.ld_out;
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int q = 0; q < FN; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = row_of(f, r);
+                const int64_t col = col0 + q * 16 + lr;
+                if (row < n && col < n && !(diag_tile && row > col)) {
+                    const double x = v[f][q][r] + (row == col ? delta : 0.0);
+                    const int64_t o = row * ldo + col, om = col * ldo + row;
+                    if (g.out_f64) {
+                        static_cast<double*>(g.Out)[o] = x;
+                        if (row != col) static_cast<double*>(g.Out)[om] = x;
+                    } else {
+                        static_cast<T*>(g.Out)[o] = (T)x;
+                        if (row != col) static_cast<T*>(g.Out)[om] = (T)x;
+                    }
+                }
+            }
+}
+
 // One BM x BM tile (ti, tj), ti <= tj, of the symmetric product g, computed by
 // WGM x WGN x SK wavefronts of the calling work-group: WGM x WGN wave tiles of
 // (BM/WGM) x (BM/WGN), each split over SK wavefronts along K (contiguous K
@@ -239,77 +356,7 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<typename Traits<P>::T>&
                 for (int q = 0; q < FN; ++q) acc[f][q] += red[j][wave][f * FN + q][lane];
     }
 
-    // Output layout of a 16 x 16 block: lane (lr, lq) holds column lr and, in its
-    // r-th register, row 4*lq + r for the f32 and bf16 MFMAs but row lq + 4*r for
-    // v_mfma_f64_16x16x4f64 (checked on gfx950).
-    //
-    // C and E are workspace matrices (ld x ld, zero padded), so every tile
-    // position is in bounds: they are read in one unpredicated batch and only
-    // the stores are predicated.
-    const double alpha = g.alpha, beta = g.beta, gamma = g.gamma, delta = g.delta;
-    auto row_of = [&](int f, int r) -> int64_t {
-        return row0 + f * 16 + (P == P_F64 ? lq + 4 * r : lq * 4 + r);
-    };
-    double v[FM][FN][4];
-#pragma unroll
-    for (int f = 0; f < FM; ++f)
-#pragma unroll
-        for (int q = 0; q < FN; ++q)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) v[f][q][r] = alpha * (double)acc[f][q][r];
-    if (g.C) {
-        const T* __restrict__ C = g.C;
-        T cv[FM][FN][4];
-#pragma unroll
-        for (int f = 0; f < FM; ++f)
-#pragma unroll
-            for (int q = 0; q < FN; ++q)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) cv[f][q][r] = C[row_of(f, r) * ld + col0 + q * 16 + lr];
-#pragma unroll
-        for (int f = 0; f < FM; ++f)
-#pragma unroll
-            for (int q = 0; q < FN; ++q)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) v[f][q][r] += beta * (double)cv[f][q][r];
-    }
-    if (g.E) {
-        const T* __restrict__ E = g.E;
-        T ev[FM][FN][4];
-#pragma unroll
-        for (int f = 0; f < FM; ++f)
-#pragma unroll
-            for (int q = 0; q < FN; ++q)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) ev[f][q][r] = E[row_of(f, r) * ld + col0 + q * 16 + lr];
-#pragma unroll
-        for (int f = 0; f < FM; ++f)
-#pragma unroll
-            for (int q = 0; q < FN; ++q)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) v[f][q][r] += gamma * (double)ev[f][q][r];
-    }
-    const int64_t ldo = g.ld_out;
-#pragma unroll
-    for (int f = 0; f < FM; ++f)
-#pragma unroll
-        for (int q = 0; q < FN; ++q)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = row_of(f, r);
-                const int64_t col = col0 + q * 16 + lr;
-                if (row < n && col < n && !(diag_tile && row > col)) {
-                    const double x = v[f][q][r] + (row == col ? delta : 0.0);
-                    const int64_t o = row * ldo + col, om = col * ldo + row;
-                    if (g.out_f64) {
-                        static_cast<double*>(g.Out)[o] = x;
-                        if (row != col) static_cast<double*>(g.Out)[om] = x;
-                    } else {
-                        static_cast<T*>(g.Out)[o] = (T)x;
-                        if (row != col) static_cast<T*>(g.Out)[om] = (T)x;
-                    }
-                }
-            }
+    tile_epilogue<P, FM, FN>(g, acc, n, ld, row0, col0, diag_tile, lr, lq);
 }
 
 

@@ -65,25 +65,27 @@ __device__ __forceinline__ void tile_of_block(int ntri, int& t, int& z) {
 
 // BM x BM workgroup tiles, blockIdx.x enumerating the upper triangle, blockIdx.z
 // the products of a grouped launch.
-template <int P, int BM, int WGM, int WGN, int KU, int XCD, int SK = 1>
+// GB > 0: tiles in blocked_tile order with GB x GB super-blocks; 0: row-major.
+template <int P, int BM, int WGM, int WGN, int KU, int XCD, int SK = 1, int GB = 0>
 __global__ void __launch_bounds__(64 * WGM * WGN * SK)
 k_gemm(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, int64_t kpad, int ntile) {
     int tlin, z;
     tile_of_block<XCD>(ntile * (ntile + 1) / 2, tlin, z);
     int ti, tj;
-    upper_tile(tlin, ntile, ti, tj);
+    if constexpr (GB > 0) blocked_tile(tlin, ntile, GB, ti, tj);
+    else upper_tile(tlin, ntile, ti, tj);
     gemm_tile<P, BM, WGM, WGN, KU, SK>(batch.d[z], n, ld, kpad, ti, tj);
 }
 
-template <int P, int BM, int WGM, int WGN, int KU, int XCD, int SK = 1>
+template <int P, int BM, int WGM, int WGN, int KU, int XCD, int SK = 1, int GB = 0>
 hipError_t launch_cfg(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int64_t ld, hipStream_t st) {
     constexpr int CH = 4 * KU;
     const int64_t kpad = (n + 2 * CH - 1) / (2 * CH) * (2 * CH);
     if (kpad > ld || (n + BM - 1) / BM * BM > ld) return hipErrorInvalidValue;
     const int ntile = (int)((n + BM - 1) / BM);
     dim3 grid((unsigned)(ntile * (ntile + 1) / 2), 1, (unsigned)b.count);
-    hipLaunchKernelGGL((k_gemm<P, BM, WGM, WGN, KU, XCD, SK>), grid, dim3(64 * WGM * WGN * SK), 0, st, b, n, ld,
-                       kpad, ntile);
+    hipLaunchKernelGGL((k_gemm<P, BM, WGM, WGN, KU, XCD, SK, GB>), grid, dim3(64 * WGM * WGN * SK), 0, st, b, n,
+                       ld, kpad, ntile);
     return hipGetLastError();
 }
 

@@ -86,15 +86,21 @@ def batch_problems(count: int, seed: int = 3000, n_lo: int = 96, n_hi: int = 102
     return sizes.astype(np.int64), betas
 
 
-def _cholesky_qr2(torch, g):
-    """Orthogonal factor of G (positive-diagonal R) by two Cholesky QR passes; None on failure."""
+def _cholesky_qr2(torch, g, chunk: int = 16):
+    """Orthogonal factor of G (positive-diagonal R) by two Cholesky QR passes; None on failure.
+
+    The triangular solves run ``chunk`` matrices at a time (the batched BLAS
+    solve asks for workspace in proportion to the batch).
+    """
     q = g
     for _ in range(2):
         a = torch.matmul(q.transpose(-1, -2).contiguous(), q)
         low, info = torch.linalg.cholesky_ex(a)
         if bool((info != 0).any()):
             return None
-        q = torch.linalg.solve_triangular(low.transpose(-1, -2).contiguous(), q, upper=True, left=False)
+        up = low.transpose(-1, -2).contiguous()
+        q = torch.cat([torch.linalg.solve_triangular(up[i:i + chunk], q[i:i + chunk], upper=True, left=False)
+                       for i in range(0, q.shape[0], chunk)])
     return q
 
 
