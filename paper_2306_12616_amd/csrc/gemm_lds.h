@@ -1,0 +1,128 @@
+// LDS-staged tile routine for the split-bf16 precisions.
+//
+// The register-direct routine (gemm_tile) splits every float32 operand into
+// bf16 terms inside each wavefront, once per use, and streams its operands
+// from L2 per wavefront; for the split precisions that makes the VALU split
+// work and the operand traffic, not the MFMA units, the bound.  Here a
+// work-group of 2 x 2 wavefronts owns a 128 x 128 tile: per K step of 32 it
+// loads the 128-row A and B panels once (float32, 16-byte loads), splits each
+// element once into its bf16 terms, stores the terms in LDS, and every
+// wavefront reads its 64 x 64 operands from LDS (each panel row is used by two
+// wavefronts).  Same K order in both operands, same float32 accumulation and
+// the same fused epilogue as gemm_tile.
+#pragma once
+
+#include "gemm_tile.h"
+
+namespace chebdm {
+namespace {
+
+template <int P>
+struct SplitTerms;
+template <>
+struct SplitTerms<P_BF16X3> {
+    static constexpr int N = 2;
+};
+template <>
+struct SplitTerms<P_BF16X6> {
+    static constexpr int N = 3;
+};
+
+// One 128 x 128 tile (ti, tj), ti <= tj, by the calling 256-thread work-group.
+// kpad: K padded to a multiple of 32, kpad <= ld; rows ti*128 .. +127 and
+// tj*128 .. +127 must lie inside the ld x ld operands.
+template <int P, int PAD = 8>
+__device__ __forceinline__ void gemm_tile_lds(const GemmDesc<float>& g, int64_t n, int64_t ld, int64_t kpad, int ti,
+                                              int tj) {
+    static_assert(P == P_BF16X3 || P == P_BF16X6, "split-bf16 precisions only");
+    using Acc = f32x4;
+    constexpr int BM = 128, KC = 32, NT = SplitTerms<P>::N, RS = KC + PAD;
+    __shared__ __attribute__((aligned(16))) __bf16 lds[2][NT][BM][RS];
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lr = lane & 15, lq = lane >> 4;
+    const bool diag_tile = ti == tj;
+    const bool idle = diag_tile && wm > wn;   // this wave's 64 x 64 lies below the diagonal
+
+    // staging: thread -> row tid/2 of both panels, 16 consecutive k at (tid%2)*16
+    const int srow = tid >> 1, sk = (tid & 1) * 16;
+    const float* __restrict__ ga = g.A + ((int64_t)ti * BM + srow) * ld + sk;
+    const float* __restrict__ gb = g.B + ((int64_t)tj * BM + srow) * ld + sk;
+    f32x4 ra[4], rb[4];
+    auto gload = [&](int64_t k0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            ra[c] = *reinterpret_cast<const f32x4*>(ga + k0 + 4 * c);
+            rb[c] = *reinterpret_cast<const f32x4*>(gb + k0 + 4 * c);
+        }
+    };
+    auto put = [&](int which, const f32x4 (&r)[4]) {
+        float x[16];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) x[4 * c + t] = r[c][t];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            bf16x8 t0, t1, t2;
+            if constexpr (NT == 2) split_bf16(&x[8 * h], t0, t1);
+            else split3_bf16(&x[8 * h], t0, t1, t2);
+            *reinterpret_cast<bf16x8*>(&lds[which][0][srow][sk + 8 * h]) = t0;
+            *reinterpret_cast<bf16x8*>(&lds[which][1][srow][sk + 8 * h]) = t1;
+            if constexpr (NT == 3) *reinterpret_cast<bf16x8*>(&lds[which][2][srow][sk + 8 * h]) = t2;
+        }
+    };
+
+    Acc acc[4][4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[f][q] = Acc{};
+
+    const int64_t steps = kpad / KC;
+    gload(0);
+    put(0, ra);
+    put(1, rb);
+    __syncthreads();
+    for (int64_t s = 0; s < steps; ++s) {
+        gload((s + 1 < steps ? s + 1 : steps - 1) * KC);   // next panels in flight (clamped, no branch)
+        if (!idle) {
+            bf16x8 a[NT][4], b[NT][4];
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int f = 0; f < 4; ++f) {
+                    a[t][f] = *reinterpret_cast<const bf16x8*>(&lds[0][t][wm * 64 + f * 16 + lr][lq * 8]);
+                    b[t][f] = *reinterpret_cast<const bf16x8*>(&lds[1][t][wn * 64 + f * 16 + lr][lq * 8]);
+                }
+#pragma unroll
+            for (int f = 0; f < 4; ++f)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if constexpr (NT == 2) {
+                        acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][f], b[0][q], acc[f][q], 0, 0, 0);
+                        acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][f], b[1][q], acc[f][q], 0, 0, 0);
+                        acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][f], b[0][q], acc[f][q], 0, 0, 0);
+                    } else {
+                        acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][f], b[0][q], acc[f][q], 0, 0, 0);
+                        acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][f], b[2][q], acc[f][q], 0, 0, 0);
+                        acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][f], b[1][q], acc[f][q], 0, 0, 0);
+                        acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][f], b[0][q], acc[f][q], 0, 0, 0);
+                        acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][f], b[1][q], acc[f][q], 0, 0, 0);
+                        acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][f], b[0][q], acc[f][q], 0, 0, 0);
+                    }
+                }
+        }
+        __syncthreads();
+        put(0, ra);
+        put(1, rb);
+        __syncthreads();
+    }
+    if (!idle)
+        tile_epilogue<P, 4, 4>(g, acc, n, ld, (int64_t)ti * BM + wm * 64, (int64_t)tj * BM + wn * 64, diag_tile, lr,
+                               lq);
+}
+
+}  // namespace
+}  // namespace chebdm

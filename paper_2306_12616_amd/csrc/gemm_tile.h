@@ -210,48 +210,40 @@ __device__ __forceinline__ void tile_epilogue(const GemmDesc<typename Traits<P>:
     auto row_of = [&](int f, int r) -> int64_t {
         return row0 + f * 16 + (P == P_F64 ? lq + 4 * r : lq * 4 + r);
     };
-    double v[FM][FN][4];
+    const int64_t ldo = g.ld_out;
+    // one row of 16 x 16 blocks at a time: its C and E values are loaded in one
+    // batch, which keeps the live registers of the epilogue small
 #pragma unroll
-    for (int f = 0; f < FM; ++f)
+    for (int f = 0; f < FM; ++f) {
+        double v[FN][4];
 #pragma unroll
         for (int q = 0; q < FN; ++q)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) v[f][q][r] = alpha * (double)acc[f][q][r];
-    if (g.C) {
-        const T* __restrict__ C = g.C;
-        T cv[FM][FN][4];
-#pragma unroll
-        for (int f = 0; f < FM; ++f)
+            for (int r = 0; r < 4; ++r) v[q][r] = alpha * (double)acc[f][q][r];
+        if (g.C) {
+            const T* __restrict__ C = g.C;
+            T cv[FN][4];
 #pragma unroll
             for (int q = 0; q < FN; ++q)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) cv[f][q][r] = C[row_of(f, r) * ld + col0 + q * 16 + lr];
-#pragma unroll
-        for (int f = 0; f < FM; ++f)
+                for (int r = 0; r < 4; ++r) cv[q][r] = C[row_of(f, r) * ld + col0 + q * 16 + lr];
 #pragma unroll
             for (int q = 0; q < FN; ++q)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) v[f][q][r] += beta * (double)cv[f][q][r];
-    }
-    if (g.E) {
-        const T* __restrict__ E = g.E;
-        T ev[FM][FN][4];
-#pragma unroll
-        for (int f = 0; f < FM; ++f)
+                for (int r = 0; r < 4; ++r) v[q][r] += beta * (double)cv[q][r];
+        }
+        if (g.E) {
+            const T* __restrict__ E = g.E;
+            T ev[FN][4];
 #pragma unroll
             for (int q = 0; q < FN; ++q)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) ev[f][q][r] = E[row_of(f, r) * ld + col0 + q * 16 + lr];
-#pragma unroll
-        for (int f = 0; f < FM; ++f)
+                for (int r = 0; r < 4; ++r) ev[q][r] = E[row_of(f, r) * ld + col0 + q * 16 + lr];
 #pragma unroll
             for (int q = 0; q < FN; ++q)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) v[f][q][r] += gamma * (double)ev[f][q][r];
-    }
-    const int64_t ldo = g.ld_out;
-#pragma unroll
-    for (int f = 0; f < FM; ++f)
+                for (int r = 0; r < 4; ++r) v[q][r] += gamma * (double)ev[q][r];
+        }
 #pragma unroll
         for (int q = 0; q < FN; ++q)
 #pragma unroll
@@ -259,7 +251,7 @@ __device__ __forceinline__ void tile_epilogue(const GemmDesc<typename Traits<P>:
                 const int64_t row = row_of(f, r);
                 const int64_t col = col0 + q * 16 + lr;
                 if (row < n && col < n && !(diag_tile && row > col)) {
-                    const double x = v[f][q][r] + (row == col ? delta : 0.0);
+                    const double x = v[q][r] + (row == col ? delta : 0.0);
                     const int64_t o = row * ldo + col, om = col * ldo + row;
                     if (g.out_f64) {
                         static_cast<double*>(g.Out)[o] = x;
@@ -270,6 +262,7 @@ __device__ __forceinline__ void tile_epilogue(const GemmDesc<typename Traits<P>:
                     }
                 }
             }
+    }
 }
 
 // One BM x BM tile (ti, tj), ti <= tj, of the symmetric product g, computed by

@@ -38,6 +38,7 @@
 //           float32 accumulation (lo*lo, ~2^-16 relative, is dropped).
 //   bf16x6  three-way split x = hi + mid + lo; the six products down to 2^-16
 //           relative (hh, hm, mh, hl, lh, mm) keep about float32 accuracy.
+#include "gemm_lds.h"
 #include "gemm_tile.h"
 
 namespace chebdm {
@@ -86,6 +87,28 @@ hipError_t launch_cfg(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
     dim3 grid((unsigned)(ntile * (ntile + 1) / 2), 1, (unsigned)b.count);
     hipLaunchKernelGGL((k_gemm<P, BM, WGM, WGN, KU, XCD, SK, GB>), grid, dim3(64 * WGM * WGN * SK), 0, st, b, n,
                        ld, kpad, ntile);
+    return hipGetLastError();
+}
+
+// Split-bf16 products with LDS staging: 128 x 128 tiles, 2 x 2 wavefronts.
+template <int P, int XCD, int GB>
+__global__ void __launch_bounds__(256)
+k_gemm_lds(const GemmBatch<float> batch, int64_t n, int64_t ld, int64_t kpad, int ntile) {
+    int tlin, z;
+    tile_of_block<XCD>(ntile * (ntile + 1) / 2, tlin, z);
+    int ti, tj;
+    if constexpr (GB > 0) blocked_tile(tlin, ntile, GB, ti, tj);
+    else upper_tile(tlin, ntile, ti, tj);
+    gemm_tile_lds<P>(batch.d[z], n, ld, kpad, ti, tj);
+}
+
+template <int P, int XCD, int GB>
+hipError_t launch_lds(const GemmBatch<float>& b, int64_t n, int64_t ld, hipStream_t st) {
+    const int64_t kpad = (n + 31) / 32 * 32;
+    const int ntile = (int)((n + 127) / 128);
+    if (kpad > ld || (int64_t)ntile * 128 > ld) return hipErrorInvalidValue;
+    dim3 grid((unsigned)(ntile * (ntile + 1) / 2), 1, (unsigned)b.count);
+    hipLaunchKernelGGL((k_gemm_lds<P, XCD, GB>), grid, dim3(256), 0, st, b, n, ld, kpad, ntile);
     return hipGetLastError();
 }
 
