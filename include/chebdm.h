@@ -42,7 +42,7 @@ extern "C" {
 typedef struct chebdm_ctx* chebdm_handle;
 
 /* Arithmetic of the matrix products (the bounds, coefficients, traces,
- * moments and the mu bisection are always float64). */
+ * moments and the mu search are always float64). */
 enum chebdm_prec {
     CHEBDM_FP64 = 0,   /* float64 MFMA products, float64 matrices            */
     CHEBDM_FP32 = 1,   /* float32 MFMA products, float32 matrices            */
@@ -79,7 +79,7 @@ enum chebdm_search {
 
 enum chebdm_status {
     CHEBDM_OK = 0,
-    CHEBDM_WARN_NOCONV = 1,       /* bisection stopped before |tr D - N_e| < tol */
+    CHEBDM_WARN_NOCONV = 1,       /* mu search stopped before |t - N_e| < tol    */
     CHEBDM_ERR_ARG = -1,          /* invalid argument                            */
     CHEBDM_ERR_HIP = -2,          /* a HIP runtime call failed                   */
     CHEBDM_ERR_OOM = -3,          /* workspace allocation failed                 */
@@ -93,7 +93,7 @@ typedef struct {
     int32_t giant_form;  /* enum chebdm_giant, default CHEBDM_GIANT_COMPOSITION    */
     int32_t k_override;  /* baby-step count k; 0 = ceil(sqrt(L+1))                 */
     int32_t n_quad;      /* quadrature nodes M for c_n; 0 = automatic rule         */
-    int32_t max_iter;    /* bisection sweep cap; 0 = 200                           */
+    int32_t max_iter;    /* cap on search steps (trace evaluations); 0 = 200       */
     int32_t baby_steps;  /* enum chebdm_baby, default CHEBDM_BABY_AUTO                */
     int32_t search;      /* enum chebdm_search of chebdm_mu_search, default BISECTION */
     double tol;          /* target |tr D - N_e| of the mu search; 0 = 1e-10        */
@@ -103,12 +103,12 @@ typedef struct {
     int32_t k, m;        /* baby-step count and block count, L + 1 <= k*m           */
     int32_t n_gemm;      /* matrix products executed                               */
     int32_t n_quad;      /* quadrature nodes M used for the coefficients           */
-    int32_t iters;       /* bisection sweeps (mu search)                           */
+    int32_t iters;       /* search steps after the bracket check (mu search)       */
     int32_t status;      /* same as the return value                               */
     double emin, emax;   /* spectral bounds used                                   */
     double mu;           /* chemical potential used (energy units)                 */
     double trace;        /* tr D in float64 (or t(mu) when no D was built)         */
-    double trace_err;    /* |t(mu) - N_e| of the bisection (mu search only)        */
+    double trace_err;    /* |t(mu) - N_e| of the search (mu search only)           */
 } chebdm_info;
 
 /* Fill *o with the defaults listed above. */
@@ -174,9 +174,11 @@ int chebdm_density(chebdm_handle h, const double* dH, int64_t n, int64_t ldh,
  * Chemical potential with tr D_L(mu) = n_elec, then (if dD != NULL) D at it.
  * The trace moments tau_n = tr T_n(H~), n <= L, come from the baby steps and
  * a ladder T_{2k}, ..., T_{(m-1)k} through 2 T_a T_b = T_{a+b} + T_{|a-b|}
- * (eq. "identity"); t(mu~) = sum_n c_n(mu~) tau_n is bisected on
- * mu~ in [-1, 1] (midpoint rule; stop when |t - n_elec| < tol, when the
- * bracket is narrower than 4 ulp, or after max_iter sweeps).
+ * (eq. "identity"); t(mu~) = sum_n c_n(mu~) tau_n is searched on
+ * mu~ in [-1, 1] by bisection (midpoint rule) or, with opts->search =
+ * CHEBDM_SEARCH_NEWTON, by safeguarded Newton; both stop when
+ * |t - n_elec| < tol, when the bracket is narrower than 4 ulp, or after
+ * max_iter steps.
  * Writes *mu_out (energy units, host).  0 < n_elec < n required.
  * Returns CHEBDM_WARN_NOCONV if the bracket collapsed before tol was met.
  * Errors: as chebdm_density, plus CHEBDM_ERR_BRACKET.
@@ -214,7 +216,7 @@ int chebdm_block_coeffs(chebdm_handle h, const double* c, int32_t order, int32_t
  * afterwards; the caller's pointers, beta and N_e are read from a table
  * uploaded before each replay, so the graph is reused across calls).  Per
  * problem it computes exactly what chebdm_mu_search computes (Gershgorin
- * bounds, sequential baby steps, ladder and Gram moments, bisection,
+ * bounds, sequential baby steps, ladder and Gram moments, the mu search,
  * composition-form giant steps); every product step of all problems is one
  * persistent launch over a list of (problem, tile) items.
  *
@@ -225,7 +227,7 @@ int chebdm_block_coeffs(chebdm_handle h, const double* c, int32_t order, int32_t
  *   rule asks for more reports CHEBDM_ERR_ARG in its status).  Allocates
  *   sum_p (k+m) ld_p^2 workspace elements (ld_p = round_up(n_p, 128)).
  * chebdm_batch_tune: the autotuner.  Times one product step for each
- *   candidate schedule on the plan's workspace (tile edge 64 or 32 per size
+ *   candidate schedule on the plan's workspace (tile edge 64, 48 or 32 per size
  *   bucket n <= 256 / 512 / 768 / larger; problems ordered by decreasing n or
  *   as given) and keeps the fastest.  cache_path (nullable): a text file of
  *   "key value" lines; a matching key is applied without timing, a new result
