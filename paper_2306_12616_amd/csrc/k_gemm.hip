@@ -30,9 +30,9 @@
 // without bounds checks and write only the n x n block, so the padding stays
 // zero and contributes nothing along K.
 //
-// Precisions:
-//   f64     v_mfma_f64_16x16x4f64, KU = 2 (one 16-byte double2 per lane and operand)
-//   f32     v_mfma_f32_16x16x4f32, KU = 4 (one float4)
+// Precisions (KU = k per lane and chunk, loaded as 16-byte vectors):
+//   f64     v_mfma_f64_16x16x4f64, KU = 4
+//   f32     v_mfma_f32_16x16x4f32, KU = 8
 //   bf16x3  v_mfma_f32_16x16x32_bf16 on hi/lo splits of float operands:
 //           x = hi + lo, hi = bf16(x), lo = bf16(x - hi); AB ~ hi*hi + hi*lo + lo*hi,
 //           float32 accumulation (lo*lo, ~2^-16 relative, is dropped).
@@ -78,6 +78,12 @@ k_gemm(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, int6
     gemm_tile<P, BM, WGM, WGN, KU, SK>(batch.d[z], n, ld, kpad, ti, tj);
 }
 
+// One wavefront per SIMD is faster than two for these register-direct tiles (measured: float32
+// 64-tiles at N = 4000, 118 vs 78 TFLOP/s; two resident tiles per SIMD double the L2 working
+// set).  Kernels whose registers would allow two are held to one by reserving LDS: a CU's
+// 160 KiB then holds at most four single-wavefront work-groups.
+constexpr unsigned kOneWavePerSimdLds = 40 * 1024;
+
 template <int P, int BM, int WGM, int WGN, int KU, int XCD, int SK = 1, int GB = 0>
 hipError_t launch_cfg(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int64_t ld, hipStream_t st) {
     constexpr int CH = 4 * KU;
@@ -85,8 +91,9 @@ hipError_t launch_cfg(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
     if (kpad > ld || (n + BM - 1) / BM * BM > ld) return hipErrorInvalidValue;
     const int ntile = (int)((n + BM - 1) / BM);
     dim3 grid((unsigned)(ntile * (ntile + 1) / 2), 1, (unsigned)b.count);
-    hipLaunchKernelGGL((k_gemm<P, BM, WGM, WGN, KU, XCD, SK, GB>), grid, dim3(64 * WGM * WGN * SK), 0, st, b, n,
-                       ld, kpad, ntile);
+    const unsigned lds = (WGM * WGN * SK == 1) ? kOneWavePerSimdLds : 0u;
+    hipLaunchKernelGGL((k_gemm<P, BM, WGM, WGN, KU, XCD, SK, GB>), grid, dim3(64 * WGM * WGN * SK), lds, st, b,
+                       n, ld, kpad, ntile);
     return hipGetLastError();
 }
 
@@ -142,6 +149,11 @@ hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
         if (w64 < 1800 || n <= 2500) return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st);
         return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st);
     } else {
+        // three-term split: LDS staging (each element split once per work-group) once there are
+        // >= 100 128-tiles (N = 4000: 394 -> 492 TFLOP/s of bf16 work; N = 2000, four products:
+        // 290 -> 474); the six-term split measured no better with it
+        const int64_t t128 = (n + 127) / 128;
+        if (P == P_BF16X3 && t128 * (t128 + 1) / 2 * b.count >= 100) return launch_lds<P, 1, 0>(b, n, ld, st);
         if (w64 < 300) return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st);
         return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st);
     }

@@ -97,6 +97,8 @@ FULL = [
     (1000, "gaussmix6", 512, 100.0, "fp32", 2000),
     (4000, "gaussmix6", 512, 100.0, "fp32", 2002),
     (4000, "gaussmix6", 512, 100.0, "bf16x3", 2002),
+    (1800, "uniform", 512, 100.0, "bf16x3", 2003),     # LDS-staged split products, ragged 128-tiles
+    (2000, "gaussmix6", 512, 100.0, "fp32", 2001),
     (5000, "highdos", 2048, 400.0, "bf16x6", 4000),
     (5000, "highdos", 2048, 400.0, "bf16x3", 4000),
     (5000, "highdos", 2048, 400.0, "fp32", 4000),
