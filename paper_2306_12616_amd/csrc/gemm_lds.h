@@ -29,12 +29,15 @@ struct SplitTerms<P_BF16X6> {
 };
 
 // One 128 x 128 tile (ti, tj), ti <= tj, by the calling 256-thread work-group.
-// kpad: K padded to a multiple of 32, kpad <= ld; rows ti*128 .. +127 and
+// kpad: K padded to a multiple of 2*32 = 64, kpad <= ld; rows ti*128 .. +127 and
 // tj*128 .. +127 must lie inside the ld x ld operands.
-template <int P, int PAD = 8>
+// DEPTH = 1: the panels of step s+1 are loaded while step s computes; DEPTH = 2:
+// those of step s+2 (two register stages, the loop body unrolled by two).
+template <int P, int DEPTH = 2, int PAD = 8>
 __device__ __forceinline__ void gemm_tile_lds(const GemmDesc<float>& g, int64_t n, int64_t ld, int64_t kpad, int ti,
                                               int tj) {
     static_assert(P == P_BF16X3 || P == P_BF16X6, "split-bf16 precisions only");
+    static_assert(DEPTH == 1 || DEPTH == 2, "prefetch depth 1 or 2");
     using Acc = f32x4;
     constexpr int BM = 128, KC = 32, NT = SplitTerms<P>::N, RS = KC + PAD;
     __shared__ __attribute__((aligned(16))) __bf16 lds[2][NT][BM][RS];
@@ -49,15 +52,19 @@ __device__ __forceinline__ void gemm_tile_lds(const GemmDesc<float>& g, int64_t 
     const int srow = tid >> 1, sk = (tid & 1) * 16;
     const float* __restrict__ ga = g.A + ((int64_t)ti * BM + srow) * ld + sk;
     const float* __restrict__ gb = g.B + ((int64_t)tj * BM + srow) * ld + sk;
-    f32x4 ra[4], rb[4];
-    auto gload = [&](int64_t k0) {
+    const int64_t steps = kpad / KC;
+    struct Stage {
+        f32x4 a[4], b[4];
+    };
+    auto gload = [&](Stage& r, int64_t s) {
+        const int64_t k0 = (s < steps ? s : steps - 1) * KC;   // clamped: no branch in the loop
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            ra[c] = *reinterpret_cast<const f32x4*>(ga + k0 + 4 * c);
-            rb[c] = *reinterpret_cast<const f32x4*>(gb + k0 + 4 * c);
+            r.a[c] = *reinterpret_cast<const f32x4*>(ga + k0 + 4 * c);
+            r.b[c] = *reinterpret_cast<const f32x4*>(gb + k0 + 4 * c);
         }
     };
-    auto put = [&](int which, const f32x4 (&r)[4]) {
+    auto put1 = [&](int which, const f32x4 (&r)[4]) {
         float x[16];
 #pragma unroll
         for (int c = 0; c < 4; ++c)
@@ -73,6 +80,10 @@ __device__ __forceinline__ void gemm_tile_lds(const GemmDesc<float>& g, int64_t 
             if constexpr (NT == 3) *reinterpret_cast<bf16x8*>(&lds[which][2][srow][sk + 8 * h]) = t2;
         }
     };
+    auto put = [&](const Stage& r) {
+        put1(0, r.a);
+        put1(1, r.b);
+    };
 
     Acc acc[4][4];
 #pragma unroll
@@ -80,48 +91,72 @@ __device__ __forceinline__ void gemm_tile_lds(const GemmDesc<float>& g, int64_t 
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[f][q] = Acc{};
 
-    const int64_t steps = kpad / KC;
-    gload(0);
-    put(0, ra);
-    put(1, rb);
-    __syncthreads();
-    for (int64_t s = 0; s < steps; ++s) {
-        gload((s + 1 < steps ? s + 1 : steps - 1) * KC);   // next panels in flight (clamped, no branch)
-        if (!idle) {
-            bf16x8 a[NT][4], b[NT][4];
+    auto compute = [&]() {
+        if (idle) return;
+        bf16x8 a[NT][4], b[NT][4];
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
+        for (int t = 0; t < NT; ++t)
 #pragma unroll
-                for (int f = 0; f < 4; ++f) {
-                    a[t][f] = *reinterpret_cast<const bf16x8*>(&lds[0][t][wm * 64 + f * 16 + lr][lq * 8]);
-                    b[t][f] = *reinterpret_cast<const bf16x8*>(&lds[1][t][wn * 64 + f * 16 + lr][lq * 8]);
+            for (int f = 0; f < 4; ++f) {
+                a[t][f] = *reinterpret_cast<const bf16x8*>(&lds[0][t][wm * 64 + f * 16 + lr][lq * 8]);
+                b[t][f] = *reinterpret_cast<const bf16x8*>(&lds[1][t][wn * 64 + f * 16 + lr][lq * 8]);
+            }
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if constexpr (NT == 2) {
+                    acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][f], b[0][q], acc[f][q], 0, 0, 0);
+                    acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][f], b[1][q], acc[f][q], 0, 0, 0);
+                    acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][f], b[0][q], acc[f][q], 0, 0, 0);
+                } else {
+                    acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][f], b[0][q], acc[f][q], 0, 0, 0);
+                    acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][f], b[2][q], acc[f][q], 0, 0, 0);
+                    acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][f], b[1][q], acc[f][q], 0, 0, 0);
+                    acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][f], b[0][q], acc[f][q], 0, 0, 0);
+                    acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][f], b[1][q], acc[f][q], 0, 0, 0);
+                    acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][f], b[0][q], acc[f][q], 0, 0, 0);
                 }
-#pragma unroll
-            for (int f = 0; f < 4; ++f)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if constexpr (NT == 2) {
-                        acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][f], b[0][q], acc[f][q], 0, 0, 0);
-                        acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][f], b[1][q], acc[f][q], 0, 0, 0);
-                        acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][f], b[0][q], acc[f][q], 0, 0, 0);
-                    } else {
-                        acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][f], b[0][q], acc[f][q], 0, 0, 0);
-                        acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][f], b[2][q], acc[f][q], 0, 0, 0);
-                        acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][f], b[1][q], acc[f][q], 0, 0, 0);
-                        acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][f], b[0][q], acc[f][q], 0, 0, 0);
-                        acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][f], b[1][q], acc[f][q], 0, 0, 0);
-                        acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][f], b[0][q], acc[f][q], 0, 0, 0);
-                    }
-                }
+            }
+    };
+
+    if constexpr (DEPTH == 1) {
+        Stage r;
+        gload(r, 0);
+        put(r);
+        __syncthreads();
+        for (int64_t s = 0; s < steps; ++s) {
+            gload(r, s + 1);
+            compute();
+            __syncthreads();
+            put(r);
+            __syncthreads();
         }
+    } else {
+        // steps is even (kpad is a multiple of 64)
+        Stage r0, r1;
+        gload(r0, 0);
+        gload(r1, 1);
+        put(r0);
         __syncthreads();
-        put(0, ra);
-        put(1, rb);
-        __syncthreads();
+        for (int64_t s = 0; s < steps; s += 2) {
+            gload(r0, s + 2);   // r0 was consumed: fetch two steps ahead
+            compute();          // step s
+            __syncthreads();
+            put(r1);            // step s + 1
+            __syncthreads();
+            gload(r1, s + 3);
+            compute();          // step s + 1
+            __syncthreads();
+            put(r0);            // step s + 2
+            __syncthreads();
+        }
     }
+    // one block row at a time: keeps the kernel within two wavefronts per SIMD, which
+    // lets two work-groups per CU alternate around their barriers
     if (!idle)
-        tile_epilogue<P, 4, 4>(g, acc, n, ld, (int64_t)ti * BM + wm * 64, (int64_t)tj * BM + wn * 64, diag_tile, lr,
-                               lq);
+        tile_epilogue<P, 4, 4, 1>(g, acc, n, ld, (int64_t)ti * BM + wm * 64, (int64_t)tj * BM + wn * 64, diag_tile,
+                                  lr, lq);
 }
 
 }  // namespace

@@ -194,74 +194,88 @@ __device__ __forceinline__ void blocked_tile(int t, int T, int G, int& I, int& J
 
 // Epilogue of one wave tile (FM x FN blocks of 16 x 16 at row0, col0):
 // Out = alpha*acc + beta*C + gamma*E + delta*I in float64, stored at (i, j) and (j, i).
-template <int P, int FM, int FN>
+// RB rows of 16 x 16 blocks are handled per batch: their C and E values are all
+// loaded before any is used (RB = FM: one batch for the whole tile; smaller RB
+// keeps fewer registers live).
+template <int P, int FM, int FN, int RB = FM>
 __device__ __forceinline__ void tile_epilogue(const GemmDesc<typename Traits<P>::T>& g,
                                               const typename Traits<P>::Acc (&acc)[FM][FN], int64_t n, int64_t ld,
                                               int64_t row0, int64_t col0, bool diag_tile, int lr, int lq) {
     using T = typename Traits<P>::T;
+    static_assert(FM % RB == 0, "row batches must divide the tile");
     // Output layout of a 16 x 16 block: lane (lr, lq) holds column lr and, in its
     // r-th register, row 4*lq + r for the f32 and bf16 MFMAs but row lq + 4*r for
     // v_mfma_f64_16x16x4f64 (checked on gfx950).
     //
     // C and E are workspace matrices (ld x ld, zero padded), so every tile
-    // position is in bounds: they are read in one unpredicated batch and only
-    // the stores are predicated.
+    // position is in bounds: they are read unpredicated and only the stores are
+    // predicated.
     const double alpha = g.alpha, beta = g.beta, gamma = g.gamma, delta = g.delta;
     auto row_of = [&](int f, int r) -> int64_t {
         return row0 + f * 16 + (P == P_F64 ? lq + 4 * r : lq * 4 + r);
     };
     const int64_t ldo = g.ld_out;
-    // one row of 16 x 16 blocks at a time: its C and E values are loaded in one
-    // batch, which keeps the live registers of the epilogue small
 #pragma unroll
-    for (int f = 0; f < FM; ++f) {
-        double v[FN][4];
+    for (int f0 = 0; f0 < FM; f0 += RB) {
+        double v[RB][FN][4];
 #pragma unroll
-        for (int q = 0; q < FN; ++q)
+        for (int f = 0; f < RB; ++f)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) v[q][r] = alpha * (double)acc[f][q][r];
+            for (int q = 0; q < FN; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[f][q][r] = alpha * (double)acc[f0 + f][q][r];
         if (g.C) {
             const T* __restrict__ C = g.C;
-            T cv[FN][4];
+            T cv[RB][FN][4];
 #pragma unroll
-            for (int q = 0; q < FN; ++q)
+            for (int f = 0; f < RB; ++f)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) cv[q][r] = C[row_of(f, r) * ld + col0 + q * 16 + lr];
+                for (int q = 0; q < FN; ++q)
 #pragma unroll
-            for (int q = 0; q < FN; ++q)
+                    for (int r = 0; r < 4; ++r) cv[f][q][r] = C[row_of(f0 + f, r) * ld + col0 + q * 16 + lr];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) v[q][r] += beta * (double)cv[q][r];
+            for (int f = 0; f < RB; ++f)
+#pragma unroll
+                for (int q = 0; q < FN; ++q)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) v[f][q][r] += beta * (double)cv[f][q][r];
         }
         if (g.E) {
             const T* __restrict__ E = g.E;
-            T ev[FN][4];
+            T ev[RB][FN][4];
 #pragma unroll
-            for (int q = 0; q < FN; ++q)
+            for (int f = 0; f < RB; ++f)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) ev[q][r] = E[row_of(f, r) * ld + col0 + q * 16 + lr];
+                for (int q = 0; q < FN; ++q)
 #pragma unroll
-            for (int q = 0; q < FN; ++q)
+                    for (int r = 0; r < 4; ++r) ev[f][q][r] = E[row_of(f0 + f, r) * ld + col0 + q * 16 + lr];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) v[q][r] += gamma * (double)ev[q][r];
+            for (int f = 0; f < RB; ++f)
+#pragma unroll
+                for (int q = 0; q < FN; ++q)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) v[f][q][r] += gamma * (double)ev[f][q][r];
         }
 #pragma unroll
-        for (int q = 0; q < FN; ++q)
+        for (int f = 0; f < RB; ++f)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = row_of(f, r);
-                const int64_t col = col0 + q * 16 + lr;
-                if (row < n && col < n && !(diag_tile && row > col)) {
-                    const double x = v[q][r] + (row == col ? delta : 0.0);
-                    const int64_t o = row * ldo + col, om = col * ldo + row;
-                    if (g.out_f64) {
-                        static_cast<double*>(g.Out)[o] = x;
-                        if (row != col) static_cast<double*>(g.Out)[om] = x;
-                    } else {
-                        static_cast<T*>(g.Out)[o] = (T)x;
-                        if (row != col) static_cast<T*>(g.Out)[om] = (T)x;
+            for (int q = 0; q < FN; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = row_of(f0 + f, r);
+                    const int64_t col = col0 + q * 16 + lr;
+                    if (row < n && col < n && !(diag_tile && row > col)) {
+                        const double x = v[f][q][r] + (row == col ? delta : 0.0);
+                        const int64_t o = row * ldo + col, om = col * ldo + row;
+                        if (g.out_f64) {
+                            static_cast<double*>(g.Out)[o] = x;
+                            if (row != col) static_cast<double*>(g.Out)[om] = x;
+                        } else {
+                            static_cast<T*>(g.Out)[o] = (T)x;
+                            if (row != col) static_cast<T*>(g.Out)[om] = (T)x;
+                        }
                     }
                 }
-            }
     }
 }
 
@@ -271,7 +285,7 @@ __device__ __forceinline__ void tile_epilogue(const GemmDesc<typename Traits<P>:
 // ranges in units of two chunks) whose partial sums are added through LDS in
 // a fixed order (deterministic) before the epilogue.  With SK > 1 the routine
 // ends in a work-group barrier, so every thread of the work-group must call it.
-template <int P, int BM, int WGM, int WGN, int KU, int SK = 1>
+template <int P, int BM, int WGM, int WGN, int KU, int SK = 1, int RB = 16>
 __device__ __forceinline__ void gemm_tile(const GemmDesc<typename Traits<P>::T>& g, int64_t n, int64_t ld,
                                           int64_t kpad, int ti, int tj) {
     using T = typename Traits<P>::T;
@@ -349,7 +363,7 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<typename Traits<P>::T>&
                 for (int q = 0; q < FN; ++q) acc[f][q] += red[j][wave][f * FN + q][lane];
     }
 
-    tile_epilogue<P, FM, FN>(g, acc, n, ld, row0, col0, diag_tile, lr, lq);
+    tile_epilogue<P, FM, FN, (RB < FM ? RB : FM)>(g, acc, n, ld, row0, col0, diag_tile, lr, lq);
 }
 
 

@@ -543,7 +543,6 @@ int batch_gemm_grid(int prec) {
         default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_gemm<P_BF16X6>, 64, 0); break;
     }
     if (e != hipSuccess || per < 1) per = 4;
-    if (per > 4) per = 4;   // one wavefront per SIMD: faster than two for these tiles (see k_gemm.hip)
     return cus * per;
 }
 

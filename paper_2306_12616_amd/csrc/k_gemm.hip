@@ -67,7 +67,7 @@ __device__ __forceinline__ void tile_of_block(int ntri, int& t, int& z) {
 // BM x BM workgroup tiles, blockIdx.x enumerating the upper triangle, blockIdx.z
 // the products of a grouped launch.
 // GB > 0: tiles in blocked_tile order with GB x GB super-blocks; 0: row-major.
-template <int P, int BM, int WGM, int WGN, int KU, int XCD, int SK = 1, int GB = 0>
+template <int P, int BM, int WGM, int WGN, int KU, int XCD, int SK = 1, int GB = 0, int RB = 16>
 __global__ void __launch_bounds__(64 * WGM * WGN * SK)
 k_gemm(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, int64_t kpad, int ntile) {
     int tlin, z;
@@ -75,30 +75,23 @@ k_gemm(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, int6
     int ti, tj;
     if constexpr (GB > 0) blocked_tile(tlin, ntile, GB, ti, tj);
     else upper_tile(tlin, ntile, ti, tj);
-    gemm_tile<P, BM, WGM, WGN, KU, SK>(batch.d[z], n, ld, kpad, ti, tj);
+    gemm_tile<P, BM, WGM, WGN, KU, SK, RB>(batch.d[z], n, ld, kpad, ti, tj);
 }
 
-// One wavefront per SIMD is faster than two for these register-direct tiles (measured: float32
-// 64-tiles at N = 4000, 118 vs 78 TFLOP/s; two resident tiles per SIMD double the L2 working
-// set).  Kernels whose registers would allow two are held to one by reserving LDS: a CU's
-// 160 KiB then holds at most four single-wavefront work-groups.
-constexpr unsigned kOneWavePerSimdLds = 40 * 1024;
-
-template <int P, int BM, int WGM, int WGN, int KU, int XCD, int SK = 1, int GB = 0>
+template <int P, int BM, int WGM, int WGN, int KU, int XCD, int SK = 1, int GB = 0, int RB = 16>
 hipError_t launch_cfg(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int64_t ld, hipStream_t st) {
     constexpr int CH = 4 * KU;
     const int64_t kpad = (n + 2 * CH - 1) / (2 * CH) * (2 * CH);
     if (kpad > ld || (n + BM - 1) / BM * BM > ld) return hipErrorInvalidValue;
     const int ntile = (int)((n + BM - 1) / BM);
     dim3 grid((unsigned)(ntile * (ntile + 1) / 2), 1, (unsigned)b.count);
-    const unsigned lds = (WGM * WGN * SK == 1) ? kOneWavePerSimdLds : 0u;
-    hipLaunchKernelGGL((k_gemm<P, BM, WGM, WGN, KU, XCD, SK, GB>), grid, dim3(64 * WGM * WGN * SK), lds, st, b,
+    hipLaunchKernelGGL((k_gemm<P, BM, WGM, WGN, KU, XCD, SK, GB, RB>), grid, dim3(64 * WGM * WGN * SK), 0, st, b,
                        n, ld, kpad, ntile);
     return hipGetLastError();
 }
 
 // Split-bf16 products with LDS staging: 128 x 128 tiles, 2 x 2 wavefronts.
-template <int P, int XCD, int GB>
+template <int P, int XCD, int GB, int DEPTH>
 __global__ void __launch_bounds__(256)
 k_gemm_lds(const GemmBatch<float> batch, int64_t n, int64_t ld, int64_t kpad, int ntile) {
     int tlin, z;
@@ -106,16 +99,16 @@ k_gemm_lds(const GemmBatch<float> batch, int64_t n, int64_t ld, int64_t kpad, in
     int ti, tj;
     if constexpr (GB > 0) blocked_tile(tlin, ntile, GB, ti, tj);
     else upper_tile(tlin, ntile, ti, tj);
-    gemm_tile_lds<P>(batch.d[z], n, ld, kpad, ti, tj);
+    gemm_tile_lds<P, DEPTH>(batch.d[z], n, ld, kpad, ti, tj);
 }
 
-template <int P, int XCD, int GB>
+template <int P, int XCD, int GB, int DEPTH = 2>
 hipError_t launch_lds(const GemmBatch<float>& b, int64_t n, int64_t ld, hipStream_t st) {
-    const int64_t kpad = (n + 31) / 32 * 32;
+    const int64_t kpad = (n + 63) / 64 * 64;
     const int ntile = (int)((n + 127) / 128);
     if (kpad > ld || (int64_t)ntile * 128 > ld) return hipErrorInvalidValue;
     dim3 grid((unsigned)(ntile * (ntile + 1) / 2), 1, (unsigned)b.count);
-    hipLaunchKernelGGL((k_gemm_lds<P, XCD, GB>), grid, dim3(256), 0, st, b, n, ld, kpad, ntile);
+    hipLaunchKernelGGL((k_gemm_lds<P, XCD, GB, DEPTH>), grid, dim3(256), 0, st, b, n, ld, kpad, ntile);
     return hipGetLastError();
 }
 
@@ -153,7 +146,7 @@ hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
         // >= 100 128-tiles (N = 4000: 394 -> 492 TFLOP/s of bf16 work; N = 2000, four products:
         // 290 -> 474); the six-term split measured no better with it
         const int64_t t128 = (n + 127) / 128;
-        if (P == P_BF16X3 && t128 * (t128 + 1) / 2 * b.count >= 100) return launch_lds<P, 1, 0>(b, n, ld, st);
+        if (P == P_BF16X3 && t128 * (t128 + 1) / 2 * b.count >= 100) return launch_lds<P, 1, 0, 1>(b, n, ld, st);
         if (w64 < 300) return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st);
         return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st);
     }
