@@ -142,11 +142,12 @@ hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
         if (w64 < 1800 || n <= 2500) return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st);
         return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st);
     } else {
-        // three-term split: LDS staging (each element split once per work-group) once there are
-        // >= 100 128-tiles (N = 4000: 394 -> 492 TFLOP/s of bf16 work; N = 2000, four products:
-        // 290 -> 474); the six-term split measured no better with it
-        const int64_t t128 = (n + 127) / 128;
-        if (P == P_BF16X3 && t128 * (t128 + 1) / 2 * b.count >= 100) return launch_lds<P, 1, 0, 1>(b, n, ld, st);
+        // LDS staging (each element split once per work-group, panels two K steps ahead) once
+        // there are >= 100 128-tiles: three-term split at N = 4000 390 -> 563 TFLOP/s of bf16
+        // work, N = 2000 four products 289 -> 532; the six-term split gains only with several
+        // products per launch (N = 2000, four: 498 -> 688; N = 4000 single: 749 vs 709)
+        const int64_t t128 = (n + 127) / 128, w128 = t128 * (t128 + 1) / 2 * b.count;
+        if (w128 >= 100 && (P == P_BF16X3 || b.count >= 2)) return launch_lds<P, 1, 0, 2>(b, n, ld, st);
         if (w64 < 300) return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st);
         return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st);
     }

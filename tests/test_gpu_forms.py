@@ -133,3 +133,18 @@ def test_full_size_mu_search_sampled_rows(cd, handle, case):
         assert info["status"] == 0 and err <= 1e-10 and t_err <= 1e-8
     else:
         assert err <= LOOSE.get((prec, order), 1e-5) and t_err <= 1e-5 * n
+
+
+def test_six_term_split_grouped_stage_launches(cd, handle):
+    # Algorithm-1 stages put several products in one launch: at this size the six-term
+    # split then runs on the LDS-staged kernel (ragged 128-tiles: 1800 = 14 * 128 + 8)
+    n, order, beta, seed = 1800, 512, 100.0, 2004
+    h, q, lam = synth.hamiltonian(n, "gaussmix6", seed=seed)
+    mu, D, info = cd.chebdm_mu_search(handle, _dev(h), beta, n / 2, order, cd.make_opts("bf16x6", baby="stages"))
+    torch.cuda.synchronize()
+    rows = np.array([0, 1, 127, 128, 900, n - 9, n - 1])
+    ref = _oracle_rows(q, lam, rows, order, beta, mu, info["emin"], info["emax"], info["n_quad"])
+    err = float(np.max(np.abs(D[rows].cpu().numpy() - ref)))
+    _say(f"  bf16x6 stages n={n}: max|D-D_oracle|(rows)={err:.3e} status={info['status']}")
+    assert err <= 1e-5
+    assert abs(info["trace"] - n / 2) <= 1e-5 * n
