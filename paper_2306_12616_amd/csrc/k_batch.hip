@@ -47,9 +47,6 @@ k_batch_gemm(const GemmDesc<typename Traits<P>::T>* __restrict__ descs, const Ba
         if (gm.tile == 64) {
             const int64_t kpad = (gm.n + 8 * KU64 - 1) / (8 * KU64) * (8 * KU64);
             gemm_tile<P, 64, 1, 1, KU64>(g, gm.n, gm.ld, kpad, ti, tj);
-        } else if (gm.tile == 48) {
-            const int64_t kpad = (gm.n + 8 * KU64 - 1) / (8 * KU64) * (8 * KU64);
-            gemm_tile<P, 48, 1, 1, KU64>(g, gm.n, gm.ld, kpad, ti, tj);
         } else {
             const int64_t kpad = (gm.n + 8 * KU32 - 1) / (8 * KU32) * (8 * KU32);
             gemm_tile<P, 32, 1, 1, KU32>(g, gm.n, gm.ld, kpad, ti, tj);
