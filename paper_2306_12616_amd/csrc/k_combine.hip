@@ -15,6 +15,7 @@
 // matrices are widened to float64 first so the moments keep float64 sums.
 // Per-workgroup partials are folded in a fixed order (deterministic).
 #include "internal.h"
+#include "reduce.h"
 
 namespace chebdm {
 
@@ -174,14 +175,17 @@ k_gram_partial(const PtrList<T> lm, int nl, const PtrList<T> tm, int nt, int64_t
     }
 }
 
-__global__ void k_gram_final(const double* __restrict__ partial, int nblocks, int nl, int nt,
-                             double* __restrict__ G) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= nl * nt) return;
+// G[l][i] = sum over the blocks' partials: one wavefront per entry, lane j adding blocks
+// j, j+64, ... in order, then a fixed butterfly across the lanes (deterministic).
+__global__ void __launch_bounds__(256)
+k_gram_final(const double* __restrict__ partial, int nblocks, int nl, int nt, double* __restrict__ G) {
+    const int idx = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (idx >= nl * nt) return;   // whole wavefronts leave together
     const int l = idx / nt, i = idx % nt;
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * kGramMax * kGramMax + l * kGramMax + i];
-    G[idx] = s;
+    for (int b = lane; b < nblocks; b += 64) s += partial[(int64_t)b * kGramMax * kGramMax + l * kGramMax + i];
+    s = wave_sum(s);
+    if (lane == 0) G[idx] = s;
 }
 
 template <typename T, int FM, int FN>
@@ -241,7 +245,7 @@ hipError_t launch_gram(const T* const* lmats, int nl, const T* const* tmats, int
     if (fm == 1) launch_gram_fm<T, 1>(fn, L, nl, Tm, nt, nchunk, (int)nblocks, partial, st);
     else if (fm == 2) launch_gram_fm<T, 2>(fn, L, nl, Tm, nt, nchunk, (int)nblocks, partial, st);
     else launch_gram_fm<T, 3>(fn, L, nl, Tm, nt, nchunk, (int)nblocks, partial, st);
-    hipLaunchKernelGGL(k_gram_final, dim3((unsigned)((nl * nt + 255) / 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_gram_final, dim3((unsigned)((nl * nt + 3) / 4)), dim3(256), 0, st,
                        (const double*)partial, (int)nblocks, nl, nt, G);
     return hipGetLastError();
 }
