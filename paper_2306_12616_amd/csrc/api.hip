@@ -300,42 +300,50 @@ void* rslot(chebdm_handle h, const Plan& pl, int l) { return slot(h, pl, pl.k + 
 // Baby steps T_2..T_k in the stages of Algorithm 1: stage 1 makes T_2; stage
 // s >= 2 makes T_{2^{s-2}+i} and T_{2^{s-1}+i} from already known T's.  The
 // products of one stage are independent and go out as one grouped launch.
-int baby_steps(chebdm_handle h, const Plan& pl, int* n_gemm) {
-    if (pl.k < 2) return 0;
-    Chain ch(h, pl, n_gemm);
-    if (pl.baby == CHEBDM_BABY_SEQUENTIAL) {
-        // T_{i+1} = 2 T_1 T_i - T_{i-1}, T_0 = I
-        for (int i = 1; i < pl.k; ++i) {
-            ch.add(tslot(h, pl, 1), tslot(h, pl, i), i == 1 ? nullptr : tslot(h, pl, i - 1), -1.0, nullptr, 0.0,
-                   2.0, i == 1 ? -1.0 : 0.0, tslot(h, pl, i + 1), pl.ld, 0);
+// P_2(Y) .. P_K(Y) from P_1 = Y and P_0 = I for the Chebyshev polynomials P_i = T_i of a
+// symmetric Y, where slot(i) holds P_i (i >= 1).  Sequential: P_{i+1} = 2 Y P_i - P_{i-1}.
+// Stages (Algorithm 1, Sec. III.B): stage s forms P_{v+1..2v} (v = 2^{s-1}) from P_1..P_v by
+// P_{i+u} = 2 P_i P_u - P_{i-u} and P_{i+v} = 2 P_v P_i - P_{v-i} (u = v/2, u < i <= v); the
+// products of a stage are independent and go out as one grouped launch.
+template <class Slot>
+int chebyshev_powers(Chain& ch, const Plan& pl, Slot slot, int K, bool stages) {
+    if (K < 2) return 0;
+    if (!stages) {
+        for (int i = 1; i < K; ++i) {
+            ch.add(slot(1), slot(i), i == 1 ? nullptr : slot(i - 1), -1.0, nullptr, 0.0, 2.0, i == 1 ? -1.0 : 0.0,
+                   slot(i + 1), pl.ld, 0);
             CHECK(ch.flush());
         }
         return 0;
     }
-    // stage 1: T_2 = 2 T_1 T_1 - T_0
-    ch.add(tslot(h, pl, 1), tslot(h, pl, 1), nullptr, 0.0, nullptr, 0.0, 2.0, -1.0, tslot(h, pl, 2), pl.ld, 0);
+    // stage 1: P_2 = 2 P_1 P_1 - P_0
+    ch.add(slot(1), slot(1), nullptr, 0.0, nullptr, 0.0, 2.0, -1.0, slot(2), pl.ld, 0);
     CHECK(ch.flush());
     for (int s = 2;; ++s) {
         const int u = 1 << (s - 2), v = 1 << (s - 1);
-        if (u + 1 + u > pl.k && v + u + 1 > pl.k) break;
+        if (u + 1 + u > K && v + u + 1 > K) break;
         for (int i = u + 1; i <= v; ++i)
-            if (i + u <= pl.k) {
-                // T_{i+u} = 2 T_i T_u - T_{i-u}
+            if (i + u <= K) {
                 const int r = i - u;
-                ch.add(tslot(h, pl, i), tslot(h, pl, u), r == 0 ? nullptr : tslot(h, pl, r), -1.0, nullptr, 0.0,
-                       2.0, r == 0 ? -1.0 : 0.0, tslot(h, pl, i + u), pl.ld, 0);
+                ch.add(slot(i), slot(u), r == 0 ? nullptr : slot(r), -1.0, nullptr, 0.0, 2.0, r == 0 ? -1.0 : 0.0,
+                       slot(i + u), pl.ld, 0);
             }
         for (int i = u + 1; i <= v; ++i)
-            if (i + v <= pl.k) {
-                // T_{i+v} = 2 T_v T_i - T_{v-i}
+            if (i + v <= K) {
                 const int r = v - i;
-                ch.add(tslot(h, pl, v), tslot(h, pl, i), r == 0 ? nullptr : tslot(h, pl, r), -1.0, nullptr, 0.0,
-                       2.0, r == 0 ? -1.0 : 0.0, tslot(h, pl, i + v), pl.ld, 0);
+                ch.add(slot(v), slot(i), r == 0 ? nullptr : slot(r), -1.0, nullptr, 0.0, 2.0, r == 0 ? -1.0 : 0.0,
+                       slot(i + v), pl.ld, 0);
             }
         CHECK(ch.flush());
-        if (v >= pl.k) break;
+        if (v >= K) break;
     }
     return 0;
+}
+
+int baby_steps(chebdm_handle h, const Plan& pl, int* n_gemm) {
+    Chain ch(h, pl, n_gemm);
+    return chebyshev_powers(ch, pl, [&](int i) -> void* { return tslot(h, pl, i); }, pl.k,
+                            pl.baby == CHEBDM_BABY_STAGES);
 }
 
 // Ladder T_{2k}, ..., T_{lmax k} (T_{lk} in R slot l-2) and the moments tau_0..tau_L.
@@ -344,15 +352,10 @@ int moments_on_device(chebdm_handle h, const Plan& pl, int* n_gemm) {
     int lmax = (L >= 1) ? (L - 1) / k : 0;
     if (lmax > pl.m - 1) lmax = pl.m - 1;
     auto lptr = [&](int l) -> void* { return l == 1 ? tslot(h, pl, k) : rslot(h, pl, l - 2); };
+    // the ladder T_{lk} = T_l(T_k) is the same Chebyshev recurrence in Y = T_k, so it takes the
+    // baby steps' schedule (stage-parallel or sequential)
     Chain ch(h, pl, n_gemm);
-    for (int l = 1; l + 1 <= lmax; ++l) {
-        // T_{(l+1)k} = 2 T_k T_{lk} - T_{(l-1)k}
-        if (l == 1)
-            ch.add(tslot(h, pl, k), tslot(h, pl, k), nullptr, 0.0, nullptr, 0.0, 2.0, -1.0, lptr(2), pl.ld, 0);
-        else
-            ch.add(tslot(h, pl, k), lptr(l), lptr(l - 1), -1.0, nullptr, 0.0, 2.0, 0.0, lptr(l + 1), pl.ld, 0);
-        CHECK(ch.flush());
-    }
+    CHECK(chebyshev_powers(ch, pl, lptr, lmax, pl.baby == CHEBDM_BABY_STAGES));
     const int64_t stride = pl.ld * pl.ld;
     HIP_TRY(launch_traces(tslot(h, pl, 1), stride, k, pl.n, pl.ld, pl.elem == 8, h->trb, h->stream));
     if (lmax >= 1) {
