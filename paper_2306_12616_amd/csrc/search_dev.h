@@ -30,18 +30,32 @@ namespace {
 // The nodes are ordered in x, so whole wavefronts skip the exponential except near mu~.
 constexpr double kSat = 50.0;
 
+// Nodes j = threadIdx.x + i NT in increasing i; the loads of U consecutive i are issued
+// together (the search is a chain of dependent passes, so load latency is what it waits on).
+// Slots past M add w = 0 with an in-range x, which leaves the sum unchanged.
 template <int NT, bool SLOPE>
 __device__ __forceinline__ void trace_pass(double mu_s, const double* __restrict__ w, const double* __restrict__ x,
                                            int64_t M, double beta_s, double* smem, double& t, double& dt) {
+    constexpr int U = 4;
     double acc = 0.0, accd = 0.0;
-    for (int64_t j = threadIdx.x; j < M; j += NT) {
-        const double z = beta_s * (x[j] - mu_s);
-        if (z < -kSat) {
-            acc += w[j];
-        } else if (z <= kSat) {
-            const double f = 1.0 / (1.0 + exp(z));
-            acc += f * w[j];
-            if (SLOPE) accd += beta_s * f * (1.0 - f) * w[j];
+    for (int64_t j = threadIdx.x; j < M; j += (int64_t)U * NT) {
+        double xs[U], ws[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t jj = j + (int64_t)u * NT;
+            xs[u] = jj < M ? x[jj] : 0.0;
+            ws[u] = jj < M ? w[jj] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double z = beta_s * (xs[u] - mu_s);
+            if (z < -kSat) {
+                acc += ws[u];
+            } else if (z <= kSat) {
+                const double f = 1.0 / (1.0 + exp(z));
+                acc += f * ws[u];
+                if (SLOPE) accd += beta_s * f * (1.0 - f) * ws[u];
+            }
         }
     }
     t = block_sum<NT>(acc, smem) / (double)M;
