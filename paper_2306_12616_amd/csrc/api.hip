@@ -300,6 +300,98 @@ void* rslot(chebdm_handle h, const Plan& pl, int l) { return slot(h, pl, pl.k + 
 // Baby steps T_2..T_k in the stages of Algorithm 1: stage 1 makes T_2; stage
 // s >= 2 makes T_{2^{s-2}+i} and T_{2^{s-1}+i} from already known T's.  The
 // products of one stage are independent and go out as one grouped launch.
+// ---------------------------------------------------------------- graph replay
+
+// Everything a captured device sequence depends on: if two calls agree on all of it, every
+// kernel argument of their sequences agrees, and the first call's graph can be replayed.
+struct ReplayKey {
+    int32_t kind, order, k, m, prec, form, baby, search, max_iter, bounds_on_device;
+    int64_t n, ld, ldh, ldd, M;
+    const void *dH, *dD, *mats, *small;
+    double tol, beta, x, emin, emax;   // x: n_elec (mu search) or mu (density)
+};
+
+std::vector<char> replay_key(int kind, const Plan& pl, chebdm_handle h, const double* dH, int64_t ldh,
+                             const double* dD, int64_t ldd, double beta, double x, bool bounds_on_device,
+                             double emin, double emax) {
+    ReplayKey k;
+    std::memset(&k, 0, sizeof(k));   // padding too: keys are compared byte by byte
+    k.kind = kind;
+    k.order = pl.order;
+    k.k = pl.k;
+    k.m = pl.m;
+    k.prec = pl.prec;
+    k.form = pl.form;
+    k.baby = pl.baby;
+    k.search = pl.search;
+    k.max_iter = pl.max_iter;
+    k.bounds_on_device = bounds_on_device ? 1 : 0;
+    k.n = pl.n;
+    k.ld = pl.ld;
+    k.ldh = ldh;
+    k.ldd = ldd;
+    k.M = pl.M;
+    k.dH = dH;
+    k.dD = dD;
+    k.mats = h->mats;
+    k.small = h->small;
+    k.tol = pl.tol;
+    k.beta = beta;
+    k.x = x;
+    if (!bounds_on_device) {
+        k.emin = emin;
+        k.emax = emax;
+    }
+    std::vector<char> v(sizeof(k));
+    std::memcpy(v.data(), &k, sizeof(k));
+    return v;
+}
+
+void drop_replay(chebdm_ctx::Replay& r) {
+    if (r.exec) (void)hipGraphExecDestroy(r.exec);
+    if (r.graph) (void)hipGraphDestroy(r.graph);
+    r.exec = nullptr;
+    r.graph = nullptr;
+    r.key.clear();
+}
+
+// Runs body() - launches only, all on h->stream - either eagerly (launch timing on) or as a
+// graph: captured on the handle's own stream on first use, replayed on h->stream while the
+// key matches.  The replay is ordered after everything already queued on h->stream.
+// *products: the body's product count (kept with the graph for replays).
+template <class Body>
+int run_replayed(chebdm_handle h, int slot, const std::vector<char>& key, int* products, Body body) {
+    if (h->prof) return body();
+    chebdm_ctx::Replay& r = h->replay[slot];
+    if (!r.exec || r.key != key) {
+        drop_replay(r);
+        if (!h->cap) HIP_TRY(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+        hipStream_t user = h->stream;
+        h->stream = h->cap;
+        const int rc = body();
+        h->stream = user;
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(h->cap, &g);
+        if (rc < 0) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        HIP_TRY(ec);
+        r.graph = g;
+        const hipError_t ei = hipGraphInstantiate(&r.exec, g, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            drop_replay(r);
+            HIP_TRY(ei);
+        }
+        r.key = key;
+        r.products = *products;
+    }
+    *products = r.products;
+    HIP_TRY(hipGraphLaunch(r.exec, h->stream));
+    return 0;
+}
+
 // P_2(Y) .. P_K(Y) from P_1 = Y and P_0 = I for the Chebyshev polynomials P_i = T_i of a
 // symmetric Y, where slot(i) holds P_i (i >= 1).  Sequential: P_{i+1} = 2 Y P_i - P_{i-1}.
 // Stages (Algorithm 1, Sec. III.B): stage s forms P_{v+1..2v} (v = 2^{s-1}) from P_1..P_v by
@@ -487,6 +579,8 @@ int chebdm_destroy(chebdm_handle h) {
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
     }
+    for (auto& r : h->replay) drop_replay(r);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
     if (h->mats) (void)hipFree(h->mats);
     if (h->small) (void)hipFree(h->small);
     if (h->mlp_work) (void)hipFree(h->mlp_work);
@@ -566,6 +660,7 @@ int chebdm_density(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, do
     if (!dD || ldd < n) return fail(CHEBDM_ERR_ARG, "D is NULL or ldd < n");
     if (order < 0) return fail(CHEBDM_ERR_ARG, "order < 0");
     if (!(beta > 0.0) || !std::isfinite(beta) || !std::isfinite(mu)) return fail(CHEBDM_ERR_ARG, "beta must be > 0");
+    const bool bounds_dev = std::isnan(emin) || std::isnan(emax);   // Gershgorin bounds land in the scalars
     Plan pl;
     pl.n = n;
     pl.order = order;
@@ -589,12 +684,18 @@ int chebdm_density(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, do
     CHECK(ensure_small(h, pl.M));
     pl.ld = round_up(n, 128);
     CHECK(ensure_mats(h, pl, pl.k + pl.m));
-    HIP_TRY(launch_set_scalars(h->scal, emin, emax, beta, mu, 1, 0.0, pl.tol, pl.max_iter, h->stream));
-    HIP_TRY(launch_shift(dH, n, ldh, h->scal, tslot(h, pl, 1), pl.ld, pl.prec, h->stream));
-    HIP_TRY(launch_fermi_coeffs(order, pl.M, h->scal, h->ftab, h->c, h->stream));
-    HIP_TRY(launch_block_coeffs(h->c, order, pl.k, pl.m, pl.form, h->coef, h->stream));
-    CHECK(baby_steps(h, pl, &pl.n_gemm));
-    CHECK(giant_steps(h, pl, dD, ldd, &pl.n_gemm));
+    const std::vector<char> key = replay_key(2, pl, h, dH, ldh, dD, ldd, beta, mu, bounds_dev, emin, emax);
+    CHECK(run_replayed(h, 2, key, &pl.n_gemm, [&]() -> int {
+        pl.n_gemm = 0;
+        HIP_TRY(launch_set_scalars(h->scal, emin, emax, beta, mu, 1, 0.0, pl.tol, pl.max_iter, h->stream,
+                                   bounds_dev));
+        HIP_TRY(launch_shift(dH, n, ldh, h->scal, tslot(h, pl, 1), pl.ld, pl.prec, h->stream));
+        HIP_TRY(launch_fermi_coeffs(order, pl.M, h->scal, h->ftab, h->c, h->stream));
+        HIP_TRY(launch_block_coeffs(h->c, order, pl.k, pl.m, pl.form, h->coef, h->stream));
+        CHECK(baby_steps(h, pl, &pl.n_gemm));
+        CHECK(giant_steps(h, pl, dD, ldd, &pl.n_gemm));
+        return 0;
+    }));
     if (info) {
         CHECK(read_scalars(h));
         fill_info(info, pl, emin, emax, mu, *h->h_trD, 0.0, 0, CHEBDM_OK);
@@ -611,6 +712,7 @@ int chebdm_mu_search(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, 
     if (order < 0) return fail(CHEBDM_ERR_ARG, "order < 0");
     if (!(beta > 0.0) || !std::isfinite(beta)) return fail(CHEBDM_ERR_ARG, "beta must be > 0");
     if (!(n_elec > 0.0) || !(n_elec < (double)n)) return fail(CHEBDM_ERR_ARG, "need 0 < n_elec < n");
+    const bool bounds_dev = std::isnan(emin) || std::isnan(emax);   // Gershgorin bounds land in the scalars
     Plan pl;
     pl.n = n;
     pl.order = order;
@@ -633,20 +735,28 @@ int chebdm_mu_search(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, 
     CHECK(ensure_small(h, pl.M));
     pl.ld = round_up(n, 128);
     CHECK(ensure_mats(h, pl, pl.k + pl.m));
-    HIP_TRY(launch_set_scalars(h->scal, emin, emax, beta, 0.0, 0, n_elec, pl.tol, pl.max_iter, h->stream));
-    HIP_TRY(launch_shift(dH, n, ldh, h->scal, tslot(h, pl, 1), pl.ld, pl.prec, h->stream));
-    CHECK(baby_steps(h, pl, &pl.n_gemm));
-    CHECK(moments_on_device(h, pl, &pl.n_gemm));
-    size_t ev = (size_t)-1;
-    if (h->prof) CHECK(prof_begin(h, PROF_SEARCH, 0, 0.0, 0.0, &ev));
-    HIP_TRY(launch_dct3(h->tau, order, pl.M, h->w, h->xtab, h->stream));
-    HIP_TRY(launch_bisect(h->w, h->xtab, pl.M, h->scal, pl.search, h->stream));
-    if (h->prof) CHECK(prof_end(h, ev));
-    if (dD) {
-        HIP_TRY(launch_fermi_coeffs(order, pl.M, h->scal, h->ftab, h->c, h->stream));
-        HIP_TRY(launch_block_coeffs(h->c, order, pl.k, pl.m, pl.form, h->coef, h->stream));
-        CHECK(giant_steps(h, pl, dD, ldd, &pl.n_gemm));
-    }
+    const int slot = dD ? 0 : 1;
+    const std::vector<char> key = replay_key(slot, pl, h, dH, ldh, dD, dD ? ldd : 0, beta, n_elec, bounds_dev,
+                                             emin, emax);
+    CHECK(run_replayed(h, slot, key, &pl.n_gemm, [&]() -> int {
+        pl.n_gemm = 0;
+        HIP_TRY(launch_set_scalars(h->scal, emin, emax, beta, 0.0, 0, n_elec, pl.tol, pl.max_iter, h->stream,
+                                   bounds_dev));
+        HIP_TRY(launch_shift(dH, n, ldh, h->scal, tslot(h, pl, 1), pl.ld, pl.prec, h->stream));
+        CHECK(baby_steps(h, pl, &pl.n_gemm));
+        CHECK(moments_on_device(h, pl, &pl.n_gemm));
+        size_t ev = (size_t)-1;
+        if (h->prof) CHECK(prof_begin(h, PROF_SEARCH, 0, 0.0, 0.0, &ev));
+        HIP_TRY(launch_dct3(h->tau, order, pl.M, h->w, h->xtab, h->stream));
+        HIP_TRY(launch_bisect(h->w, h->xtab, pl.M, h->scal, pl.search, h->stream));
+        if (h->prof) CHECK(prof_end(h, ev));
+        if (dD) {
+            HIP_TRY(launch_fermi_coeffs(order, pl.M, h->scal, h->ftab, h->c, h->stream));
+            HIP_TRY(launch_block_coeffs(h->c, order, pl.k, pl.m, pl.form, h->coef, h->stream));
+            CHECK(giant_steps(h, pl, dD, ldd, &pl.n_gemm));
+        }
+        return 0;
+    }));
     CHECK(read_scalars(h));
     const DevScalars& s = *h->h_scal;
     const double mu = s.cen + s.half * s.mu_s;

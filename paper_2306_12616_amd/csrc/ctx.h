@@ -38,6 +38,16 @@ struct chebdm_ctx {
     // activations of the chemical-potential network
     float* mlp_work = nullptr;
     int64_t mlp_work_floats = 0;
+    // captured graphs of the device part of chebdm_mu_search / chebdm_density, replayed while
+    // the call's arguments (and so every kernel argument) are unchanged
+    struct Replay {
+        std::vector<char> key;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        int products = 0;   // matrix products in the captured sequence
+    };
+    hipStream_t cap = nullptr;   // capture stream
+    Replay replay[3];            // mu search with D, mu search without D, density
 };
 
 namespace chebdm {

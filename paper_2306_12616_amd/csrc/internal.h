@@ -58,7 +58,8 @@ struct GemmBatch {
 hipError_t launch_gershgorin(const double* H, int64_t n, int64_t ldh, double* partial,
                              int64_t partial_cap, DevScalars* s, hipStream_t st);
 hipError_t launch_set_scalars(DevScalars* s, double emin, double emax, double beta, double mu,
-                              int has_mu, double n_elec, double tol, int max_iter, hipStream_t st);
+                              int has_mu, double n_elec, double tol, int max_iter, hipStream_t st,
+                              int bounds_on_device = 0);
 hipError_t launch_shift(const double* H, int64_t n, int64_t ldh, const DevScalars* s, void* T1,
                         int64_t ldw, int prec, hipStream_t st);
 // traces of `count` matrices spaced `stride` elements apart (float or double), into out[0..count)

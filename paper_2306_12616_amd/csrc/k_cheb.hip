@@ -20,8 +20,14 @@ namespace chebdm {
 
 namespace {
 
+// bounds_on_device: take e_a, e_b from s (written there by the Gershgorin kernels) instead of
+// the arguments, so that a captured graph does not depend on their values.
 __global__ void k_set_scalars(DevScalars* s, double emin, double emax, double beta, double mu,
-                              int has_mu, double n_elec, double tol, int max_iter) {
+                              int has_mu, double n_elec, double tol, int max_iter, int bounds_on_device) {
+    if (bounds_on_device) {
+        emin = s->emin;
+        emax = s->emax;
+    }
     const double cen = 0.5 * (emin + emax), half = 0.5 * (emax - emin);
     s->emin = emin;
     s->emax = emax;
@@ -189,9 +195,10 @@ k_bisect(const double* __restrict__ w, const double* __restrict__ x, int64_t M, 
 }  // namespace
 
 hipError_t launch_set_scalars(DevScalars* s, double emin, double emax, double beta, double mu,
-                              int has_mu, double n_elec, double tol, int max_iter, hipStream_t st) {
+                              int has_mu, double n_elec, double tol, int max_iter, hipStream_t st,
+                              int bounds_on_device) {
     hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(1), 0, st, s, emin, emax, beta, mu, has_mu,
-                       n_elec, tol, max_iter);
+                       n_elec, tol, max_iter, bounds_on_device);
     return hipGetLastError();
 }
 

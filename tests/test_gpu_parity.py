@@ -337,3 +337,41 @@ def test_profile_counts_products(cd, handle):
     assert prof["gemm_ms"] > 0 and prof["combine_calls"] == 1 and prof["gram_calls"] == 1
     # read clears the counters
     assert cd.chebdm_profile_read(handle)["gemm_launches"] == 0
+
+
+def test_replayed_graph_matches_eager_and_tracks_arguments(cd, handle):
+    # the device part of a call is captured once and replayed while its arguments are unchanged;
+    # launch timing forces the eager path, which must agree bit for bit
+    h, q, lam = synth.hamiltonian(333, "gaussmix6", seed=44)
+    H = _dev(h)
+    D1 = torch.empty_like(H)
+    mu1, _, i1 = cd.chebdm_mu_search(handle, H, 40.0, 150.5, 200, None, D=D1)       # capture
+    D2 = torch.empty_like(H)
+    mu2, _, i2 = cd.chebdm_mu_search(handle, H, 40.0, 150.5, 200, None, D=D2)       # new D pointer: capture
+    mu3, _, i3 = cd.chebdm_mu_search(handle, H, 40.0, 150.5, 200, None, D=D2)       # replay
+    cd.chebdm_profile_enable(handle, True)
+    D4 = torch.empty_like(H)
+    mu4, _, i4 = cd.chebdm_mu_search(handle, H, 40.0, 150.5, 200, None, D=D4)       # eager
+    cd.chebdm_profile_read(handle)
+    cd.chebdm_profile_enable(handle, False)
+    assert mu1 == mu2 == mu3 == mu4
+    assert torch.equal(D1, D2) and torch.equal(D1, D4)
+    assert i1["n_gemm"] == i3["n_gemm"] == i4["n_gemm"] and i3["iters"] == i4["iters"]
+    # new contents under the same pointer: H scaled by 2 (bounds on the device follow it)
+    H.mul_(2.0)
+    mu5, _, i5 = cd.chebdm_mu_search(handle, H, 20.0, 150.5, 200, None, D=D2)
+    assert abs(mu5 - 2.0 * mu1) <= 1e-9 * max(1.0, abs(mu1))
+    assert float(torch.max(torch.abs(D2 - D1))) <= 1e-9
+    # a different electron count changes the key
+    mu6, _, i6 = cd.chebdm_mu_search(handle, H, 20.0, 100.5, 200, None, D=D2)
+    assert mu6 < mu5 and abs(i6["trace"] - 100.5) <= 1e-9
+    # density at fixed mu: replay equals eager
+    Da = torch.empty_like(H)
+    cd.chebdm_density(handle, H, 20.0, mu5, 200, None, D=Da)
+    cd.chebdm_density(handle, H, 20.0, mu5, 200, None, D=Da)
+    cd.chebdm_profile_enable(handle, True)
+    Db = torch.empty_like(H)
+    cd.chebdm_density(handle, H, 20.0, mu5, 200, None, D=Db)
+    cd.chebdm_profile_read(handle)
+    cd.chebdm_profile_enable(handle, False)
+    assert torch.equal(Da, Db)
