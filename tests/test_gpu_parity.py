@@ -357,21 +357,22 @@ def test_replayed_graph_matches_eager_and_tracks_arguments(cd, handle):
     assert mu1 == mu2 == mu3 == mu4
     assert torch.equal(D1, D2) and torch.equal(D1, D4)
     assert i1["n_gemm"] == i3["n_gemm"] == i4["n_gemm"] and i3["iters"] == i4["iters"]
-    # new contents under the same pointer: H scaled by 2 (bounds on the device follow it)
-    H.mul_(2.0)
-    mu5, _, i5 = cd.chebdm_mu_search(handle, H, 20.0, 150.5, 200, None, D=D2)
-    assert abs(mu5 - 2.0 * mu1) <= 1e-9 * max(1.0, abs(mu1))
+    # new contents under the same pointer, same arguments (a replay): H + I/2 moves the bounds,
+    # which the replayed graph reads on the device, and mu by 1/2; D is unchanged
+    H.add_(0.5 * torch.eye(333, dtype=torch.float64, device=H.device))
+    mu5, _, i5 = cd.chebdm_mu_search(handle, H, 40.0, 150.5, 200, None, D=D2)
+    assert abs(mu5 - (mu1 + 0.5)) <= 1e-9
     assert float(torch.max(torch.abs(D2 - D1))) <= 1e-9
     # a different electron count changes the key
-    mu6, _, i6 = cd.chebdm_mu_search(handle, H, 20.0, 100.5, 200, None, D=D2)
+    mu6, _, i6 = cd.chebdm_mu_search(handle, H, 40.0, 100.5, 200, None, D=D2)
     assert mu6 < mu5 and abs(i6["trace"] - 100.5) <= 1e-9
     # density at fixed mu: replay equals eager
     Da = torch.empty_like(H)
-    cd.chebdm_density(handle, H, 20.0, mu5, 200, None, D=Da)
-    cd.chebdm_density(handle, H, 20.0, mu5, 200, None, D=Da)
+    cd.chebdm_density(handle, H, 40.0, mu5, 200, None, D=Da)
+    cd.chebdm_density(handle, H, 40.0, mu5, 200, None, D=Da)
     cd.chebdm_profile_enable(handle, True)
     Db = torch.empty_like(H)
-    cd.chebdm_density(handle, H, 20.0, mu5, 200, None, D=Db)
+    cd.chebdm_density(handle, H, 40.0, mu5, 200, None, D=Db)
     cd.chebdm_profile_read(handle)
     cd.chebdm_profile_enable(handle, False)
     assert torch.equal(Da, Db)
