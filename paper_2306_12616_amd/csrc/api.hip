@@ -92,21 +92,26 @@ int set_device(chebdm_handle h) {
     return 0;
 }
 
+static_assert(sizeof(DevScalars) <= 64 * sizeof(double), "scalars must fit their 64-double slot");
+
+// Grows the small buffers.  The scalars carry over into a new allocation: the Gershgorin
+// bounds written there by the bounds kernels are read back on the device by later kernels.
 int ensure_small(chebdm_handle h, int64_t M) {
     if (h->small && M <= h->small_M) return 0;
-    if (h->small) {
-        HIP_TRY(hipStreamSynchronize(h->stream));
-        HIP_TRY(hipFree(h->small));
-        h->small = nullptr;
-    }
     const int64_t Mcap = M < 4096 ? 4096 : M;
     const int64_t doubles = 64 /*scalars*/ + 4 * kSmallVec + 48 * 48 + 64 + 3 * Mcap + kPartialDoubles;
     const size_t bytes = (size_t)doubles * sizeof(double);
-    if (hipMalloc(&h->small, bytes) != hipSuccess) {
-        h->small = nullptr;
+    void* fresh = nullptr;
+    if (hipMalloc(&fresh, bytes) != hipSuccess) {
         (void)hipGetLastError();
         return fail(CHEBDM_ERR_OOM, "cannot allocate " + std::to_string(bytes) + " bytes of scalar workspace");
     }
+    if (h->small) {
+        HIP_TRY(hipMemcpyAsync(fresh, h->small, 64 * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        HIP_TRY(hipFree(h->small));
+    }
+    h->small = fresh;
     double* p = static_cast<double*>(h->small);
     h->scal = reinterpret_cast<DevScalars*>(p);
     p += 64;

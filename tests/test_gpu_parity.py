@@ -376,3 +376,22 @@ def test_replayed_graph_matches_eager_and_tracks_arguments(cd, handle):
     cd.chebdm_profile_read(handle)
     cd.chebdm_profile_enable(handle, False)
     assert torch.equal(Da, Db)
+
+
+def test_bounds_survive_scalar_workspace_growth(cd):
+    # a fresh handle sized by a small quadrature, then a call whose quadrature needs a larger
+    # workspace: the Gershgorin bounds computed before the growth must carry over
+    h2 = cd.Handle(0)
+    try:
+        hm, q, lam = synth.hamiltonian(300, "uniform", seed=61)
+        H = _dev(hm)
+        cd.chebdm_mu_search(h2, H, 5.0, 150.5, 64, None)                       # small M
+        mu, D, info = cd.chebdm_mu_search(h2, H, 400.0, 150.5, 256, None)      # M grows
+        assert info["status"] == 0, info
+        emin, emax = info["emin"], info["emax"]
+        cen, a = ch.scaling(emin, emax)
+        c = ch.chebyshev_coeffs(256, 400.0 * a, (mu - cen) / a, info["n_quad"])
+        t_or = ch.trace_of_series(c, ch.moments_from_eigs(lam, emin, emax, 256))
+        assert abs(t_or - 150.5) <= 1e-9
+    finally:
+        h2.close()
