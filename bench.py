@@ -40,24 +40,44 @@ def make_h(n, law, seed):
     return h
 
 
+def timed(call, steps, warmup, cd=None, handle=None):
+    """Wall time of `steps` calls after `warmup` untimed ones, bracketed by device syncs.
+
+    With cd/handle given, the same number of calls is then repeated with the library's launch
+    timing on (HIP events on its stream around every product / block-sum / Gram / search
+    launch; that runs each call eagerly instead of replaying its graph) and those per-phase
+    timings are returned too.  The throughput comes from the first, uninstrumented pass.
+    """
+    import torch
+
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for _ in range(steps):
+        out = call()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = None
+    if cd is not None:
+        cd.chebdm_profile_enable(handle, True)
+        torch.cuda.synchronize()
+        for _ in range(steps):
+            call()
+        prof = cd.chebdm_profile_read(handle)
+        cd.chebdm_profile_enable(handle, False)
+    return dt, prof, out
+
+
 def run_steps(cd, handle, H, beta, n_elec, order, opts, steps, warmup, want_density=True):
     import torch
 
     D = torch.empty_like(H) if want_density else None
-    for _ in range(warmup):
-        cd.chebdm_mu_search(handle, H, beta, n_elec, order, opts, want_density=want_density, D=D)
-    torch.cuda.synchronize()
-    cd.chebdm_profile_enable(handle, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    info = None
-    for _ in range(steps):
-        mu, _, info = cd.chebdm_mu_search(handle, H, beta, n_elec, order, opts, want_density=want_density, D=D)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prof = cd.chebdm_profile_read(handle)
-    cd.chebdm_profile_enable(handle, False)
-    return dt, prof, info
+    dt, prof, out = timed(lambda: cd.chebdm_mu_search(handle, H, beta, n_elec, order, opts,
+                                                      want_density=want_density, D=D),
+                          steps, warmup, cd, handle)
+    return dt, prof, out[2]
 
 
 GEMM_SOURCES = ("paper_2306_12616_amd/csrc/gemm_tile.h", "paper_2306_12616_amd/csrc/k_gemm.hip")
@@ -98,18 +118,7 @@ def run_density_steps(cd, handle, H, beta, mu, order, opts, steps, warmup):
     import torch
 
     D = torch.empty_like(H)
-    for _ in range(warmup):
-        cd.chebdm_density(handle, H, beta, mu, order, opts, D=D)
-    torch.cuda.synchronize()
-    cd.chebdm_profile_enable(handle, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        cd.chebdm_density(handle, H, beta, mu, order, opts, D=D)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prof = cd.chebdm_profile_read(handle)
-    cd.chebdm_profile_enable(handle, False)
+    dt, prof, _ = timed(lambda: cd.chebdm_density(handle, H, beta, mu, order, opts, D=D), steps, warmup, cd, handle)
     return dt, prof
 
 
