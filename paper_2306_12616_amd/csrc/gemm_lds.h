@@ -33,7 +33,9 @@ struct SplitTerms<P_BF16X6> {
 // tj*128 .. +127 must lie inside the ld x ld operands.
 // DEPTH = 1: the panels of step s+1 are loaded while step s computes; DEPTH = 2:
 // those of step s+2 (two register stages, the loop body unrolled by two).
-template <int P, int DEPTH = 2, int PAD = 8>
+// LDS rows are KC + PAD bf16 long; SWZ > 0 XORs the 16-byte chunk index of row r with
+// (r >> SWZ) & 3 (a bank swizzle; use with PAD = 0).
+template <int P, int DEPTH = 2, int PAD = 8, int SWZ = 0>
 __device__ __forceinline__ void gemm_tile_lds(const GemmDesc<float>& g, int64_t n, int64_t ld, int64_t kpad, int ti,
                                               int tj) {
     static_assert(P == P_BF16X3 || P == P_BF16X6, "split-bf16 precisions only");
@@ -41,6 +43,8 @@ __device__ __forceinline__ void gemm_tile_lds(const GemmDesc<float>& g, int64_t 
     using Acc = f32x4;
     constexpr int BM = 128, KC = 32, NT = SplitTerms<P>::N, RS = KC + PAD;
     __shared__ __attribute__((aligned(16))) __bf16 lds[2][NT][BM][RS];
+    // column (in bf16) of 16-byte chunk c of row r
+    auto col = [](int r, int c) -> int { return SWZ > 0 ? 8 * (c ^ ((r >> SWZ) & 3)) : 8 * c; };
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wm = wave >> 1, wn = wave & 1;
@@ -75,9 +79,10 @@ __device__ __forceinline__ void gemm_tile_lds(const GemmDesc<float>& g, int64_t 
             bf16x8 t0, t1, t2;
             if constexpr (NT == 2) split_bf16(&x[8 * h], t0, t1);
             else split3_bf16(&x[8 * h], t0, t1, t2);
-            *reinterpret_cast<bf16x8*>(&lds[which][0][srow][sk + 8 * h]) = t0;
-            *reinterpret_cast<bf16x8*>(&lds[which][1][srow][sk + 8 * h]) = t1;
-            if constexpr (NT == 3) *reinterpret_cast<bf16x8*>(&lds[which][2][srow][sk + 8 * h]) = t2;
+            const int cc = col(srow, sk / 8 + h);
+            *reinterpret_cast<bf16x8*>(&lds[which][0][srow][cc]) = t0;
+            *reinterpret_cast<bf16x8*>(&lds[which][1][srow][cc]) = t1;
+            if constexpr (NT == 3) *reinterpret_cast<bf16x8*>(&lds[which][2][srow][cc]) = t2;
         }
     };
     auto put = [&](const Stage& r) {
@@ -98,8 +103,9 @@ __device__ __forceinline__ void gemm_tile_lds(const GemmDesc<float>& g, int64_t 
         for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int f = 0; f < 4; ++f) {
-                a[t][f] = *reinterpret_cast<const bf16x8*>(&lds[0][t][wm * 64 + f * 16 + lr][lq * 8]);
-                b[t][f] = *reinterpret_cast<const bf16x8*>(&lds[1][t][wn * 64 + f * 16 + lr][lq * 8]);
+                const int ra = wm * 64 + f * 16 + lr, rb = wn * 64 + f * 16 + lr;
+                a[t][f] = *reinterpret_cast<const bf16x8*>(&lds[0][t][ra][col(ra, lq)]);
+                b[t][f] = *reinterpret_cast<const bf16x8*>(&lds[1][t][rb][col(rb, lq)]);
             }
 #pragma unroll
         for (int f = 0; f < 4; ++f)
