@@ -271,6 +271,8 @@ def main():
     ap.add_argument("--beta", type=float, default=100.0)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
     ap.add_argument("--no-breakdown", action="store_true")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched 512-problem workload (for profiling it) and print its row")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (the calibration "
@@ -291,6 +293,10 @@ def main():
         sys.exit(1)
     cd.load_library()
     handle = cd.Handle(0)
+    if args.batch_only:
+        print(json.dumps({"batch512": batch_row(cd, handle, torch)}), flush=True)
+        handle.close()
+        return
 
     n, order, beta = args.n, args.order, args.beta
     n_elec = n / 2.0
