@@ -26,6 +26,15 @@
  *     negative error; chebdm_last_error() then describes the failure
  *     (thread-local string).  No C++ exception crosses this interface.
  *   - A handle must not be used from two threads at once.
+ *   - chebdm_density and chebdm_mu_search capture their device work (after
+ *     the bounds) into a HIP graph on a stream of the handle's own and replay
+ *     it on the handle's stream while the call's arguments are unchanged
+ *     (pointers, sizes, beta, mu or n_elec, options, quadrature size and
+ *     workspace; new contents under the same pointers are fine).  The handle
+ *     keeps one graph per kind of call (mu search with and without D,
+ *     density).  With launch timing on (chebdm_profile_enable) they run
+ *     eagerly.  Neither may be called while the handle's stream is itself
+ *     being captured (they synchronise it).
  */
 #ifndef CHEBDM_H
 #define CHEBDM_H
