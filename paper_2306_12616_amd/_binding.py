@@ -363,10 +363,10 @@ class Batch:
         return (np.array(ev[:], dtype=np.int32), np.array(le[:], dtype=np.int32), np.array(mus[:]),
                 np.array(bs[:]))
 
-    def features(self, device="cuda"):
-        """Network inputs of the last run (count x 64, device float32)."""
+    def features(self):
+        """Network inputs of the last run (count x 64, float32 on the plan's device)."""
         torch = _torch()
-        out = torch.empty((len(self.sizes), 64), dtype=torch.float32, device=device)
+        out = torch.empty((len(self.sizes), 64), dtype=torch.float32, device=f"cuda:{self.handle.device}")
         _check(load_library().chebdm_batch_features(self._b, ctypes.c_void_p(out.data_ptr())))
         return out
 
