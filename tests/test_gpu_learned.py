@@ -216,3 +216,24 @@ def test_learned_start_beats_bisection(cd, handle, tmp_path):
     assert rep["learned"]["learned_share"] >= 0.9
     assert np.max(np.abs(mus["learned"] - mus["bisection"])) <= 1e-6
     ev.close()
+
+
+def test_batch_features_match_oracle(cd, handle):
+    # the network inputs the device assembles (float32) against the oracle's moments
+    sizes = [96, 130, 257]
+    order, betas, nes = 128, [30.0, 60.0, 90.0], [40.5, 70.5, 120.5]
+    probs = [synth.hamiltonian(n, "gaussmix6", seed=70 + i) for i, n in enumerate(sizes)]
+    Hs = [torch.from_numpy(h).cuda() for h, _, _ in probs]
+    batch = cd.Batch(handle, sizes, order)
+    batch.mu_only(Hs, betas, nes)
+    X = batch.features().cpu().numpy()
+    _, _, _, beta_s = batch.stats()
+    for p, n in enumerate(sizes):
+        h, q, lam = probs[p]
+        lo, hi = ch.gershgorin_bounds(h)
+        cen, a = ch.scaling(lo, hi)
+        tau = ch.moments_from_eigs(lam, lo, hi, order)
+        ref = om.features(tau, [n], [nes[p]], [betas[p] * a])[0]
+        assert abs(beta_s[p] - betas[p] * a) <= 1e-12 * betas[p] * a
+        assert np.max(np.abs(X[p] - ref)) <= 1e-6 * max(1.0, float(np.max(np.abs(ref)))), (p, np.max(np.abs(X[p] - ref)))
+    batch.close()
