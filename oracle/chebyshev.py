@@ -78,11 +78,27 @@ def quadrature_size(order: int, beta_s: float) -> int:
     return 1 << int(math.ceil(math.log2(need)))
 
 
-def chebyshev_coeffs(order: int, beta_s: float, mu_s: float, M: int | None = None):
+def jackson_kernel(order: int):
+    """Jackson damping factors g_0..g_L for a series of N = L + 1 terms.
+
+    Not in the paper (it notes the Gibbs oscillations of the truncated series,
+    Sec. III.D, but applies no damping): an option, off by default.  The kernel
+    polynomial method's Jackson kernel (Weisse, Wellein, Alvermann, Fehske,
+    Rev. Mod. Phys. 78, 275 (2006)):
+        g_n = [(N - n + 1) cos(pi n / (N+1)) + sin(pi n / (N+1)) cot(pi / (N+1))] / (N + 1).
+    """
+    N = order + 1
+    n = np.arange(order + 1, dtype=np.float64)
+    q = np.pi / (N + 1)
+    return ((N - n + 1) * np.cos(q * n) + np.sin(q * n) / np.tan(q)) / (N + 1)
+
+
+def chebyshev_coeffs(order: int, beta_s: float, mu_s: float, M: int | None = None, damping: str | None = None):
     """Coefficients c_0..c_L of sum c_n T_n approximating f (Sec. II.B; projection is a reading).
 
     c_n = (2 - delta_{n0})/M * sum_{j<M} f(x_j) cos(n theta_j): the DCT-II of
     f sampled at the Chebyshev-Gauss nodes.  c_0 carries the factor 1/2.
+    damping="jackson" multiplies c_n by the Jackson factors g_n.
     """
     if M is None:
         M = quadrature_size(order, beta_s)
@@ -93,6 +109,10 @@ def chebyshev_coeffs(order: int, beta_s: float, mu_s: float, M: int | None = Non
     c[0] *= 0.5
     if order + 1 > M:
         raise ValueError("order + 1 must not exceed M")
+    if damping == "jackson":
+        c = c * jackson_kernel(order)
+    elif damping is not None:
+        raise ValueError(f"unknown damping {damping!r}")
     return c
 
 
@@ -167,7 +187,7 @@ OK, NOCONV, BRACKET = 0, 1, -5
 
 
 def bisect_mu(tau, order: int, beta_s: float, n_elec: float, tol: float = 1e-10,
-              max_iter: int = 200, M: int | None = None):
+              max_iter: int = 200, M: int | None = None, damping: str | None = None):
     """Scaled chemical potential mu~ with tr D_L(mu~) = N_e, by bisection (reading).
 
     Bracket [-1, 1]; it must hold t(-1) < N_e < t(1), else status BRACKET.
@@ -179,7 +199,7 @@ def bisect_mu(tau, order: int, beta_s: float, n_elec: float, tol: float = 1e-10,
         M = quadrature_size(order, beta_s)
 
     def t_of(mu_s):
-        return trace_of_series(chebyshev_coeffs(order, beta_s, mu_s, M), tau)
+        return trace_of_series(chebyshev_coeffs(order, beta_s, mu_s, M, damping), tau)
 
     lo, hi = -1.0, 1.0
     if not (t_of(lo) < n_elec < t_of(hi)):

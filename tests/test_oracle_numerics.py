@@ -216,3 +216,42 @@ def test_mu_search_density_end_to_end_small():
     assert abs(np.trace(out["D"]) - 64.0) < 1e-9
     out2 = ch.mu_search_density(h, 50.0, 64.0, 128, eig=(q, lam))
     np.testing.assert_allclose(out2["D"], out["D"], atol=1e-12)
+
+
+# ---------------------------------------------------------------- Jackson damping (option)
+
+def test_jackson_factors_by_hand():
+    g = ch.jackson_kernel(1)              # N = 2 terms: g_1 = (2 cos(pi/3) + cos(pi/3)) / 3 = 1/2
+    assert g[0] == 1.0
+    assert abs(g[1] - 0.5) < 1e-15
+    g = ch.jackson_kernel(200)
+    assert g[0] == 1.0 and np.all(np.diff(g) < 0) and g[-1] > 0
+
+
+def test_jackson_damped_series_stays_in_unit_interval():
+    # a positive kernel with unit weight: the damped expansion of 0 <= f <= 1 stays in [0, 1]
+    # (no Gibbs overshoot), while the plain truncation overshoots near a sharp step
+    order, beta_s, mu_s = 128, 2000.0, 0.13
+    M = ch.quadrature_size(order, beta_s)
+    x = np.linspace(-1, 1, 20001)
+    plain = ch.cheb_eval(ch.chebyshev_coeffs(order, beta_s, mu_s, M), x)
+    damped = ch.cheb_eval(ch.chebyshev_coeffs(order, beta_s, mu_s, M, "jackson"), x)
+    assert plain.max() > 1.05 and plain.min() < -0.05
+    assert damped.min() > -1e-12 and damped.max() < 1.0 + 1e-12
+    # damping keeps c_0 (the mean of f over the Chebyshev measure)
+    c_p = ch.chebyshev_coeffs(order, beta_s, mu_s, M)
+    c_d = ch.chebyshev_coeffs(order, beta_s, mu_s, M, "jackson")
+    assert c_d[0] == c_p[0]
+
+
+def test_jackson_damped_mu_search_counts_electrons():
+    h, q, lam = synth.hamiltonian(60, "uniform", seed=5)
+    lo, hi = ch.gershgorin_bounds(h)
+    cen, a = ch.scaling(lo, hi)
+    order, beta = 64, 20.0
+    tau = ch.moments_from_eigs(lam, lo, hi, order)
+    mu_s, it, t, st = ch.bisect_mu(tau, order, beta * a, 27.5, damping="jackson")
+    assert st == ch.OK
+    c = ch.chebyshev_coeffs(order, beta * a, mu_s, damping="jackson")
+    d = ch.density_from_eigs(q, lam, c, lo, hi)
+    assert abs(np.trace(d) - 27.5) < 1e-9
