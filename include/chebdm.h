@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define CHEBDM_ABI_VERSION 2
+#define CHEBDM_ABI_VERSION 3
 
 typedef struct chebdm_ctx* chebdm_handle;
 
@@ -86,6 +86,17 @@ enum chebdm_search {
                                  /* quadrature; a step leaving the bracket bisects   */
 };
 
+/* Optional damping of the expansion (not in the paper, which truncates plainly
+ * and notes the Gibbs oscillations): c_n -> g_n c_n in the density and in the
+ * trace t(mu~) the search solves, g_n the Jackson factors of the kernel
+ * polynomial method for N = L + 1 terms,
+ *   g_n = [(N-n+1) cos(pi n/(N+1)) + sin(pi n/(N+1)) cot(pi/(N+1))] / (N+1).
+ * The damped polynomial of a function in [0, 1] stays in [0, 1]. */
+enum chebdm_damping {
+    CHEBDM_DAMPING_NONE = 0,
+    CHEBDM_DAMPING_JACKSON = 1
+};
+
 enum chebdm_status {
     CHEBDM_OK = 0,
     CHEBDM_WARN_NOCONV = 1,       /* mu search stopped before |t - N_e| < tol    */
@@ -105,6 +116,7 @@ typedef struct {
     int32_t max_iter;    /* cap on search steps (trace evaluations); 0 = 200       */
     int32_t baby_steps;  /* enum chebdm_baby, default CHEBDM_BABY_AUTO                */
     int32_t search;      /* enum chebdm_search of chebdm_mu_search, default BISECTION */
+    int32_t damping;     /* enum chebdm_damping, default CHEBDM_DAMPING_NONE        */
     double tol;          /* target |tr D - N_e| of the mu search; 0 = 1e-10        */
 } chebdm_opts;
 

@@ -31,7 +31,7 @@ _FORM_NAMES = {"composition": COMPOSITION, "clenshaw": COMPOSITION, "power": POW
 class Opts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("giant_form", ctypes.c_int32), ("k_override", ctypes.c_int32),
                 ("n_quad", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("baby_steps", ctypes.c_int32),
-                ("search", ctypes.c_int32), ("tol", ctypes.c_double)]
+                ("search", ctypes.c_int32), ("damping", ctypes.c_int32), ("tol", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -147,10 +147,11 @@ def _check(rc: int, allow_warn: bool = False) -> int:
 
 
 _SEARCH_NAMES = {"bisection": 0, "newton": 1}
+_DAMPING_NAMES = {"none": 0, "jackson": 1}
 
 
 def make_opts(prec="fp64", giant="composition", k_override: int = 0, n_quad: int = 0,
-              max_iter: int = 0, tol: float = 0.0, baby="auto", search="bisection") -> Opts:
+              max_iter: int = 0, tol: float = 0.0, baby="auto", search="bisection", damping="none") -> Opts:
     o = Opts()
     load_library().chebdm_default_opts(ctypes.byref(o))
     o.prec = _PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
@@ -159,6 +160,7 @@ def make_opts(prec="fp64", giant="composition", k_override: int = 0, n_quad: int
     o.n_quad = int(n_quad)
     o.baby_steps = _BABY_NAMES[baby] if isinstance(baby, str) else int(baby)
     o.search = _SEARCH_NAMES[search] if isinstance(search, str) else int(search)
+    o.damping = _DAMPING_NAMES[damping] if isinstance(damping, str) else int(damping)
     if max_iter:
         o.max_iter = int(max_iter)
     if tol:

@@ -76,6 +76,7 @@ struct Plan {
     int prec = CHEBDM_FP64, form = CHEBDM_GIANT_COMPOSITION, baby = CHEBDM_BABY_STAGES;
     int max_iter = 200;
     int search = CHEBDM_SEARCH_BISECTION;
+    int damping = CHEBDM_DAMPING_NONE;
     double tol = 1e-10;
     size_t elem = 8;
     int n_gemm = 0;
@@ -192,6 +193,9 @@ int check_opts(const chebdm_opts* o, Plan& pl) {
     if (o->search != CHEBDM_SEARCH_BISECTION && o->search != CHEBDM_SEARCH_NEWTON)
         return fail(CHEBDM_ERR_ARG, "unknown mu search");
     pl.search = o->search;
+    if (o->damping != CHEBDM_DAMPING_NONE && o->damping != CHEBDM_DAMPING_JACKSON)
+        return fail(CHEBDM_ERR_ARG, "unknown damping");
+    pl.damping = o->damping;
     pl.baby = o->baby_steps != CHEBDM_BABY_AUTO
                   ? o->baby_steps
                   : (o->prec == CHEBDM_FP64 ? CHEBDM_BABY_STAGES : CHEBDM_BABY_SEQUENTIAL);
@@ -310,7 +314,7 @@ void* rslot(chebdm_handle h, const Plan& pl, int l) { return slot(h, pl, pl.k + 
 // Everything a captured device sequence depends on: if two calls agree on all of it, every
 // kernel argument of their sequences agrees, and the first call's graph can be replayed.
 struct ReplayKey {
-    int32_t kind, order, k, m, prec, form, baby, search, max_iter, bounds_on_device;
+    int32_t kind, order, k, m, prec, form, baby, search, max_iter, bounds_on_device, damping;
     int64_t n, ld, ldh, ldd, M;
     const void *dH, *dD, *mats, *small;
     double tol, beta, x, emin, emax;   // x: n_elec (mu search) or mu (density)
@@ -330,6 +334,7 @@ std::vector<char> replay_key(int kind, const Plan& pl, chebdm_handle h, const do
     k.baby = pl.baby;
     k.search = pl.search;
     k.max_iter = pl.max_iter;
+    k.damping = pl.damping;
     k.bounds_on_device = bounds_on_device ? 1 : 0;
     k.n = pl.n;
     k.ld = pl.ld;
@@ -626,7 +631,7 @@ int chebdm_coeffs(chebdm_handle h, double beta, double mu, double emin, double e
     CHECK(plan_quadrature(pl, beta, emin, emax));
     CHECK(ensure_small(h, pl.M));
     HIP_TRY(launch_set_scalars(h->scal, emin, emax, beta, mu, 1, 0.0, 0.0, 0, h->stream));
-    HIP_TRY(launch_fermi_coeffs(order, pl.M, h->scal, h->ftab, h->c, h->stream));
+    HIP_TRY(launch_fermi_coeffs(order, pl.M, h->scal, h->ftab, h->c, h->stream, pl.damping));
     HIP_TRY(hipMemcpyAsync(c_out, h->c, sizeof(double) * (size_t)(order + 1), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     return CHEBDM_OK;
@@ -695,7 +700,7 @@ int chebdm_density(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, do
         HIP_TRY(launch_set_scalars(h->scal, emin, emax, beta, mu, 1, 0.0, pl.tol, pl.max_iter, h->stream,
                                    bounds_dev));
         HIP_TRY(launch_shift(dH, n, ldh, h->scal, tslot(h, pl, 1), pl.ld, pl.prec, h->stream));
-        HIP_TRY(launch_fermi_coeffs(order, pl.M, h->scal, h->ftab, h->c, h->stream));
+        HIP_TRY(launch_fermi_coeffs(order, pl.M, h->scal, h->ftab, h->c, h->stream, pl.damping));
         HIP_TRY(launch_block_coeffs(h->c, order, pl.k, pl.m, pl.form, h->coef, h->stream));
         CHECK(baby_steps(h, pl, &pl.n_gemm));
         CHECK(giant_steps(h, pl, dD, ldd, &pl.n_gemm));
@@ -752,11 +757,11 @@ int chebdm_mu_search(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, 
         CHECK(moments_on_device(h, pl, &pl.n_gemm));
         size_t ev = (size_t)-1;
         if (h->prof) CHECK(prof_begin(h, PROF_SEARCH, 0, 0.0, 0.0, &ev));
-        HIP_TRY(launch_dct3(h->tau, order, pl.M, h->w, h->xtab, h->stream));
+        HIP_TRY(launch_dct3(h->tau, order, pl.M, h->w, h->xtab, h->stream, pl.damping));
         HIP_TRY(launch_bisect(h->w, h->xtab, pl.M, h->scal, pl.search, h->stream));
         if (h->prof) CHECK(prof_end(h, ev));
         if (dD) {
-            HIP_TRY(launch_fermi_coeffs(order, pl.M, h->scal, h->ftab, h->c, h->stream));
+            HIP_TRY(launch_fermi_coeffs(order, pl.M, h->scal, h->ftab, h->c, h->stream, pl.damping));
             HIP_TRY(launch_block_coeffs(h->c, order, pl.k, pl.m, pl.form, h->coef, h->stream));
             CHECK(giant_steps(h, pl, dD, ldd, &pl.n_gemm));
         }

@@ -301,6 +301,8 @@ int chebdm_batch_create(chebdm_handle h, int32_t count, const int64_t* n, int32_
     if (o.n_quad != 0) return fail(CHEBDM_ERR_UNSUPPORTED, "the batched path sizes the quadrature per problem");
     if (o.search != CHEBDM_SEARCH_BISECTION && o.search != CHEBDM_SEARCH_NEWTON)
         return fail(CHEBDM_ERR_ARG, "unknown mu search");
+    if (o.damping != CHEBDM_DAMPING_NONE && o.damping != CHEBDM_DAMPING_JACKSON)
+        return fail(CHEBDM_ERR_ARG, "unknown damping");
     if (order < 2) return fail(CHEBDM_ERR_ARG, "the batched path needs order >= 2");
     int64_t k = o.k_override;
     if (k <= 0) {
@@ -328,7 +330,7 @@ int chebdm_batch_create(chebdm_handle h, int32_t count, const int64_t* n, int32_
     b->search_mode = o.search;
     int lmax = (order - 1) / (int)k;
     if (lmax > (int)m - 1) lmax = (int)m - 1;
-    b->d = BatchDims{count, order, (int)k, (int)m, lmax, nmax, 0, mcap, o.prec};
+    b->d = BatchDims{count, order, (int)k, (int)m, lmax, nmax, 0, mcap, o.prec, o.damping};
     b->steps_pre = (int)(k - 1) + (lmax >= 2 ? lmax - 1 : 0);
     b->steps = b->steps_pre + (int)(m - 1);
     b->n.assign(n, n + count);

@@ -18,6 +18,15 @@ __device__ inline double fermi_scaled(double x, double beta_s, double mu_s) {
     return 1.0 / (1.0 + exp(beta_s * (x - mu_s)));
 }
 
+// Jackson damping factor g_n of a series of N = order + 1 terms (kernel polynomial method):
+// g_n = [(N - n + 1) cos(pi n/(N+1)) + sin(pi n/(N+1)) cot(pi/(N+1))] / (N + 1); 1 if damping == 0.
+__device__ inline double damping_factor(int damping, int n, int order) {
+    if (damping == 0) return 1.0;
+    const double N1 = (double)order + 2.0;   // N + 1
+    const double u = (double)n / N1;
+    return (((double)order + 2.0 - n) * cospi(u) + sinpi(u) * cospi(1.0 / N1) / sinpi(1.0 / N1)) / N1;
+}
+
 // Distance from |v| to the next larger double (|v| = 0 is taken as 1e-300).
 __device__ inline double ulp_spacing(double v) {
     const double a = v != 0.0 ? fabs(v) : 1e-300;

@@ -72,13 +72,13 @@ hipError_t launch_copy_out(const void* src, int is_f64, int64_t ld, int64_t n, d
 
 // ---- coefficients / decomposition / moments / bisection (k_cheb.hip)
 hipError_t launch_fermi_coeffs(int order, int M, const DevScalars* s, double* f_tab, double* c_out,
-                               hipStream_t st);
+                               hipStream_t st, int damping = 0);
 hipError_t launch_block_coeffs(const double* c, int order, int k, int m, int form, double* coef,
                                hipStream_t st);
 hipError_t launch_assemble_moments(const double* tr_baby, const double* gram, int k, int m,
                                    int order, int64_t n, double* tau, hipStream_t st);
-hipError_t launch_dct3(const double* tau, int order, int M, double* w, double* x_tab,
-                       hipStream_t st);
+hipError_t launch_dct3(const double* tau, int order, int M, double* w, double* x_tab, hipStream_t st,
+                       int damping = 0);
 hipError_t launch_bisect(const double* w, const double* x_tab, int M, DevScalars* s, int mode,
                          hipStream_t st);
 
@@ -134,6 +134,7 @@ struct BatchDims {         // shared sizes of a plan
     int count, order, k, m, lmax;
     int64_t nmax, ldmax, mcap;
     int prec;
+    int damping;           // enum chebdm_damping
 };
 hipError_t launch_batch_zero(int* p, int n, hipStream_t st);
 hipError_t launch_batch_bounds(const BatchDims& d, const BatchProblem* tab, const BatchGeom* geo, double* colsum,

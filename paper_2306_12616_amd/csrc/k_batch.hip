@@ -299,10 +299,11 @@ k_batch_tau(const BatchGeom* __restrict__ geo, const double* __restrict__ trb, c
 // ---- quadrature tables and the bisection
 __global__ void __launch_bounds__(256)
 k_batch_dct3(const double* __restrict__ tau, int order, const int64_t* __restrict__ mq, int64_t mcap,
-             double* __restrict__ w, double* __restrict__ x) {
+             double* __restrict__ w, double* __restrict__ x, int damping) {
     extern __shared__ double st[];
     const int p = blockIdx.y;
-    for (int i = threadIdx.x; i <= order; i += 256) st[i] = tau[(int64_t)p * (order + 1) + i];
+    for (int i = threadIdx.x; i <= order; i += 256)
+        st[i] = tau[(int64_t)p * (order + 1) + i] * damping_factor(damping, i, order);
     __syncthreads();
     const int64_t M = mq[p], j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= M) return;
@@ -357,7 +358,7 @@ k_batch_fermi(const int64_t* __restrict__ mq, int64_t mcap, const DevScalars* __
 
 __global__ void __launch_bounds__(256)
 k_batch_dct2(const int64_t* __restrict__ mq, int64_t mcap, const double* __restrict__ f, int order,
-             double* __restrict__ c) {
+             double* __restrict__ c, int damping) {
     __shared__ double smem[4];
     const int p = blockIdx.y;
     const int64_t n = blockIdx.x, M = mq[p], mod = 4 * M;
@@ -371,7 +372,8 @@ k_batch_dct2(const int64_t* __restrict__ mq, int64_t mcap, const double* __restr
         if (q >= mod) q -= mod;
     }
     acc = block_sum<256>(acc, smem);
-    if (threadIdx.x == 0) c[(int64_t)p * (order + 1) + n] = (n == 0 ? 1.0 : 2.0) * acc / (double)M;
+    if (threadIdx.x == 0)
+        c[(int64_t)p * (order + 1) + n] = (n == 0 ? 1.0 : 2.0) * acc / (double)M * damping_factor(damping, (int)n, order);
 }
 
 // e_{l,0} = c_{lk}; e_{l,i} = 2 c_{lk+i} - e_{l+1,k-i} (l >= 1); e_{0,i} = c_i - e_{1,k-i}/2
@@ -625,7 +627,7 @@ hipError_t launch_batch_bisect(const BatchDims& d, const double* tau, const int6
 hipError_t launch_batch_search(const BatchDims& d, const double* tau, const int64_t* mq, double* w, double* x,
                                DevScalars* s, int mode, const float* mu_hat, double delta, hipStream_t st) {
     hipLaunchKernelGGL(k_batch_dct3, dim3((unsigned)((d.mcap + 255) / 256), (unsigned)d.count), dim3(256),
-                       sizeof(double) * (size_t)(d.order + 1), st, tau, d.order, mq, d.mcap, w, x);
+                       sizeof(double) * (size_t)(d.order + 1), st, tau, d.order, mq, d.mcap, w, x, d.damping);
     hipLaunchKernelGGL(k_batch_search, dim3((unsigned)d.count), dim3(kBisect), 0, st, mq, d.mcap, (const double*)w,
                        (const double*)x, s, mode, mu_hat, delta);
     return hipGetLastError();
@@ -642,7 +644,7 @@ hipError_t launch_batch_coeffs(const BatchDims& d, const int64_t* mq, const DevS
     hipLaunchKernelGGL(k_batch_fermi, dim3((unsigned)((d.mcap + 255) / 256), (unsigned)d.count), dim3(256), 0, st, mq,
                        d.mcap, s, ftab);
     hipLaunchKernelGGL(k_batch_dct2, dim3((unsigned)(d.order + 1), (unsigned)d.count), dim3(256), 0, st, mq, d.mcap,
-                       (const double*)ftab, d.order, c);
+                       (const double*)ftab, d.order, c, d.damping);
     hipLaunchKernelGGL(k_batch_cform, dim3((unsigned)d.count), dim3(64), 0, st, (const double*)c, d.order, d.k, d.m,
                        coef);
     return hipGetLastError();

@@ -53,7 +53,7 @@ k_fermi_table(int64_t M, const DevScalars* __restrict__ s, double* __restrict__ 
 
 // One workgroup per coefficient n: c_n = (2 - delta_{n0})/M sum_j f_j cos(n theta_j).
 __global__ void __launch_bounds__(256)
-k_dct2(int64_t M, const double* __restrict__ f, double* __restrict__ c) {
+k_dct2(int64_t M, const double* __restrict__ f, double* __restrict__ c, int order, int damping) {
     __shared__ double smem[4];
     const int64_t n = blockIdx.x;
     const int64_t mod = 4 * M;
@@ -67,7 +67,7 @@ k_dct2(int64_t M, const double* __restrict__ f, double* __restrict__ c) {
         if (q >= mod) q -= mod;
     }
     acc = block_sum<256>(acc, smem);
-    if (threadIdx.x == 0) c[n] = (n == 0 ? 1.0 : 2.0) * acc / (double)M;
+    if (threadIdx.x == 0) c[n] = (n == 0 ? 1.0 : 2.0) * acc / (double)M * damping_factor(damping, (int)n, order);
 }
 
 // Block coefficients, one workgroup.  Output coef[l*k + i] = weight of T_i in block l.
@@ -165,9 +165,10 @@ k_assemble_moments(const double* __restrict__ tr_baby, const double* __restrict_
 // w_j = sum_n (2 - delta_{n0}) tau_n cos(n theta_j); also stores x_j.
 __global__ void __launch_bounds__(256)
 k_dct3(const double* __restrict__ tau, int order, int64_t M, double* __restrict__ w,
-       double* __restrict__ x_tab) {
+       double* __restrict__ x_tab, int damping) {
     extern __shared__ double st[];
-    for (int i = threadIdx.x; i <= order; i += 256) st[i] = tau[i];
+    // with damping, t(mu~) = sum_n g_n c_n(mu~) tau_n: the factors go onto the moments
+    for (int i = threadIdx.x; i <= order; i += 256) st[i] = tau[i] * damping_factor(damping, i, order);
     __syncthreads();
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= M) return;
@@ -203,11 +204,11 @@ hipError_t launch_set_scalars(DevScalars* s, double emin, double emax, double be
 }
 
 hipError_t launch_fermi_coeffs(int order, int M, const DevScalars* s, double* f_tab, double* c_out,
-                               hipStream_t st) {
+                               hipStream_t st, int damping) {
     hipLaunchKernelGGL(k_fermi_table, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
                        (int64_t)M, s, f_tab);
     hipLaunchKernelGGL(k_dct2, dim3((unsigned)(order + 1)), dim3(256), 0, st, (int64_t)M,
-                       (const double*)f_tab, c_out);
+                       (const double*)f_tab, c_out, order, damping);
     return hipGetLastError();
 }
 
@@ -225,10 +226,10 @@ hipError_t launch_assemble_moments(const double* tr_baby, const double* gram, in
 }
 
 hipError_t launch_dct3(const double* tau, int order, int M, double* w, double* x_tab,
-                       hipStream_t st) {
+                       hipStream_t st, int damping) {
     const size_t shmem = sizeof(double) * (size_t)(order + 1);
     hipLaunchKernelGGL(k_dct3, dim3((unsigned)((M + 255) / 256)), dim3(256), shmem, st, tau, order,
-                       (int64_t)M, w, x_tab);
+                       (int64_t)M, w, x_tab, damping);
     return hipGetLastError();
 }
 

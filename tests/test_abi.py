@@ -38,10 +38,12 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version_and_defaults(lib):
-    assert lib.chebdm_abi_version() == 2
+    assert lib.chebdm_abi_version() == 3
     o = chebdm.make_opts()
-    assert (o.prec, o.giant_form, o.k_override, o.n_quad, o.max_iter, o.baby_steps, o.search, o.tol) == \
-        (0, 0, 0, 0, 200, 0, 0, 1e-10)
+    assert (o.prec, o.giant_form, o.k_override, o.n_quad, o.max_iter, o.baby_steps, o.search, o.damping, o.tol) == \
+        (0, 0, 0, 0, 200, 0, 0, 0, 1e-10)
+    assert chebdm.make_opts(damping="jackson").damping == 1
+    assert ctypes.sizeof(chebdm.Opts) == 40   # eight int32 then one double
     assert chebdm.make_opts(search="newton").search == 1
 
 

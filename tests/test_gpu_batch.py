@@ -185,3 +185,21 @@ def test_batch_512_uneven_workload_sampled(cd, handle):
         _say(f"  p={p} n={sizes[p]} err={err:.2e} t_err={t_err:.2e}")
         assert err <= 1e-5 and t_err <= 1e-5 * sizes[p]
     batch.close()
+
+
+def test_batch_jackson_damping_matches_oracle(cd, handle):
+    sizes = [100, 170]
+    order, betas, nes = 96, [40.0, 55.0], [49.5, 80.5]
+    probs, Hs = _make(sizes, 2100)
+    batch = cd.Batch(handle, sizes, order, cd.make_opts("fp64", damping="jackson"))
+    mu, Ds, status, iters, trace = batch.mu_search(Hs, betas, nes)
+    for p, n in enumerate(sizes):
+        h, q, lam = probs[p]
+        lo, hi = ch.gershgorin_bounds(h)
+        cen, a = ch.scaling(lo, hi)
+        M = ch.quadrature_size(order, betas[p] * a)
+        c = ch.chebyshev_coeffs(order, betas[p] * a, (mu[p] - cen) / a, M, "jackson")
+        ref = ch.density_from_eigs(q, lam, c, lo, hi)
+        assert float(np.max(np.abs(Ds[p].cpu().numpy() - ref))) <= 1e-10
+        assert abs(ch.trace_of_series(c, ch.moments_from_eigs(lam, lo, hi, order)) - nes[p]) <= 1e-9
+    batch.close()

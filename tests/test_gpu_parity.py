@@ -395,3 +395,23 @@ def test_bounds_survive_scalar_workspace_growth(cd):
         assert abs(t_or - 150.5) <= 1e-9
     finally:
         h2.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_jackson_damping_matches_oracle(cd, handle, prec, tol):
+    n, order, beta, ne = 260, 150, 60.0, 120.5
+    h, q, lam = synth.hamiltonian(n, "gaussmix6", seed=77)
+    mu, D, info = cd.chebdm_mu_search(handle, _dev(h), beta, ne, order, cd.make_opts(prec, damping="jackson"))
+    assert info["status"] == 0
+    emin, emax = info["emin"], info["emax"]
+    cen, a = ch.scaling(emin, emax)
+    c = ch.chebyshev_coeffs(order, beta * a, (mu - cen) / a, info["n_quad"], "jackson")
+    ref = ch.density_from_eigs(q, lam, c, emin, emax)
+    err = float(np.max(np.abs(D.cpu().numpy() - ref)))
+    t_or = ch.trace_of_series(c, ch.moments_from_eigs(lam, emin, emax, order))
+    _say(f"  jackson {prec}: err={err:.2e} |t_oracle-Ne|={abs(t_or - ne):.2e}")
+    assert err <= tol
+    assert abs(t_or - ne) <= (1e-9 if prec == "fp64" else 1e-5 * n)
+    # the damped occupations stay in [0, 1]: D's eigenvalues p_J(lam~) are in [0, 1]
+    p = ch.cheb_eval(c, (lam - cen) / a)
+    assert p.min() > -1e-12 and p.max() < 1 + 1e-12
