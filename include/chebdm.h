@@ -210,6 +210,17 @@ int chebdm_mu_search(chebdm_handle h, const double* dH, int64_t n, int64_t ldh,
                      chebdm_info* info);
 
 /*
+ * Device memory a call of chebdm_density / chebdm_mu_search / chebdm_moments
+ * with these sizes and options makes the handle hold (it keeps the largest it
+ * has needed): the matrix workspace, (k + m) ld^2 elements with
+ * ld = round_up(n, 128) and 8 (float64) or 4 bytes per element, plus the
+ * small buffers sized for opts->n_quad quadrature nodes (2^16 when 0).
+ * Needs no device; h may be NULL.  ERR_ARG on bad sizes or options.
+ */
+int chebdm_workspace_size(chebdm_handle h, int64_t n, int32_t order, const chebdm_opts* opts,
+                          size_t* bytes);
+
+/*
  * Trace moments tau_0..tau_L of T_n(H~) (the quantities the mu search
  * bisects on), computed as in chebdm_mu_search.  tau_out: host, order+1 doubles.
  */

@@ -115,6 +115,8 @@ _SIGNATURES = {
     "chebdm_mlp_adam": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
                                        ctypes.c_float, ctypes.c_float]),
+    "chebdm_workspace_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(Opts),
+                                             ctypes.POINTER(ctypes.c_size_t)]),
     "chebdm_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "chebdm_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Profile)]),
 }
@@ -298,6 +300,14 @@ def chebdm_moments(h: Handle, H, order: int, opts: Optional[Opts] = None, emin: 
 
 def chebdm_profile_enable(h: Handle, enable: bool = True):
     _check(load_library().chebdm_profile_enable(h.ptr, 1 if enable else 0))
+
+
+def chebdm_workspace_size(n: int, order: int, opts: Optional[Opts] = None) -> int:
+    """Device bytes a handle holds for calls of this size (no device needed)."""
+    out = ctypes.c_size_t()
+    _check(load_library().chebdm_workspace_size(None, int(n), int(order),
+                                                ctypes.byref(opts) if opts is not None else None, ctypes.byref(out)))
+    return int(out.value)
 
 
 def chebdm_profile_read(h: Handle):

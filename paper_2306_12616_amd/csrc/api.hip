@@ -95,13 +95,18 @@ int set_device(chebdm_handle h) {
 
 static_assert(sizeof(DevScalars) <= 64 * sizeof(double), "scalars must fit their 64-double slot");
 
+size_t small_bytes_for(int64_t M) {
+    const int64_t Mcap = M < 4096 ? 4096 : M;
+    const int64_t doubles = 64 /*scalars*/ + 4 * kSmallVec + 48 * 48 + 64 + 3 * Mcap + kPartialDoubles;
+    return (size_t)doubles * sizeof(double);
+}
+
 // Grows the small buffers.  The scalars carry over into a new allocation: the Gershgorin
 // bounds written there by the bounds kernels are read back on the device by later kernels.
 int ensure_small(chebdm_handle h, int64_t M) {
     if (h->small && M <= h->small_M) return 0;
     const int64_t Mcap = M < 4096 ? 4096 : M;
-    const int64_t doubles = 64 /*scalars*/ + 4 * kSmallVec + 48 * 48 + 64 + 3 * Mcap + kPartialDoubles;
-    const size_t bytes = (size_t)doubles * sizeof(double);
+    const size_t bytes = small_bytes_for(M);
     void* fresh = nullptr;
     if (hipMalloc(&fresh, bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -777,6 +782,22 @@ int chebdm_mu_search(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, 
     if (status == CHEBDM_ERR_BRACKET)
         return fail(CHEBDM_ERR_BRACKET, "n_elec is not inside (t(mu~=-1), t(mu~=1)) of the expansion");
     return status;
+}
+
+int chebdm_workspace_size(chebdm_handle h, int64_t n, int32_t order, const chebdm_opts* opts, size_t* bytes) {
+    (void)h;
+    if (!bytes) return fail(CHEBDM_ERR_ARG, "NULL argument");
+    if (n < 1) return fail(CHEBDM_ERR_ARG, "n < 1");
+    if (order < 0) return fail(CHEBDM_ERR_ARG, "order < 0");
+    Plan pl;
+    pl.n = n;
+    pl.order = order;
+    CHECK(check_opts(opts, pl));
+    CHECK(plan_split(pl));
+    const int64_t ld = round_up(n, 128);
+    const int64_t M = opts && opts->n_quad > 0 ? opts->n_quad : (int64_t)1 << 16;
+    *bytes = (size_t)(pl.k + pl.m) * (size_t)ld * (size_t)ld * pl.elem + small_bytes_for(M);
+    return CHEBDM_OK;
 }
 
 int chebdm_moments(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, int32_t order,

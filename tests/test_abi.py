@@ -86,3 +86,14 @@ def test_block_split_override_and_limits(lib):
     assert lib.chebdm_block_coeffs(dummy, None, 48 * 48, 0, 0, ctypes.byref(kk), ctypes.byref(mm), None) == _binding.ERR_ARG
     assert lib.chebdm_block_coeffs(dummy, None, -1, 0, 0, ctypes.byref(kk), ctypes.byref(mm), None) == _binding.ERR_ARG
     assert lib.chebdm_block_coeffs(dummy, None, 10, 5, 0, ctypes.byref(kk), ctypes.byref(mm), None) == _binding.ERR_ARG
+
+
+def test_workspace_size_needs_no_device(lib):
+    # (k + m) ld^2 elements plus the small buffers; k = m = 23 at order 512, ld = 4096 at n = 4000
+    small = chebdm.chebdm_workspace_size(1, 0)
+    f64 = chebdm.chebdm_workspace_size(4000, 512)
+    f32 = chebdm.chebdm_workspace_size(4000, 512, chebdm.make_opts("fp32"))
+    assert f64 - small >= 46 * 4096 * 4096 * 8 - 2 * 128 * 128 * 8
+    assert f64 - f32 == 46 * 4096 * 4096 * 4
+    with pytest.raises(chebdm.ChebdmError):
+        chebdm.chebdm_workspace_size(0, 10)
