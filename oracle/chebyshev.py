@@ -5,7 +5,8 @@ the expansion sum c_n T_n, the spectral map by the extreme eigenvalues).
 The readings where the paper is silent are stated per function:
 
 * spectrum map: H~ = (2H - (e_a + e_b) I)/(e_b - e_a), T_0 = I, T_1 = H~;
-* extreme eigenvalues e_a, e_b: Gershgorin discs (an outer bound);
+* extreme eigenvalues e_a, e_b: Gershgorin discs (an outer bound), or optionally a
+  few Lanczos steps with a residual widening (tighter, see lanczos_bounds);
 * coefficients: Chebyshev-Gauss projection with M nodes (a DCT-II), no damping;
 * chemical potential: bisection of tr D_L(mu) = N_e on the scaled interval [-1, 1].
 
@@ -34,6 +35,98 @@ def gershgorin_bounds(h: np.ndarray):
     diag = np.diag(h)
     radius = np.abs(h).sum(axis=1) - np.abs(diag)
     return float(np.min(diag - radius)), float(np.max(diag + radius))
+
+
+def splitmix64(count: int, seed: int = 0):
+    """The first `count` outputs of SplitMix64 (Steele, Lea, Flood, OOPSLA 2014) seeded with
+    `seed`: state_i = seed + (i + 1) * 0x9E3779B97F4A7C15 (mod 2^64), then two
+    xor-shift-multiply rounds and a final xor-shift (the published finaliser)."""
+    mask = (1 << 64) - 1
+    out = []
+    for i in range(count):
+        z = (seed + (i + 1) * 0x9E3779B97F4A7C15) & mask
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & mask
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & mask
+        out.append(z ^ (z >> 31))
+    return out
+
+
+def splitmix64_uniform(count: int, seed: int = 0) -> np.ndarray:
+    """count doubles in [-1, 1): u = (top 53 bits of output i) * 2^-53, returned as 2u - 1 (exact)."""
+    return np.array([2.0 * ((z >> 11) * 2.0 ** -53) - 1.0 for z in splitmix64(count, seed)])
+
+
+LANCZOS_BREAKDOWN = 1e-12   # beta_j <= this * max(|g_lo|, |g_hi|) ends the recurrence
+
+
+def lanczos(h: np.ndarray, steps: int, seed: int = 0, scale: float | None = None):
+    """Lanczos tridiagonalisation with one full reorthogonalisation pass per step.
+
+    Start vector: SplitMix64 doubles in [-1, 1) of `seed`, normalised.  Step j:
+    w = H v_j;  alpha_j = v_j . w;  w -= alpha_j v_j + beta_{j-1} v_{j-1};
+    w -= V (V^T w) over v_0..v_j;  beta_j = ||w||;  v_{j+1} = w / beta_j.
+    The recurrence stops after min(steps, n) steps, or after step j when
+    beta_j <= LANCZOS_BREAKDOWN * scale (an invariant subspace: the Ritz values
+    are then eigenvalues).  scale defaults to the Gershgorin bound max(|g_lo|, |g_hi|).
+    Returns (alpha, beta, V) with len(alpha) = len(beta) = steps done and V of shape
+    (steps done, n).
+    """
+    n = h.shape[0]
+    if scale is None:
+        g_lo, g_hi = gershgorin_bounds(h)
+        scale = max(abs(g_lo), abs(g_hi))
+    k = min(steps, n)
+    v = splitmix64_uniform(n, seed)
+    v = v / np.linalg.norm(v)
+    V = np.zeros((k, n))
+    alpha, beta = np.zeros(k), np.zeros(k)
+    for j in range(k):
+        V[j] = v
+        w = h @ v
+        alpha[j] = v @ w
+        w = w - alpha[j] * v
+        if j > 0:
+            w = w - beta[j - 1] * V[j - 1]
+        w = w - V[: j + 1].T @ (V[: j + 1] @ w)
+        beta[j] = np.linalg.norm(w)
+        if beta[j] <= LANCZOS_BREAKDOWN * scale:
+            k = j + 1
+            break
+        v = w / beta[j]
+    return alpha[:k], beta[:k], V[:k]
+
+
+def tridiag_eigvals(alpha, beta) -> np.ndarray:
+    """Eigenvalues (ascending) of the symmetric tridiagonal matrix with diagonal alpha and
+    off-diagonal beta[0..k-2]."""
+    k = len(alpha)
+    t = np.diag(np.asarray(alpha, dtype=np.float64))
+    if k > 1:
+        off = np.asarray(beta[: k - 1], dtype=np.float64)
+        t = t + np.diag(off, 1) + np.diag(off, -1)
+    return np.linalg.eigvalsh(t)
+
+
+def lanczos_bounds(h: np.ndarray, steps: int = 40, margin: float = 0.01, seed: int = 0):
+    """Outer spectral bounds from a few Lanczos steps (the paper needs e_a, e_b, Sec. II.B, and
+    names no method; this is the tight alternative to Gershgorin's discs).
+
+    With theta_min, theta_max the extreme Ritz values after k steps and beta_{k-1} the norm of
+    the last residual, the estimate is [theta_min - beta_{k-1}, theta_max + beta_{k-1}] widened
+    on both sides by margin times its width, then intersected with the Gershgorin interval
+    (which always holds the spectrum); if that intersection is empty (rounding, H = cI) the
+    Gershgorin interval is returned.  Returns (emin, emax, alpha, beta).
+    """
+    g_lo, g_hi = gershgorin_bounds(h)
+    alpha, beta, _ = lanczos(h, steps, seed, max(abs(g_lo), abs(g_hi)))
+    theta = tridiag_eigvals(alpha, beta)
+    r = beta[-1]
+    lo, hi = theta[0] - r, theta[-1] + r
+    pad = margin * (hi - lo)
+    lo, hi = max(lo - pad, g_lo), min(hi + pad, g_hi)
+    if lo > hi:
+        lo, hi = g_lo, g_hi
+    return lo, hi, alpha, beta
 
 
 def scaling(emin: float, emax: float):
