@@ -164,6 +164,32 @@ def cpu_baseline(h_np, beta, n_elec, order, budget_s=10.0, max_reps=50):
                       f"(oracle route: LAPACK eigh of H, moments, bisection, Q p(lam) Q^T), {dt:.1f} s"}
 
 
+def lanczos_rows(cd, handle, hs, beta, order, reps=10):
+    """Bounds by Gershgorin vs 40 Lanczos steps: time of the bounds call, interval, beta', and the
+    mu search + density with each (same order; the tighter interval is more accurate, not faster)."""
+    import torch
+
+    out = {}
+    for nn in sorted(hs):
+        H = hs[nn]
+        row = {}
+        for name in ("gershgorin", "lanczos"):
+            call = (lambda: cd.chebdm_bounds(handle, H)) if name == "gershgorin" else \
+                (lambda: cd.chebdm_bounds_lanczos(handle, H, 40, 0.01, 0)[:2])
+            lo, hi = call()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                call()
+            dt = (time.perf_counter() - t0) / reps
+            steps = 20 if nn <= 1000 else 5
+            d2, _, i2 = run_steps(cd, handle, H, beta, nn / 2.0, order, cd.make_opts("fp64", bounds=name), steps, 2)
+            row[name] = {"emin": lo, "emax": hi, "beta_scaled": round(beta * (hi - lo) / 2, 2),
+                         "bounds_ms": round(1e3 * dt, 3), "mu_search_dm_per_s": round(steps / d2, 3)}
+        out[f"n{nn}"] = row
+    return out
+
+
 def batch_row(cd, handle, torch, prec="fp32", order=256, reps=3):
     """Batched form: 512 Hamiltonians, n uniform on {96..1024}, beta on [30, 200], one graph per batch."""
     import numpy as np
@@ -379,8 +405,8 @@ def main():
                                     "products": p3["gemm_products"] // steps,
                                     "gemm_frac_of_peak": r3["frac"] if r3 else None}
         result["fixed_mu"] = fixed
+        result["lanczos_bounds"] = lanczos_rows(cd, handle, hs, beta, order)
         del hs
-            # fixed-mu density only (no ladder / moments / bisection)
         for key, row in rows.items():
             nn = key.split("_")[0]
             base = value if (nn == f"n{n}" and args.prec == "fp64") else rows.get(f"{nn}_fp64", {}).get("dm_per_s")

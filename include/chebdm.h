@@ -20,8 +20,9 @@
  *     stream before returning; chebdm_density with info == NULL does not.
  *   - dD must not alias dH.  The library owns a workspace of about
  *     (k + m) * ld^2 elements, grown on demand and kept until chebdm_destroy.
- *   - emin/emax arguments: pass NAN (both) to let the call compute Gershgorin
- *     bounds of H itself, or the caller's own outer bounds of the spectrum.
+ *   - emin/emax arguments: pass NAN (both) to let the call compute bounds of H
+ *     itself (Gershgorin's, or Lanczos' with opts->bounds), or the caller's own
+ *     outer bounds of the spectrum.
  *   - Return value: CHEBDM_OK (0), a positive warning (result usable), or a
  *     negative error; chebdm_last_error() then describes the failure
  *     (thread-local string).  No C++ exception crosses this interface.
@@ -46,7 +47,7 @@
 extern "C" {
 #endif
 
-#define CHEBDM_ABI_VERSION 3
+#define CHEBDM_ABI_VERSION 4
 
 typedef struct chebdm_ctx* chebdm_handle;
 
@@ -97,6 +98,15 @@ enum chebdm_damping {
     CHEBDM_DAMPING_JACKSON = 1
 };
 
+/* Where NaN bounds are resolved from (the paper needs the extreme eigenvalues
+ * e_a, e_b, Sec. II.B, and names no method).  A tighter interval lowers
+ * beta' = beta (emax - emin)/2 and so the truncation error at a given order. */
+enum chebdm_bounds_method {
+    CHEBDM_BOUNDS_GERSHGORIN = 0, /* Gershgorin discs (always hold the spectrum)       */
+    CHEBDM_BOUNDS_LANCZOS = 1     /* chebdm_bounds_lanczos with seed 0: a few Lanczos  */
+                                  /* steps, residual-widened, inside Gershgorin's      */
+};
+
 enum chebdm_status {
     CHEBDM_OK = 0,
     CHEBDM_WARN_NOCONV = 1,       /* mu search stopped before |t - N_e| < tol    */
@@ -118,6 +128,9 @@ typedef struct {
     int32_t search;      /* enum chebdm_search of chebdm_mu_search, default BISECTION */
     int32_t damping;     /* enum chebdm_damping, default CHEBDM_DAMPING_NONE        */
     double tol;          /* target |tr D - N_e| of the mu search; 0 = 1e-10        */
+    int32_t bounds;      /* enum chebdm_bounds_method for NaN bounds, default GERSHGORIN */
+    int32_t lanczos_steps; /* Lanczos steps; 0 = 40, at most 128                   */
+    double bounds_margin;  /* relative widening of the Lanczos bounds; 0 = 0.01    */
 } chebdm_opts;
 
 typedef struct {
@@ -162,6 +175,33 @@ int chebdm_set_stream(chebdm_handle h, void* stream);
  */
 int chebdm_bounds(chebdm_handle h, const double* dH, int64_t n, int64_t ldh,
                   double* emin, double* emax);
+
+/*
+ * Spectral bounds of H from `steps` Lanczos steps (not in the paper; a
+ * tighter alternative to Gershgorin's discs for e_a, e_b of Sec. II.B).
+ * Start vector: the SplitMix64 generator (Steele, Lea, Flood 2014) of `seed`,
+ * output i mapped to 2 (top 53 bits) 2^-53 - 1, normalised.  Step j:
+ *     w = H v_j,  alpha_j = v_j.w,  w -= alpha_j v_j + beta_{j-1} v_{j-1},
+ *     w -= sum_{i<=j} (v_i.w) v_i (one full reorthogonalisation),
+ *     beta_j = ||w||,  v_{j+1} = w / beta_j,
+ * all in float64 on the device; it stops early when beta_j <= 1e-12 *
+ * max(|g_lo|, |g_hi|), [g_lo, g_hi] the Gershgorin bounds.  With theta the
+ * extreme eigenvalues of the k x k tridiagonal (alpha, beta) and
+ * r = beta_{k-1}, the result is [theta_min - r, theta_max + r] widened by
+ * margin * width on each side and intersected with [g_lo, g_hi] (that
+ * interval alone if the intersection is empty).  Once the extreme Ritz
+ * values have settled (about ten steps for dense H; the default is 40) the
+ * widening by the last residual norm encloses the spectrum in practice, but
+ * it is not a proof, and one or two steps can miss the edges; the Gershgorin
+ * intersection keeps the result inside a proven enclosure.
+ * steps in [1, 128] (min(steps, n) are taken); margin >= 0.
+ * Host outputs: *emin, *emax; alpha_out, beta_out (optional, NULL allowed,
+ * `steps` doubles each: the tridiagonal, beta_out[k-1] = r); *steps_done
+ * (optional): k.  Errors: CHEBDM_ERR_ARG, CHEBDM_ERR_NONFINITE, CHEBDM_ERR_OOM.
+ */
+int chebdm_bounds_lanczos(chebdm_handle h, const double* dH, int64_t n, int64_t ldh,
+                          int32_t steps, double margin, uint64_t seed, double* emin, double* emax,
+                          double* alpha_out, double* beta_out, int32_t* steps_done);
 
 /*
  * Chebyshev coefficients c_0..c_L of the Fermi function on [emin, emax]

@@ -31,7 +31,8 @@ _FORM_NAMES = {"composition": COMPOSITION, "clenshaw": COMPOSITION, "power": POW
 class Opts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("giant_form", ctypes.c_int32), ("k_override", ctypes.c_int32),
                 ("n_quad", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("baby_steps", ctypes.c_int32),
-                ("search", ctypes.c_int32), ("damping", ctypes.c_int32), ("tol", ctypes.c_double)]
+                ("search", ctypes.c_int32), ("damping", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("bounds", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32), ("bounds_margin", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -71,6 +72,11 @@ _SIGNATURES = {
     "chebdm_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "chebdm_bounds": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "chebdm_bounds_lanczos": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                             ctypes.c_int32, ctypes.c_double, ctypes.c_uint64,
+                                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_int32)]),
     "chebdm_coeffs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_double)]),
@@ -150,10 +156,12 @@ def _check(rc: int, allow_warn: bool = False) -> int:
 
 _SEARCH_NAMES = {"bisection": 0, "newton": 1}
 _DAMPING_NAMES = {"none": 0, "jackson": 1}
+_BOUNDS_NAMES = {"gershgorin": 0, "lanczos": 1}
 
 
 def make_opts(prec="fp64", giant="composition", k_override: int = 0, n_quad: int = 0,
-              max_iter: int = 0, tol: float = 0.0, baby="auto", search="bisection", damping="none") -> Opts:
+              max_iter: int = 0, tol: float = 0.0, baby="auto", search="bisection", damping="none",
+              bounds="gershgorin", lanczos_steps: int = 0, bounds_margin: float = 0.0) -> Opts:
     o = Opts()
     load_library().chebdm_default_opts(ctypes.byref(o))
     o.prec = _PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
@@ -163,6 +171,9 @@ def make_opts(prec="fp64", giant="composition", k_override: int = 0, n_quad: int
     o.baby_steps = _BABY_NAMES[baby] if isinstance(baby, str) else int(baby)
     o.search = _SEARCH_NAMES[search] if isinstance(search, str) else int(search)
     o.damping = _DAMPING_NAMES[damping] if isinstance(damping, str) else int(damping)
+    o.bounds = _BOUNDS_NAMES[bounds] if isinstance(bounds, str) else int(bounds)
+    o.lanczos_steps = int(lanczos_steps)
+    o.bounds_margin = float(bounds_margin)
     if max_iter:
         o.max_iter = int(max_iter)
     if tol:
@@ -224,6 +235,21 @@ def chebdm_bounds(h: Handle, H):
     lo, hi = ctypes.c_double(), ctypes.c_double()
     _check(load_library().chebdm_bounds(h.ptr, p, n, ld, ctypes.byref(lo), ctypes.byref(hi)))
     return lo.value, hi.value
+
+
+def chebdm_bounds_lanczos(h: Handle, H, steps: int = 40, margin: float = 0.01, seed: int = 0):
+    """(emin, emax, alpha, beta): Lanczos bounds and the tridiagonal (alpha, beta of the steps done)."""
+    p, n, ld = _matrix_args(H, "H")
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    a = np.zeros(steps, dtype=np.float64)
+    b = np.zeros(steps, dtype=np.float64)
+    done = ctypes.c_int32()
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(load_library().chebdm_bounds_lanczos(h.ptr, p, n, ld, int(steps), float(margin), int(seed),
+                                                ctypes.byref(lo), ctypes.byref(hi), a.ctypes.data_as(dp),
+                                                b.ctypes.data_as(dp), ctypes.byref(done)))
+    k = done.value
+    return lo.value, hi.value, a[:k], b[:k]
 
 
 def chebdm_coeffs(h: Handle, beta: float, mu: float, emin: float, emax: float, order: int, n_quad: int = 0):

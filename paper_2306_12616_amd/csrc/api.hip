@@ -77,6 +77,8 @@ struct Plan {
     int max_iter = 200;
     int search = CHEBDM_SEARCH_BISECTION;
     int damping = CHEBDM_DAMPING_NONE;
+    int bounds = CHEBDM_BOUNDS_GERSHGORIN, lz_steps = 40;
+    double lz_margin = 0.01;
     double tol = 1e-10;
     size_t elem = 8;
     int n_gemm = 0;
@@ -201,6 +203,15 @@ int check_opts(const chebdm_opts* o, Plan& pl) {
     if (o->damping != CHEBDM_DAMPING_NONE && o->damping != CHEBDM_DAMPING_JACKSON)
         return fail(CHEBDM_ERR_ARG, "unknown damping");
     pl.damping = o->damping;
+    if (o->bounds != CHEBDM_BOUNDS_GERSHGORIN && o->bounds != CHEBDM_BOUNDS_LANCZOS)
+        return fail(CHEBDM_ERR_ARG, "unknown bounds method");
+    if (o->lanczos_steps < 0 || o->lanczos_steps > kMaxLanczosSteps)
+        return fail(CHEBDM_ERR_ARG, "lanczos_steps must be in [0, 128]");
+    if (!(o->bounds_margin >= 0.0) || !std::isfinite(o->bounds_margin))
+        return fail(CHEBDM_ERR_ARG, "bounds_margin must be finite and >= 0");
+    pl.bounds = o->bounds;
+    pl.lz_steps = o->lanczos_steps ? o->lanczos_steps : 40;
+    pl.lz_margin = o->bounds_margin > 0.0 ? o->bounds_margin : 0.01;
     pl.baby = o->baby_steps != CHEBDM_BABY_AUTO
                   ? o->baby_steps
                   : (o->prec == CHEBDM_FP64 ? CHEBDM_BABY_STAGES : CHEBDM_BABY_SEQUENTIAL);
@@ -238,11 +249,18 @@ int validate_matrix(const void* dH, int64_t n, int64_t ldh) {
     return 0;
 }
 
-// Bounds: the caller's, or Gershgorin's computed here (one read-back).
-int resolve_bounds(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, double& emin, double& emax) {
+int lanczos_on_device(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, int steps, double margin,
+                      uint64_t seed);
+
+// Bounds: the caller's, or computed here (one read-back): Gershgorin's, then with
+// CHEBDM_BOUNDS_LANCZOS the Lanczos bounds inside them.
+int resolve_bounds(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, double& emin, double& emax,
+                   const Plan* pl = nullptr) {
     if (std::isnan(emin) || std::isnan(emax)) {
         CHECK(ensure_small(h, 0));
         HIP_TRY(launch_gershgorin(dH, n, ldh, h->partial, kPartialDoubles, h->scal, h->stream));
+        if (pl && pl->bounds == CHEBDM_BOUNDS_LANCZOS)
+            CHECK(lanczos_on_device(h, dH, n, ldh, pl->lz_steps, pl->lz_margin, 0));
         CHECK(read_scalars(h));
         if (h->h_scal->nonfinite) return fail(CHEBDM_ERR_NONFINITE, "H holds NaN or Inf");
         emin = h->h_scal->emin;
@@ -405,6 +423,58 @@ int run_replayed(chebdm_handle h, int slot, const std::vector<char>& key, int* p
     *products = r.products;
     HIP_TRY(hipGraphLaunch(r.exec, h->stream));
     return 0;
+}
+
+// ---------------------------------------------------------------- Lanczos bounds
+
+struct LanczosKey {
+    const void *dH, *lz, *small;
+    int64_t n, ldh;
+    int32_t steps, pad;
+    double margin;
+    uint64_t seed;
+};
+
+int ensure_lanczos(chebdm_handle h, int64_t n, int steps) {
+    const int64_t need = lanczos_work_doubles(n, steps);
+    if (need <= h->lz_doubles) return 0;
+    drop_replay(h->replay[3]);
+    if (h->lz) HIP_TRY(hipFree(h->lz));
+    h->lz = nullptr;
+    h->lz_doubles = 0;
+    if (hipMalloc(&h->lz, sizeof(double) * (size_t)need) != hipSuccess) {
+        h->lz = nullptr;
+        (void)hipGetLastError();
+        return fail(CHEBDM_ERR_OOM, "cannot allocate the Lanczos workspace");
+    }
+    h->lz_doubles = need;
+    return 0;
+}
+
+// Lanczos bounds into h->scal (which holds the Gershgorin bounds); the launch sequence is
+// captured once per argument set and replayed.
+int lanczos_on_device(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, int steps, double margin,
+                      uint64_t seed) {
+    const int k = (int)std::min<int64_t>(steps, n);
+    CHECK(ensure_lanczos(h, n, k));
+    LanczosKey lk;
+    std::memset(&lk, 0, sizeof(lk));
+    lk.dH = dH;
+    lk.lz = h->lz;
+    lk.small = h->small;
+    lk.n = n;
+    lk.ldh = ldh;
+    lk.steps = k;
+    lk.margin = margin;
+    lk.seed = seed;
+    std::vector<char> key(sizeof(lk));
+    std::memcpy(key.data(), &lk, sizeof(lk));
+    int unused = 0;
+    const LanczosWork L = lanczos_layout(h->lz, n, k);
+    return run_replayed(h, 3, key, &unused, [&]() -> int {
+        HIP_TRY(launch_lanczos(dH, n, ldh, k, margin, seed, L, h->scal, h->stream));
+        return 0;
+    });
 }
 
 // P_2(Y) .. P_K(Y) from P_1 = Y and P_0 = I for the Chebyshev polynomials P_i = T_i of a
@@ -598,6 +668,7 @@ int chebdm_destroy(chebdm_handle h) {
     if (h->cap) (void)hipStreamDestroy(h->cap);
     if (h->mats) (void)hipFree(h->mats);
     if (h->small) (void)hipFree(h->small);
+    if (h->lz) (void)hipFree(h->lz);
     if (h->mlp_work) (void)hipFree(h->mlp_work);
     if (h->h_scal) (void)hipHostFree(h->h_scal);
     delete h;
@@ -618,6 +689,36 @@ int chebdm_bounds(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, dou
     CHECK(resolve_bounds(h, dH, n, ldh, lo, hi));
     *emin = lo;
     *emax = hi;
+    return CHEBDM_OK;
+}
+
+int chebdm_bounds_lanczos(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, int32_t steps, double margin,
+                          uint64_t seed, double* emin, double* emax, double* alpha_out, double* beta_out,
+                          int32_t* steps_done) {
+    if (!h || !emin || !emax) return fail(CHEBDM_ERR_ARG, "NULL argument");
+    CHECK(validate_matrix(dH, n, ldh));
+    if (steps < 1 || steps > kMaxLanczosSteps) return fail(CHEBDM_ERR_ARG, "steps must be in [1, 128]");
+    if (!(margin >= 0.0) || !std::isfinite(margin)) return fail(CHEBDM_ERR_ARG, "margin must be finite and >= 0");
+    CHECK(set_device(h));
+    CHECK(ensure_small(h, 0));
+    HIP_TRY(launch_gershgorin(dH, n, ldh, h->partial, kPartialDoubles, h->scal, h->stream));
+    CHECK(lanczos_on_device(h, dH, n, ldh, steps, margin, seed));
+    const int k = (int)std::min<int64_t>(steps, n);
+    const LanczosWork L = lanczos_layout(h->lz, n, k);
+    std::vector<double> ab(2 * (size_t)k);
+    int32_t st[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(ab.data(), L.alpha, sizeof(double) * 2 * (size_t)k, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(st, L.state, sizeof(st), hipMemcpyDeviceToHost, h->stream));
+    CHECK(read_scalars(h));
+    if (h->h_scal->nonfinite) return fail(CHEBDM_ERR_NONFINITE, "H holds NaN or Inf");
+    *emin = h->h_scal->emin;
+    *emax = h->h_scal->emax;
+    const int done = st[1];
+    if (alpha_out)
+        for (int i = 0; i < steps; ++i) alpha_out[i] = i < done ? ab[i] : 0.0;
+    if (beta_out)
+        for (int i = 0; i < steps; ++i) beta_out[i] = i < done ? ab[k + i] : 0.0;
+    if (steps_done) *steps_done = done;
     return CHEBDM_OK;
 }
 
@@ -682,7 +783,7 @@ int chebdm_density(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, do
     CHECK(check_opts(opts, pl));
     CHECK(plan_split(pl));
     CHECK(set_device(h));
-    CHECK(resolve_bounds(h, dH, n, ldh, emin, emax));
+    CHECK(resolve_bounds(h, dH, n, ldh, emin, emax, &pl));
     CHECK(ensure_small(h, 0));
     if (emax == emin) {
         // H = cI: D = f(c) I exactly (no spectrum map exists)
@@ -734,7 +835,7 @@ int chebdm_mu_search(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, 
     CHECK(check_opts(opts, pl));
     CHECK(plan_split(pl));
     CHECK(set_device(h));
-    CHECK(resolve_bounds(h, dH, n, ldh, emin, emax));
+    CHECK(resolve_bounds(h, dH, n, ldh, emin, emax, &pl));
     CHECK(ensure_small(h, 0));
     if (emax == emin) {
         // H = cI: tr f(c) I = n_elec fixes the occupation n_elec/n and mu in closed form
@@ -811,7 +912,7 @@ int chebdm_moments(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, in
     CHECK(check_opts(opts, pl));
     CHECK(plan_split(pl));
     CHECK(set_device(h));
-    CHECK(resolve_bounds(h, dH, n, ldh, emin, emax));
+    CHECK(resolve_bounds(h, dH, n, ldh, emin, emax, &pl));
     if (!(emax > emin)) return fail(CHEBDM_ERR_ARG, "moments need emin < emax");
     CHECK(ensure_small(h, 0));
     pl.ld = round_up(n, 128);

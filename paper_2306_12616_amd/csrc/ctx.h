@@ -47,7 +47,10 @@ struct chebdm_ctx {
         int products = 0;   // matrix products in the captured sequence
     };
     hipStream_t cap = nullptr;   // capture stream
-    Replay replay[3];            // mu search with D, mu search without D, density
+    Replay replay[4];            // mu search with D, mu search without D, density, Lanczos bounds
+    // Lanczos bounds workspace (basis, work vectors, partials, tridiagonal)
+    double* lz = nullptr;
+    int64_t lz_doubles = 0;
 };
 
 namespace chebdm {

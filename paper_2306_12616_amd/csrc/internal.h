@@ -70,6 +70,21 @@ hipError_t launch_fill_identity(double* D, int64_t n, int64_t ldd, double value,
 hipError_t launch_copy_out(const void* src, int is_f64, int64_t ld, int64_t n, double* D, int64_t ldd,
                            hipStream_t st);
 
+// ---- Lanczos bounds (k_lanczos.hip)
+constexpr int kMaxLanczosSteps = 128;
+struct LanczosWork {          // views into one device buffer of lanczos_work_doubles(n, steps) doubles
+    double *V, *w, *w2;        // basis v_0..v_{steps-1} (rows of n), work vectors
+    double *pa, *pc, *pn;      // per-block partials: alpha, projections, norm
+    double *alpha, *beta;      // tridiagonal T (steps each)
+    int32_t* state;            // [0]: steps done at a breakdown (0: none), [1]: steps done
+};
+int64_t lanczos_work_doubles(int64_t n, int steps);
+LanczosWork lanczos_layout(double* base, int64_t n, int steps);
+// Overwrites s->emin / s->emax (which must hold the Gershgorin bounds) with the Lanczos bounds.
+// steps in [1, min(n, kMaxLanczosSteps)].
+hipError_t launch_lanczos(const double* H, int64_t n, int64_t ldh, int steps, double margin, uint64_t seed,
+                          const LanczosWork& L, DevScalars* s, hipStream_t st);
+
 // ---- coefficients / decomposition / moments / bisection (k_cheb.hip)
 hipError_t launch_fermi_coeffs(int order, int M, const DevScalars* s, double* f_tab, double* c_out,
                                hipStream_t st, int damping = 0);

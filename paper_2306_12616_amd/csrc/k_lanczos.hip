@@ -1,0 +1,332 @@
+// Tight spectral bounds by a few Lanczos steps (an alternative to Gershgorin's
+// discs for the extreme eigenvalues e_a, e_b of Sec. II.B, which the paper
+// asks for without naming a method).
+//
+// Start vector: SplitMix64 (Steele, Lea, Flood 2014) doubles in [-1, 1),
+// normalised.  Step j (0-based), with one full reorthogonalisation pass:
+//     w = H v_j;  alpha_j = v_j . w;  w -= alpha_j v_j + beta_{j-1} v_{j-1};
+//     w -= sum_{i<=j} (v_i . w) v_i;   beta_j = ||w||;   v_{j+1} = w / beta_j.
+// The recurrence ends after `steps` steps or when beta_j falls to 1e-12 times
+// the Gershgorin scale max(|g_lo|, |g_hi|) (an invariant subspace).  The bounds
+// are [theta_min - r, theta_max + r] with theta the extreme eigenvalues of the
+// tridiagonal T_k and r = beta_{k-1}, widened by margin * width on each side
+// and intersected with the Gershgorin interval already in the scalars (the
+// Gershgorin interval alone if the intersection is empty).
+//
+// Kernels per step: the product H v_j (one wavefront per two rows, H read once
+// along rows), alpha (one work-group), the three-term update with the partial
+// projections v_i . w (a grid of slices x (j + 1)), and the reorthogonalisation
+// with the partial norm.  Every reduction is a fixed-order sum of per-block
+// partials, so the result does not depend on scheduling.  The tridiagonal
+// extremes come from Sturm-sequence multisection (Barth, Martin, Wilkinson 1967)
+// in one work-group.
+#include <cmath>
+
+#include "internal.h"
+#include "reduce.h"
+
+namespace chebdm {
+
+namespace {
+
+constexpr int kNT = 256;
+constexpr int kSlice = 1024;       // vector elements per work-group (4 per thread)
+constexpr int kRowsPerWave = 2;
+constexpr int kRowsPerBlock = (kNT / 64) * kRowsPerWave;
+constexpr double kBreakdown = 1e-12;
+
+__device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Fixed-order sum of count partials by one work-group (every thread gets it).
+__device__ inline double sum_partials(const double* __restrict__ p, int count, double* smem) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < count; b += kNT) acc += p[b];
+    return block_sum<kNT>(acc, smem);
+}
+
+__global__ void __launch_bounds__(kNT)
+k_lz_init(int64_t n, uint64_t seed, double* __restrict__ w, double* __restrict__ pn, int32_t* __restrict__ state) {
+    __shared__ double smem[kNT / 64];
+    const int64_t base = (int64_t)blockIdx.x * kSlice;
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < kSlice / kNT; ++q) {
+        const int64_t e = base + q * kNT + threadIdx.x;
+        if (e < n) {
+            const uint64_t z = splitmix64_at(seed, (uint64_t)e);
+            const double u = 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
+            w[e] = u;
+            acc += u * u;
+        }
+    }
+    acc = block_sum<kNT>(acc, smem);
+    if (threadIdx.x == 0) pn[blockIdx.x] = acc;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        state[0] = 0;   // steps done at a breakdown (0: none)
+        state[1] = 0;   // steps done in total
+    }
+}
+
+// beta = ||w|| from the partial norms; v_j = w / beta; w2 = (H w) / beta; partial v_j . w2.
+__global__ void __launch_bounds__(kNT)
+k_lz_matvec(const double* __restrict__ H, int64_t n, int64_t ldh, int j, double* __restrict__ V,
+            const double* __restrict__ w, double* __restrict__ w2, double* __restrict__ pa,
+            const double* __restrict__ pn, int nbv, double* __restrict__ beta, int32_t* __restrict__ state,
+            const DevScalars* __restrict__ s) {
+    __shared__ double smem[kNT / 64];
+    __shared__ double part[kNT / 64];
+    if (state[0]) return;
+    const double bt = sqrt(sum_partials(pn, nbv, smem));
+    if (j > 0) {
+        const double scale = fmax(fabs(s->emin), fabs(s->emax));
+        const bool broke = !(bt > kBreakdown * scale);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            beta[j - 1] = bt;
+            if (broke) state[0] = j;
+        }
+        if (broke) return;
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlock + wave * kRowsPerWave;
+    double y[kRowsPerWave];
+#pragma unroll
+    for (int t = 0; t < kRowsPerWave; ++t) y[t] = 0.0;
+    if (r0 < n) {
+        const double* h0 = H + r0 * ldh;
+        const double* h1 = H + (r0 + 1 < n ? r0 + 1 : r0) * ldh;
+#pragma unroll 4
+        for (int64_t c = lane; c < n; c += 64) {
+            const double x = w[c];
+            y[0] = fma(h0[c], x, y[0]);
+            y[1] = fma(h1[c], x, y[1]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kRowsPerWave; ++t) y[t] = wave_sum(y[t]);
+    double contrib = 0.0;
+    if (lane == 0) {
+#pragma unroll
+        for (int t = 0; t < kRowsPerWave; ++t) {
+            const int64_t r = r0 + t;
+            if (r < n) {
+                const double v = w[r] / bt;
+                const double z = y[t] / bt;
+                V[(int64_t)j * n + r] = v;
+                w2[r] = z;
+                contrib += v * z;
+            }
+        }
+        part[wave] = contrib;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < kNT / 64; ++q) acc += part[q];
+        pa[blockIdx.x] = acc;
+    }
+}
+
+__global__ void __launch_bounds__(kNT)
+k_lz_alpha(int j, const double* __restrict__ pa, int nbr, double* __restrict__ alpha,
+           const int32_t* __restrict__ state) {
+    __shared__ double smem[kNT / 64];
+    if (state[0]) return;
+    const double a = sum_partials(pa, nbr, smem);
+    if (threadIdx.x == 0) alpha[j] = a;
+}
+
+// x = w2 - alpha_j v_j - beta_{j-1} v_{j-1} on a slice (stored by the blockIdx.y == 0 row
+// of blocks); partial v_i . x for i = blockIdx.y.
+__global__ void __launch_bounds__(kNT)
+k_lz_proj(int64_t n, int j, const double* __restrict__ V, const double* __restrict__ w2,
+          const double* __restrict__ alpha, const double* __restrict__ beta, double* __restrict__ w,
+          double* __restrict__ pc, int nbv, const int32_t* __restrict__ state) {
+    __shared__ double smem[kNT / 64];
+    if (state[0]) return;
+    const int i = blockIdx.y;
+    const double a = alpha[j], bm = j > 0 ? beta[j - 1] : 0.0;
+    const double* vj = V + (int64_t)j * n;
+    const double* vm = V + (int64_t)(j > 0 ? j - 1 : 0) * n;
+    const double* vi = V + (int64_t)i * n;
+    const int64_t base = (int64_t)blockIdx.x * kSlice;
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < kSlice / kNT; ++q) {
+        const int64_t e = base + q * kNT + threadIdx.x;
+        if (e < n) {
+            double x = w2[e] - a * vj[e];
+            if (j > 0) x -= bm * vm[e];
+            if (i == 0) w[e] = x;
+            acc += vi[e] * x;
+        }
+    }
+    acc = block_sum<kNT>(acc, smem);
+    if (threadIdx.x == 0) pc[(int64_t)i * nbv + blockIdx.x] = acc;
+}
+
+// c_i = sum of the partials; w -= sum_{i<=j} c_i v_i on a slice; partial ||w||^2.
+__global__ void __launch_bounds__(kNT)
+k_lz_reorth(int64_t n, int j, const double* __restrict__ V, double* __restrict__ w,
+            const double* __restrict__ pc, int nbv, double* __restrict__ pn, const int32_t* __restrict__ state) {
+    __shared__ double smem[kNT / 64];
+    __shared__ double c[kMaxLanczosSteps];
+    if (state[0]) return;
+    for (int i = threadIdx.x; i <= j; i += kNT) {
+        double acc = 0.0;
+        for (int b = 0; b < nbv; ++b) acc += pc[(int64_t)i * nbv + b];
+        c[i] = acc;
+    }
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSlice;
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < kSlice / kNT; ++q) {
+        const int64_t e = base + q * kNT + threadIdx.x;
+        if (e < n) {
+            double x = w[e];
+            for (int i = 0; i <= j; ++i) x -= c[i] * V[(int64_t)i * n + e];
+            w[e] = x;
+            acc += x * x;
+        }
+    }
+    acc = block_sum<kNT>(acc, smem);
+    if (threadIdx.x == 0) pn[blockIdx.x] = acc;
+}
+
+// Number of eigenvalues of the tridiagonal (a, b) below x (Sturm sequence of the LDL^T pivots).
+__device__ inline int sturm_count(const double* a, const double* b, int k, double x) {
+    constexpr double pivmin = 1e-300;
+    int cnt = 0;
+    double q = a[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+    for (int i = 1; i < k; ++i) {
+        q = (a[i] - x) - b[i - 1] * b[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += q < 0.0;
+    }
+    return cnt;
+}
+
+constexpr int kFinalNT = 128;   // wave 0: theta_min, wave 1: theta_max
+constexpr int kRounds = 12;     // 65-way multisection: 65^12 > 2^72
+
+__global__ void __launch_bounds__(kFinalNT)
+k_lz_final(int steps, const double* __restrict__ alpha, double* __restrict__ beta, const double* __restrict__ pn,
+           int nbv, int32_t* __restrict__ state, double margin, DevScalars* __restrict__ s) {
+    __shared__ double a[kMaxLanczosSteps], b[kMaxLanczosSteps];
+    __shared__ double theta[2];
+    __shared__ double smem[kFinalNT / 64];
+    __shared__ double r_last;
+    const int done = state[0];
+    const int k = done ? done : steps;
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < nbv; q += kFinalNT) acc += pn[q];
+    acc = block_sum<kFinalNT>(acc, smem);
+    if (threadIdx.x == 0) {
+        r_last = done ? beta[k - 1] : sqrt(acc);
+        if (!done) beta[k - 1] = r_last;
+        state[1] = k;
+    }
+    for (int i = threadIdx.x; i < k; i += kFinalNT) {
+        a[i] = alpha[i];
+        b[i] = i + 1 < k ? beta[i] : 0.0;
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // Gershgorin interval of T
+    double lo = INFINITY, hi = -INFINITY;
+    for (int i = 0; i < k; ++i) {
+        const double rad = fabs(b[i]) + (i > 0 ? fabs(b[i - 1]) : 0.0);
+        lo = fmin(lo, a[i] - rad);
+        hi = fmax(hi, a[i] + rad);
+    }
+    // wave 0: smallest x with count(x) >= 1 (theta_min in [lo, hi]); wave 1: count(x) >= k
+    const int need = wave == 0 ? 1 : k;
+    for (int round = 0; round < kRounds; ++round) {
+        const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+        const bool ge = sturm_count(a, b, k, x) >= need;
+        const uint64_t mask = __ballot(ge);
+        const int first = mask ? __ffsll((unsigned long long)mask) - 1 : 64;
+        const double xl = first == 0 ? lo : lo + (hi - lo) * (double)first / 65.0;
+        const double xh = first == 64 ? hi : lo + (hi - lo) * (double)(first + 1) / 65.0;
+        lo = xl;
+        hi = xh;
+    }
+    if (lane == 0) theta[wave] = wave == 0 ? lo : hi;   // outer side of the final interval
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double g_lo = s->emin, g_hi = s->emax;
+        double e_lo = theta[0] - r_last, e_hi = theta[1] + r_last;
+        const double pad = margin * (e_hi - e_lo);
+        e_lo = fmax(e_lo - pad, g_lo);
+        e_hi = fmin(e_hi + pad, g_hi);
+        if (!(e_lo <= e_hi)) {
+            e_lo = g_lo;
+            e_hi = g_hi;
+        }
+        s->emin = e_lo;
+        s->emax = e_hi;
+    }
+}
+
+}  // namespace
+
+int64_t lanczos_work_doubles(int64_t n, int steps) {
+    const int64_t nbv = (n + kSlice - 1) / kSlice, nbr = (n + kRowsPerBlock - 1) / kRowsPerBlock;
+    return (int64_t)steps * n + 2 * n + nbr + (int64_t)steps * nbv + nbv + 2 * (int64_t)steps + 2;
+}
+
+LanczosWork lanczos_layout(double* base, int64_t n, int steps) {
+    const int64_t nbv = (n + kSlice - 1) / kSlice, nbr = (n + kRowsPerBlock - 1) / kRowsPerBlock;
+    LanczosWork L;
+    double* p = base;
+    L.V = p;
+    p += (int64_t)steps * n;
+    L.w = p;
+    p += n;
+    L.w2 = p;
+    p += n;
+    L.pa = p;
+    p += nbr;
+    L.pc = p;
+    p += (int64_t)steps * nbv;
+    L.pn = p;
+    p += nbv;
+    L.alpha = p;
+    p += steps;
+    L.beta = p;
+    p += steps;
+    L.state = reinterpret_cast<int32_t*>(p);   // two int32 in one double
+    return L;
+}
+
+hipError_t launch_lanczos(const double* H, int64_t n, int64_t ldh, int steps, double margin, uint64_t seed,
+                          const LanczosWork& L, DevScalars* s, hipStream_t st) {
+    if (steps < 1 || steps > kMaxLanczosSteps || steps > n) return hipErrorInvalidValue;
+    const int nbv = (int)((n + kSlice - 1) / kSlice);
+    const int nbr = (int)((n + kRowsPerBlock - 1) / kRowsPerBlock);
+    hipLaunchKernelGGL(k_lz_init, dim3(nbv), dim3(kNT), 0, st, n, seed, L.w, L.pn, L.state);
+    for (int j = 0; j < steps; ++j) {
+        hipLaunchKernelGGL(k_lz_matvec, dim3(nbr), dim3(kNT), 0, st, H, n, ldh, j, L.V, (const double*)L.w, L.w2,
+                           L.pa, (const double*)L.pn, nbv, L.beta, L.state, (const DevScalars*)s);
+        hipLaunchKernelGGL(k_lz_alpha, dim3(1), dim3(kNT), 0, st, j, (const double*)L.pa, nbr, L.alpha,
+                           (const int32_t*)L.state);
+        hipLaunchKernelGGL(k_lz_proj, dim3(nbv, j + 1), dim3(kNT), 0, st, n, j, (const double*)L.V,
+                           (const double*)L.w2, (const double*)L.alpha, (const double*)L.beta, L.w, L.pc, nbv,
+                           (const int32_t*)L.state);
+        hipLaunchKernelGGL(k_lz_reorth, dim3(nbv), dim3(kNT), 0, st, n, j, (const double*)L.V, L.w,
+                           (const double*)L.pc, nbv, L.pn, (const int32_t*)L.state);
+    }
+    hipLaunchKernelGGL(k_lz_final, dim3(1), dim3(kFinalNT), 0, st, steps, (const double*)L.alpha, L.beta,
+                       (const double*)L.pn, nbv, L.state, margin, s);
+    return hipGetLastError();
+}
+
+}  // namespace chebdm

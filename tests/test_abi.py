@@ -38,13 +38,28 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version_and_defaults(lib):
-    assert lib.chebdm_abi_version() == 3
+    assert lib.chebdm_abi_version() == 4
     o = chebdm.make_opts()
     assert (o.prec, o.giant_form, o.k_override, o.n_quad, o.max_iter, o.baby_steps, o.search, o.damping, o.tol) == \
         (0, 0, 0, 0, 200, 0, 0, 0, 1e-10)
     assert chebdm.make_opts(damping="jackson").damping == 1
-    assert ctypes.sizeof(chebdm.Opts) == 40   # eight int32 then one double
+    assert ctypes.sizeof(chebdm.Opts) == 56   # eight int32, a double, two int32, a double
     assert chebdm.make_opts(search="newton").search == 1
+    assert (o.bounds, o.lanczos_steps, o.bounds_margin) == (0, 0, 0.0)
+    lz = chebdm.make_opts(bounds="lanczos", lanczos_steps=24, bounds_margin=0.05)
+    assert (lz.bounds, lz.lanczos_steps, lz.bounds_margin) == (1, 24, 0.05)
+
+
+def test_bounds_options_are_checked_on_the_host(lib):
+    # chebdm_workspace_size validates the options without touching a device
+    size = ctypes.c_size_t()
+    for kw in ({"bounds": 2}, {"bounds": -1}, {"bounds": "lanczos", "lanczos_steps": 129},
+               {"bounds": "lanczos", "lanczos_steps": -1}, {"bounds": "lanczos", "bounds_margin": -0.1},
+               {"bounds": "lanczos", "bounds_margin": math.inf}):
+        o = chebdm.make_opts(**kw)
+        assert lib.chebdm_workspace_size(None, 100, 64, ctypes.byref(o), ctypes.byref(size)) == _binding.ERR_ARG, kw
+    o = chebdm.make_opts(bounds="lanczos", lanczos_steps=128, bounds_margin=0.5)
+    assert lib.chebdm_workspace_size(None, 100, 64, ctypes.byref(o), ctypes.byref(size)) == 0
 
 
 def _dbl():
@@ -61,6 +76,8 @@ def test_null_handle_is_rejected(lib):
     assert lib.chebdm_mu_search(None, None, 4, 4, 1.0, 2.0, 4, None, math.nan, math.nan, ctypes.byref(mu), None, 4,
                                 None) == _binding.ERR_ARG
     assert lib.chebdm_moments(None, None, 4, 4, 4, None, math.nan, math.nan, c) == _binding.ERR_ARG
+    assert lib.chebdm_bounds_lanczos(None, None, 4, 4, 8, 0.01, 0, ctypes.byref(lo), ctypes.byref(hi), None, None,
+                                     None) == _binding.ERR_ARG
     assert b"NULL" in lib.chebdm_last_error() or b"handle" in lib.chebdm_last_error()
     assert lib.chebdm_destroy(None) == 0
     assert lib.chebdm_set_stream(None, None) == _binding.ERR_ARG
