@@ -190,6 +190,36 @@ def lanczos_rows(cd, handle, hs, beta, order, reps=10):
     return out
 
 
+def accuracy_rows(cd, handle, n=1000, beta=400.0, mu=0.0, orders=(64, 128, 256, 512, 1024, 2048)):
+    """Distance of the float64 expansion D_L to the exact Fermi operator f(H) = Q f(Lambda) Q^T
+    against the order L, on the high-density-of-states spectrum (40 % of the levels in a
+    Gaussian of width 0.01 at the Fermi level), for three choices of [e_a, e_b]: the spectrum's
+    own extremes (passed by the caller), 40 Lanczos steps and Gershgorin's discs.  f(H) comes
+    from the generator's eigenpairs (host float64), not from the library."""
+    import numpy as np
+    import torch
+    import synth
+
+    h, q, lam = synth.hamiltonian(n, "highdos", seed=4000)
+    with np.errstate(over="ignore"):
+        occ = 1.0 / (1.0 + np.exp(beta * (lam - mu)))
+    exact = (q * occ) @ q.T
+    H = torch.from_numpy(h).to("cuda:0")
+    D = torch.empty_like(H)
+    lz = cd.chebdm_bounds_lanczos(handle, H, 40, 0.01, 0)[:2]
+    bounds = {"spectrum": (float(lam.min()), float(lam.max())), "lanczos": lz, "gershgorin": cd.chebdm_bounds(handle, H)}
+    out = {"workload": f"N={n} high-DOS spectrum (seed 4000), beta {beta:g}, mu {mu:g}, float64, max|D_L - f(H)|",
+           "beta_scaled": {k: round(beta * (b[1] - b[0]) / 2, 1) for k, b in bounds.items()}, "orders": list(orders)}
+    for name, (lo, hi) in bounds.items():
+        errs = []
+        for L in orders:
+            cd.chebdm_density(handle, H, beta, mu, L, cd.make_opts("fp64"), lo, hi, D=D)
+            errs.append(float(np.max(np.abs(D.cpu().numpy() - exact))))
+        out[name] = [float(f"{e:.3e}") for e in errs]
+        log(f"accuracy: {name} {out[name]}")
+    return out
+
+
 def batch_row(cd, handle, torch, prec="fp32", order=256, reps=3):
     """Batched form: 512 Hamiltonians, n uniform on {96..1024}, beta on [30, 200], one graph per batch."""
     import numpy as np
@@ -406,6 +436,7 @@ def main():
                                     "gemm_frac_of_peak": r3["frac"] if r3 else None}
         result["fixed_mu"] = fixed
         result["lanczos_bounds"] = lanczos_rows(cd, handle, hs, beta, order)
+        result["accuracy_vs_order"] = accuracy_rows(cd, handle)
         del hs
         for key, row in rows.items():
             nn = key.split("_")[0]

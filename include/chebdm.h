@@ -204,6 +204,21 @@ int chebdm_bounds_lanczos(chebdm_handle h, const double* dH, int64_t n, int64_t 
                           double* alpha_out, double* beta_out, int32_t* steps_done);
 
 /*
+ * Commutator check of a density matrix: *out = max_ij |(H D - D H)_ij|.
+ * A function of H commutes with it (D is built from H's eigenvectors in
+ * Sec. II.A), so this measures how far D is from any function of H; for a
+ * float64 expansion it sits at rounding level (about 1e-13 |H|).  H and D
+ * must be symmetric (not checked).  Float64 MFMA products on the device
+ * (2 n^3 flops); H and D are copied into two matrices of the handle's
+ * workspace (which the next density or mu-search call overwrites).
+ * dH, dD: n x n device matrices, leading dimensions ldh, ldd >= n.
+ * *out: host double (NaN if H or D holds NaN).
+ * Errors: CHEBDM_ERR_ARG, CHEBDM_ERR_OOM, CHEBDM_ERR_HIP.
+ */
+int chebdm_commutator_norm(chebdm_handle h, const double* dH, int64_t ldh, const double* dD, int64_t ldd,
+                           int64_t n, double* out);
+
+/*
  * Chebyshev coefficients c_0..c_L of the Fermi function on [emin, emax]
  * (the expansion sum c_n T_n of Sec. II.B; projection is a reading):
  *     c_n = (2 - delta_{n0})/M * sum_{j<M} f(x_j) cos(n theta_j),

@@ -245,6 +245,11 @@ def density_recursion(h: np.ndarray, c, emin: float, emax: float):
     return d
 
 
+def commutator_max(h: np.ndarray, d: np.ndarray) -> float:
+    """max_ij |(H D - D H)_ij| by two plain products (zero for any function of H, Sec. II.A)."""
+    return float(np.max(np.abs(h @ d - d @ h)))
+
+
 def fermi_dirac_density(q, lam, beta: float, mu: float):
     """Exact Fermi operator Q f(Lambda) Q^T (eqs. D from diag, fermifunc) - truncation reference."""
     with np.errstate(over="ignore"):

@@ -77,6 +77,8 @@ _SIGNATURES = {
                                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                              ctypes.POINTER(ctypes.c_int32)]),
+    "chebdm_commutator_norm": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                              ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
     "chebdm_coeffs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_double)]),
@@ -250,6 +252,17 @@ def chebdm_bounds_lanczos(h: Handle, H, steps: int = 40, margin: float = 0.01, s
                                                 b.ctypes.data_as(dp), ctypes.byref(done)))
     k = done.value
     return lo.value, hi.value, a[:k], b[:k]
+
+
+def chebdm_commutator_norm(h: Handle, H, D) -> float:
+    """max |H D - D H| of two symmetric device matrices (float64)."""
+    p, n, ld = _matrix_args(H, "H")
+    pd, nd, ldd = _matrix_args(D, "D")
+    if nd != n:
+        raise ValueError("D must match H's size")
+    out = ctypes.c_double()
+    _check(load_library().chebdm_commutator_norm(h.ptr, p, ld, pd, ldd, n, ctypes.byref(out)))
+    return out.value
 
 
 def chebdm_coeffs(h: Handle, beta: float, mu: float, emin: float, emax: float, order: int, n_quad: int = 0):

@@ -722,6 +722,25 @@ int chebdm_bounds_lanczos(chebdm_handle h, const double* dH, int64_t n, int64_t 
     return CHEBDM_OK;
 }
 
+int chebdm_commutator_norm(chebdm_handle h, const double* dH, int64_t ldh, const double* dD, int64_t ldd,
+                           int64_t n, double* out) {
+    if (!h || !out) return fail(CHEBDM_ERR_ARG, "NULL argument");
+    CHECK(validate_matrix(dH, n, ldh));
+    if (!dD || ldd < n) return fail(CHEBDM_ERR_ARG, "D is NULL or ldd < n");
+    CHECK(set_device(h));
+    CHECK(ensure_small(h, 0));
+    Plan pl;
+    pl.n = n;
+    pl.ld = round_up(n, 128);
+    pl.elem = 8;
+    CHECK(ensure_mats(h, pl, 2));
+    double* w = static_cast<double*>(h->mats);
+    HIP_TRY(launch_commutator(dH, ldh, dD, ldd, n, pl.ld, w, w + pl.ld * pl.ld, h->partial, h->stream));
+    HIP_TRY(hipMemcpyAsync(out, h->partial, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return CHEBDM_OK;
+}
+
 int chebdm_coeffs(chebdm_handle h, double beta, double mu, double emin, double emax, int32_t order,
                   int32_t n_quad, double* c_out) {
     if (!h || !c_out) return fail(CHEBDM_ERR_ARG, "NULL argument");

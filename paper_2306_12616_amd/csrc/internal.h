@@ -70,6 +70,11 @@ hipError_t launch_fill_identity(double* D, int64_t n, int64_t ldd, double value,
 hipError_t launch_copy_out(const void* src, int is_f64, int64_t ld, int64_t n, double* D, int64_t ldd,
                            hipStream_t st);
 
+// ---- commutator check (k_check.hip): *out = max |H D - D H| (float64 bits written as a double);
+// Hw, Dw: ld x ld workspace matrices with zero padding (ld a multiple of 64)
+hipError_t launch_commutator(const double* H, int64_t ldh, const double* D, int64_t ldd, int64_t n, int64_t ld,
+                             double* Hw, double* Dw, double* out, hipStream_t st);
+
 // ---- Lanczos bounds (k_lanczos.hip)
 constexpr int kMaxLanczosSteps = 128;
 struct LanczosWork {          // views into one device buffer of lanczos_work_doubles(n, steps) doubles

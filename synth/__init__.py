@@ -174,3 +174,49 @@ def mu_problems(sizes, seed: int, device="cuda"):
 def mu_training_sizes(count: int, seed: int = 100):
     """Training sizes of the learned-mu workload: n ~ U{64, 80, ..., 512}."""
     return 64 + 16 * np.random.default_rng(seed).integers(0, 29, size=count)
+
+
+# ---------------------------------------------------------------------------
+# two-level tight-binding model Hamiltonians (Sec. III.C, the paper's workload family)
+
+TB_KINDS = {
+    # alpha (A-A), beta (B-B), gamma (A-B), eps_a, eps_b, decay k, noise amplitude r
+    "metal": dict(alpha=-1.0, beta=-1.0, gamma=0.0, eps_a=0.0, eps_b=0.0, k=-1.0, r=0.0),
+    "semiconductor": dict(alpha=0.0, beta=-1.0, gamma=-2.0, eps_a=0.0, eps_b=0.0, k=-0.01, r=0.0),
+    "softmatter": dict(alpha=0.0, beta=-1.0, gamma=-1.0, eps_a=-10.0, eps_b=0.0, k=-0.1, r=1.0),
+    # the accuracy study's metallic case (Sec. III.D): wide spectrum, DOS piled at the Fermi level
+    "metal_accuracy": dict(alpha=-1.0, beta=1.0, gamma=0.0, eps_a=1.0, eps_b=-1.0, k=-1.0, r=0.0),
+}
+
+
+def tight_binding(n: int, kind: str = "metal", seed: int = 0, **override) -> np.ndarray:
+    """Two-level tight-binding model, n orbitals (float64, exactly symmetric).
+
+    Orbital i is the A orbital of site i // 2 for even i and its B orbital for
+    odd i (the layout is a reading; the paper does not give it).  Off-diagonal
+    H_ij = c(type_i, type_j) exp(-|k| |s_i - s_j|) with c = alpha (A-A), beta
+    (B-B), gamma (A-B) and s the site index (so gamma couples the two orbitals
+    of one site at full strength, as in the paper's two-level schematic; the
+    paper's negative k is read as the decay rate |k|); H_ii = eps_a or eps_b.  With r > 0
+    every onsite energy and every coupling pair is multiplied by (1 + r eta),
+    eta ~ U[-1, 1] drawn once per upper-triangle entry (PCG64, ``seed``).
+    Parameters: ``TB_KINDS[kind]``, then the keyword overrides.
+    """
+    p = dict(TB_KINDS[kind])
+    p.update(override)
+    idx = np.arange(n)
+    is_b = (idx % 2).astype(bool)
+    ta, tb = ~is_b[:, None], is_b[:, None]
+    sa, sb = ~is_b[None, :], is_b[None, :]
+    coup = np.where(ta & sa, p["alpha"], 0.0) + np.where(tb & sb, p["beta"], 0.0) \
+        + np.where((ta & sb) | (tb & sa), p["gamma"], 0.0)
+    site = idx // 2
+    dist = np.abs(site[:, None] - site[None, :]).astype(np.float64)
+    h = coup * np.exp(-abs(p["k"]) * dist)
+    np.fill_diagonal(h, np.where(is_b, p["eps_b"], p["eps_a"]))
+    if p["r"] > 0.0:
+        rng = np.random.default_rng(seed)
+        eta = rng.uniform(-1.0, 1.0, size=(n, n))
+        eta = np.triu(eta) + np.triu(eta, 1).T
+        h = h * (1.0 + p["r"] * eta)
+    return h

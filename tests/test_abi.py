@@ -78,6 +78,7 @@ def test_null_handle_is_rejected(lib):
     assert lib.chebdm_moments(None, None, 4, 4, 4, None, math.nan, math.nan, c) == _binding.ERR_ARG
     assert lib.chebdm_bounds_lanczos(None, None, 4, 4, 8, 0.01, 0, ctypes.byref(lo), ctypes.byref(hi), None, None,
                                      None) == _binding.ERR_ARG
+    assert lib.chebdm_commutator_norm(None, None, 4, None, 4, 4, ctypes.byref(lo)) == _binding.ERR_ARG
     assert b"NULL" in lib.chebdm_last_error() or b"handle" in lib.chebdm_last_error()
     assert lib.chebdm_destroy(None) == 0
     assert lib.chebdm_set_stream(None, None) == _binding.ERR_ARG

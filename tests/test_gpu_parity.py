@@ -415,3 +415,65 @@ def test_jackson_damping_matches_oracle(cd, handle, prec, tol):
     # the damped occupations stay in [0, 1]: D's eigenvalues p_J(lam~) are in [0, 1]
     p = ch.cheb_eval(c, (lam - cen) / a)
     assert p.min() > -1e-12 and p.max() < 1 + 1e-12
+
+
+# ------------------------------------------------------------------ commutator check
+
+@pytest.mark.parametrize("n", [1, 70, 300, 1000])
+def test_commutator_norm_matches_oracle(cd, handle, n):
+    _say(f"commutator n={n}")
+    rng = np.random.default_rng(n)
+    h, _, _ = synth.hamiltonian(n, "uniform", seed=40 + n)
+    d = rng.normal(size=(n, n))
+    d = (d + d.T) / 2
+    got = cd.chebdm_commutator_norm(handle, _dev(h), _dev(d))
+    ref = ch.commutator_max(h, d)
+    scale = n * np.max(np.abs(h)) * np.max(np.abs(d))
+    _say(f"  max|HD-DH| gpu {got:.15e} oracle {ref:.15e}")
+    assert abs(got - ref) <= 1e-14 * scale
+
+
+def test_commutator_of_expansion_is_rounding_level(cd, handle):
+    n, ld = 500, 640
+    h, q, lam = synth.hamiltonian(n, "gaussmix6", seed=9)
+    big = torch.zeros((n, ld), dtype=torch.float64, device="cuda:0")
+    big[:, :n] = _dev(h)
+    H = big[:, :n]
+    mu, D, info = cd.chebdm_mu_search(handle, H, 60.0, n / 2, 256)
+    got = cd.chebdm_commutator_norm(handle, H, D)
+    ref = ch.commutator_max(h, D.cpu().numpy())
+    _say(f"  ||[H, D_L]||_max gpu {got:.3e} oracle {ref:.3e}")
+    assert got < 1e-11 and abs(got - ref) <= 1e-12
+    # a matrix that is not a function of H is flagged
+    E = D.clone()
+    E[0, 1] += 1e-3
+    E[1, 0] += 1e-3
+    assert cd.chebdm_commutator_norm(handle, H, E) > 1e-5
+    bad = D.clone()
+    bad[2, 3] = float("nan")
+    assert math.isnan(cd.chebdm_commutator_norm(handle, H, bad))
+
+
+# ------------------------------------------------------------------ tight-binding model inputs
+
+@pytest.mark.parametrize("bounds", ["gershgorin", "lanczos"])
+@pytest.mark.parametrize("kind", ["metal", "semiconductor", "softmatter", "metal_accuracy"])
+def test_mu_search_tight_binding(cd, handle, kind, bounds):
+    # the paper's model-Hamiltonian family (Sec. III.C); the oracle diagonalises H itself
+    n, order, beta = 601, 256, 20.0
+    ne = n / 2
+    _say(f"tight-binding {kind} bounds={bounds}")
+    h = synth.tight_binding(n, kind, seed=11)
+    lam, q = np.linalg.eigh(h)
+    mu, D, info = cd.chebdm_mu_search(handle, _dev(h), beta, ne, order, cd.make_opts(bounds=bounds))
+    assert info["status"] == 0, info
+    emin, emax = info["emin"], info["emax"]
+    assert emin <= lam.min() and lam.max() <= emax
+    cen, a = ch.scaling(emin, emax)
+    c = ch.chebyshev_coeffs(order, beta * a, (mu - cen) / a, info["n_quad"])
+    err = float(np.max(np.abs(D.cpu().numpy() - ch.density_from_eigs(q, lam, c, emin, emax))))
+    t_or = ch.trace_of_series(c, ch.moments_from_eigs(lam, emin, emax, order))
+    _say(f"  [{emin:.3f}, {emax:.3f}] beta'={beta * a:.0f} mu={mu:.10f} |t_oracle-Ne|={abs(t_or - ne):.1e} "
+         f"max|D-D_oracle|={err:.1e}")
+    assert err <= 1e-10
+    assert abs(t_or - ne) <= 1e-9

@@ -106,6 +106,17 @@ def test_density_symmetric_and_commutes():
     d = ch.density_eigh(h, c, emin, emax)
     assert np.max(np.abs(d - d.T)) < 1e-13
     assert np.max(np.abs(h @ d - d @ h)) < 1e-12
+    assert ch.commutator_max(h, d) < 1e-12
+
+
+def test_commutator_closed_form_for_diagonal_h():
+    # (diag(a) D - D diag(a))_ij = (a_i - a_j) D_ij
+    rng = np.random.default_rng(3)
+    a = rng.normal(size=9)
+    d = rng.normal(size=(9, 9))
+    d = d + d.T
+    assert abs(ch.commutator_max(np.diag(a), d) - np.max(np.abs((a[:, None] - a[None, :]) * d))) < 1e-15
+    assert ch.commutator_max(np.diag(a), np.diag(rng.normal(size=9))) == 0.0
 
 
 def test_density_diagonal_hamiltonian():
