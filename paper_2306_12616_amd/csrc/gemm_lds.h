@@ -35,14 +35,17 @@ struct SplitTerms<P_BF16X6> {
 // those of step s+2 (two register stages, the loop body unrolled by two).
 // LDS rows are KC + PAD bf16 long; SWZ > 0 XORs the 16-byte chunk index of row r with
 // (r >> SWZ) & 3 (a bank swizzle; use with PAD = 0).
-template <int P, int DEPTH = 2, int PAD = 8, int SWZ = 0>
+// LDB = 2 keeps two LDS stages: step s + 1 is written into one while step s is read from the
+// other, so one barrier per K step suffices (LDB = 1: two, around the single stage).
+template <int P, int DEPTH = 2, int PAD = 8, int SWZ = 0, int LDB = 1, int IGLP = -1, int TO = 0>
 __device__ __forceinline__ void gemm_tile_lds(const GemmDesc<float>& g, int64_t n, int64_t ld, int64_t kpad, int ti,
                                               int tj) {
     static_assert(P == P_BF16X3 || P == P_BF16X6, "split-bf16 precisions only");
     static_assert(DEPTH == 1 || DEPTH == 2, "prefetch depth 1 or 2");
+    static_assert(LDB == 1 || (LDB == 2 && DEPTH == 2), "two LDS stages need two register stages");
     using Acc = f32x4;
     constexpr int BM = 128, KC = 32, NT = SplitTerms<P>::N, RS = KC + PAD;
-    __shared__ __attribute__((aligned(16))) __bf16 lds[2][NT][BM][RS];
+    __shared__ __attribute__((aligned(16))) __bf16 lds[LDB][2][NT][BM][RS];
     // column (in bf16) of 16-byte chunk c of row r
     auto col = [](int r, int c) -> int { return SWZ > 0 ? 8 * (c ^ ((r >> SWZ) & 3)) : 8 * c; };
 
@@ -68,7 +71,7 @@ __device__ __forceinline__ void gemm_tile_lds(const GemmDesc<float>& g, int64_t 
             r.b[c] = *reinterpret_cast<const f32x4*>(gb + k0 + 4 * c);
         }
     };
-    auto put1 = [&](int which, const f32x4 (&r)[4]) {
+    auto put1 = [&](int buf, int which, const f32x4 (&r)[4]) {
         float x[16];
 #pragma unroll
         for (int c = 0; c < 4; ++c)
@@ -80,14 +83,14 @@ __device__ __forceinline__ void gemm_tile_lds(const GemmDesc<float>& g, int64_t 
             if constexpr (NT == 2) split_bf16(&x[8 * h], t0, t1);
             else split3_bf16(&x[8 * h], t0, t1, t2);
             const int cc = col(srow, sk / 8 + h);
-            *reinterpret_cast<bf16x8*>(&lds[which][0][srow][cc]) = t0;
-            *reinterpret_cast<bf16x8*>(&lds[which][1][srow][cc]) = t1;
-            if constexpr (NT == 3) *reinterpret_cast<bf16x8*>(&lds[which][2][srow][cc]) = t2;
+            *reinterpret_cast<bf16x8*>(&lds[buf][which][0][srow][cc]) = t0;
+            *reinterpret_cast<bf16x8*>(&lds[buf][which][1][srow][cc]) = t1;
+            if constexpr (NT == 3) *reinterpret_cast<bf16x8*>(&lds[buf][which][2][srow][cc]) = t2;
         }
     };
-    auto put = [&](const Stage& r) {
-        put1(0, r.a);
-        put1(1, r.b);
+    auto put = [&](const Stage& r, int buf = 0) {
+        put1(buf, 0, r.a);
+        put1(buf, 1, r.b);
     };
 
     Acc acc[4][4];
@@ -96,17 +99,33 @@ __device__ __forceinline__ void gemm_tile_lds(const GemmDesc<float>& g, int64_t 
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[f][q] = Acc{};
 
-    auto compute = [&]() {
+    auto compute = [&](int buf = 0) {
         if (idle) return;
+        if constexpr (IGLP >= 0) __builtin_amdgcn_iglp_opt(IGLP);
         bf16x8 a[NT][4], b[NT][4];
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int f = 0; f < 4; ++f) {
                 const int ra = wm * 64 + f * 16 + lr, rb = wn * 64 + f * 16 + lr;
-                a[t][f] = *reinterpret_cast<const bf16x8*>(&lds[0][t][ra][col(ra, lq)]);
-                b[t][f] = *reinterpret_cast<const bf16x8*>(&lds[1][t][rb][col(rb, lq)]);
+                a[t][f] = *reinterpret_cast<const bf16x8*>(&lds[buf][0][t][ra][col(ra, lq)]);
+                b[t][f] = *reinterpret_cast<const bf16x8*>(&lds[buf][1][t][rb][col(rb, lq)]);
             }
+        if constexpr (TO) {
+            // term-major order: consecutive MFMAs write different accumulators (no dependent
+            // back-to-back issue); every accumulator still takes its terms in the same order
+            constexpr int NTERM = NT == 2 ? 3 : 6;
+            constexpr int ta[6] = {NT == 2 ? 1 : 2, 0, NT == 2 ? 0 : 1, 1, 0, 0};
+            constexpr int tb[6] = {0, NT == 2 ? 1 : 2, NT == 2 ? 0 : 1, 0, 1, 0};
+#pragma unroll
+            for (int u = 0; u < NTERM; ++u)
+#pragma unroll
+                for (int f = 0; f < 4; ++f)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ta[u]][f], b[tb[u]][q], acc[f][q], 0, 0, 0);
+            return;
+        }
 #pragma unroll
         for (int f = 0; f < 4; ++f)
 #pragma unroll
@@ -136,6 +155,24 @@ __device__ __forceinline__ void gemm_tile_lds(const GemmDesc<float>& g, int64_t 
             compute();
             __syncthreads();
             put(r);
+            __syncthreads();
+        }
+    } else if constexpr (LDB == 2) {
+        // steps is even; stage 0 holds even steps, stage 1 odd ones
+        Stage r0, r1;
+        gload(r0, 0);
+        gload(r1, 1);
+        put(r0, 0);
+        gload(r0, 2);
+        __syncthreads();
+        for (int64_t s = 0; s < steps; s += 2) {
+            compute(0);         // step s
+            put(r1, 1);         // step s + 1: stage 1 was last read before the previous barrier
+            gload(r1, s + 3);
+            __syncthreads();
+            compute(1);         // step s + 1
+            put(r0, 0);         // step s + 2
+            gload(r0, s + 4);
             __syncthreads();
         }
     } else {

@@ -91,7 +91,7 @@ hipError_t launch_cfg(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
 }
 
 // Split-bf16 products with LDS staging: 128 x 128 tiles, 2 x 2 wavefronts.
-template <int P, int XCD, int GB, int DEPTH, int PAD, int SWZ>
+template <int P, int XCD, int GB, int DEPTH, int PAD, int SWZ, int LDB, int IGLP, int TO>
 __global__ void __launch_bounds__(256)
 k_gemm_lds(const GemmBatch<float> batch, int64_t n, int64_t ld, int64_t kpad, int ntile) {
     int tlin, z;
@@ -99,18 +99,19 @@ k_gemm_lds(const GemmBatch<float> batch, int64_t n, int64_t ld, int64_t kpad, in
     int ti, tj;
     if constexpr (GB > 0) blocked_tile(tlin, ntile, GB, ti, tj);
     else upper_tile(tlin, ntile, ti, tj);
-    gemm_tile_lds<P, DEPTH, PAD, SWZ>(batch.d[z], n, ld, kpad, ti, tj);
+    gemm_tile_lds<P, DEPTH, PAD, SWZ, LDB, IGLP, TO>(batch.d[z], n, ld, kpad, ti, tj);
 }
 
 // LDS layout: unpadded 64-byte rows with the 16-byte chunks of row r XOR-swizzled by
 // (r >> 1) & 3 (measured: 522 -> 570 TFLOP/s of bf16 work at N = 4000 against 8-element padding)
-template <int P, int XCD, int GB, int DEPTH = 2, int PAD = 0, int SWZ = 1>
+template <int P, int XCD, int GB, int DEPTH = 2, int PAD = 0, int SWZ = 1, int LDB = 1, int IGLP = -1, int TO = 0>
 hipError_t launch_lds(const GemmBatch<float>& b, int64_t n, int64_t ld, hipStream_t st) {
     const int64_t kpad = (n + 63) / 64 * 64;
     const int ntile = (int)((n + 127) / 128);
     if (kpad > ld || (int64_t)ntile * 128 > ld) return hipErrorInvalidValue;
     dim3 grid((unsigned)(ntile * (ntile + 1) / 2), 1, (unsigned)b.count);
-    hipLaunchKernelGGL((k_gemm_lds<P, XCD, GB, DEPTH, PAD, SWZ>), grid, dim3(256), 0, st, b, n, ld, kpad, ntile);
+    hipLaunchKernelGGL((k_gemm_lds<P, XCD, GB, DEPTH, PAD, SWZ, LDB, IGLP, TO>), grid, dim3(256), 0, st, b, n, ld,
+                       kpad, ntile);
     return hipGetLastError();
 }
 
@@ -147,9 +148,16 @@ hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
         // LDS staging (each element split once per work-group, panels two K steps ahead) once
         // there are >= 100 128-tiles: three-term split at N = 4000 390 -> 563 TFLOP/s of bf16
         // work, N = 2000 four products 289 -> 532; the six-term split gains only with several
-        // products per launch (N = 2000, four: 498 -> 688; N = 4000 single: 749 vs 709)
+        // products per launch (N = 2000, four: 498 -> 688; N = 4000 single: 749 vs 709).
+        // Three-term: two LDS stages (one barrier per K step) and the compiler's MFMA/LDS
+        // interleave (iglp 0), 591 -> 617 at N = 4000; six-term: interleave only (two stages
+        // would take 96 KB of LDS, one work-group per CU), 742 -> 754.
         const int64_t t128 = (n + 127) / 128, w128 = t128 * (t128 + 1) / 2 * b.count;
-        if (w128 >= 100 && (P == P_BF16X3 || b.count >= 2)) return launch_lds<P, 1, 0, 2>(b, n, ld, st);
+        if constexpr (P == P_BF16X3) {
+            if (w128 >= 100) return launch_lds<P, 1, 0, 2, 0, 1, 2, 0>(b, n, ld, st);
+        } else {
+            if (w128 >= 100 && b.count >= 2) return launch_lds<P, 1, 0, 2, 0, 1, 1, 0>(b, n, ld, st);
+        }
         if (w64 < 300) return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st);
         return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st);
     }
