@@ -73,10 +73,19 @@ enum chebdm_baby {
                                 /* of ~i^2, which matters for float32 / bf16 products     */
 };
 
-/* How the giant steps combine the blocks (both give the same polynomial). */
+/* How the giant steps combine the blocks (all give the same polynomial). */
 enum chebdm_giant {
-    CHEBDM_GIANT_COMPOSITION = 0, /* sum_l T_l(T_k) R_l by Clenshaw over l (default) */
-    CHEBDM_GIANT_POWER = 1        /* paper's sum_j T_k^j S_j by Horner (eq. "ansatz") */
+    CHEBDM_GIANT_COMPOSITION = 0, /* sum_l T_l(T_k) R_l by Clenshaw over l (default);  */
+                                  /* the library picks one or two chains (below)      */
+    CHEBDM_GIANT_POWER = 1,       /* paper's sum_j T_k^j S_j by Horner (eq. "ansatz") */
+    CHEBDM_GIANT_ONE_CHAIN = 2,   /* composition form, one Clenshaw chain: m-1 steps  */
+    CHEBDM_GIANT_TWO_CHAINS = 3   /* composition form as two chains of about m/2      */
+                                  /* steps run side by side, joined by one product    */
+                                  /* with T_h(T_k), h = ceil(m/2) (via eq. "identity"),*/
+                                  /* when that matrix comes from the moment ladder:   */
+                                  /* chebdm_mu_search with D and m >= 4; otherwise one */
+                                  /* chain.  Same m-1 products, half the sequential   */
+                                  /* launches, two products per launch.               */
 };
 
 /* How chebdm_mu_search finds mu~ on the quadrature trace t(mu~) (both stop
@@ -267,8 +276,9 @@ int chebdm_mu_search(chebdm_handle h, const double* dH, int64_t n, int64_t ldh,
 /*
  * Device memory a call of chebdm_density / chebdm_mu_search / chebdm_moments
  * with these sizes and options makes the handle hold (it keeps the largest it
- * has needed): the matrix workspace, (k + m) ld^2 elements with
- * ld = round_up(n, 128) and 8 (float64) or 4 bytes per element, plus the
+ * has needed): the matrix workspace, (k + m) ld^2 elements (k + m + 1 for
+ * the composition form with m >= 4: the two-chain giant steps keep T_h(T_k))
+ * with ld = round_up(n, 128) and 8 (float64) or 4 bytes per element, plus the
  * small buffers sized for opts->n_quad quadrature nodes (2^16 when 0).
  * Needs no device; h may be NULL.  ERR_ARG on bad sizes or options.
  */

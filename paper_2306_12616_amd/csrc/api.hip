@@ -78,6 +78,8 @@ struct Plan {
     int search = CHEBDM_SEARCH_BISECTION;
     int damping = CHEBDM_DAMPING_NONE;
     int bounds = CHEBDM_BOUNDS_GERSHGORIN, lz_steps = 40;
+    int chains = 0;    // composition form: 0 library's choice, 1 or 2 chains
+    int split_h = 0;   // > 0: giant steps as two Clenshaw chains joined by T_h(T_k) (extra slot k + m)
     double lz_margin = 0.01;
     double tol = 1e-10;
     size_t elem = 8;
@@ -188,7 +190,7 @@ int check_opts(const chebdm_opts* o, Plan& pl) {
     chebdm_default_opts(&d);
     if (!o) o = &d;
     if (o->prec < CHEBDM_FP64 || o->prec > CHEBDM_BF16X6) return fail(CHEBDM_ERR_ARG, "unknown precision");
-    if (o->giant_form != CHEBDM_GIANT_COMPOSITION && o->giant_form != CHEBDM_GIANT_POWER)
+    if (o->giant_form < CHEBDM_GIANT_COMPOSITION || o->giant_form > CHEBDM_GIANT_TWO_CHAINS)
         return fail(CHEBDM_ERR_ARG, "unknown giant-step form");
     if (o->giant_form == CHEBDM_GIANT_POWER && o->prec != CHEBDM_FP64)
         return fail(CHEBDM_ERR_UNSUPPORTED,
@@ -216,7 +218,8 @@ int check_opts(const chebdm_opts* o, Plan& pl) {
                   ? o->baby_steps
                   : (o->prec == CHEBDM_FP64 ? CHEBDM_BABY_STAGES : CHEBDM_BABY_SEQUENTIAL);
     pl.prec = o->prec;
-    pl.form = o->giant_form;
+    pl.form = o->giant_form == CHEBDM_GIANT_POWER ? CHEBDM_GIANT_POWER : CHEBDM_GIANT_COMPOSITION;
+    pl.chains = o->giant_form == CHEBDM_GIANT_ONE_CHAIN ? 1 : (o->giant_form == CHEBDM_GIANT_TWO_CHAINS ? 2 : 0);
     pl.elem = o->prec == CHEBDM_FP64 ? 8 : 4;
     pl.max_iter = o->max_iter ? o->max_iter : 200;
     pl.tol = o->tol > 0.0 ? o->tol : 1e-10;
@@ -271,6 +274,12 @@ int resolve_bounds(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, do
     return 0;
 }
 
+// Library's choice between one and two giant-step chains.  Measured (mu search + D, order 512,
+// DM/s one -> two chains): N = 1000 float64 405 -> 412, float32 417 -> 433, split-bf16 354 -> 384;
+// N = 2000 float64 82.5 -> 82.7, float32 107.1 -> 106.0, split-bf16 162 -> 177; N = 4000
+// float64 13.51 -> 13.53, float32 27.00 -> 26.93, split-bf16 43.0 -> 44.9.
+bool two_chains_pay(const Plan& pl) { return !(pl.prec == CHEBDM_FP32 && pl.n >= 1500); }
+
 int plan_quadrature(Plan& pl, double beta, double emin, double emax) {
     const double beta_s = beta * 0.5 * (emax - emin);
     if (pl.M <= 0) pl.M = quadrature_rule(pl.order, beta_s);
@@ -278,6 +287,15 @@ int plan_quadrature(Plan& pl, double beta, double emin, double emax) {
     if (pl.M < pl.order + 1) return fail(CHEBDM_ERR_ARG, "n_quad must be at least order + 1");
     if (pl.M > (1 << 26)) return fail(CHEBDM_ERR_ARG, "n_quad above 2^26");
     return 0;
+}
+
+// Split point of the two-chain giant steps, or 0 for one chain.  Two chains need T_h(T_k), which
+// only the mu search's moment ladder provides, and m >= 4; the library's choice takes them
+// where one product per launch leaves the chip underfilled.
+int two_chain_split(const Plan& pl, bool ladder_and_density) {
+    if (pl.form != CHEBDM_GIANT_COMPOSITION || !ladder_and_density || pl.m < 4 || pl.chains == 1) return 0;
+    if (pl.chains == 0 && !two_chains_pay(pl)) return 0;
+    return (pl.m + 1) / 2;
 }
 
 // ---------------------------------------------------------------- GEMM helper
@@ -337,7 +355,7 @@ void* rslot(chebdm_handle h, const Plan& pl, int l) { return slot(h, pl, pl.k + 
 // Everything a captured device sequence depends on: if two calls agree on all of it, every
 // kernel argument of their sequences agrees, and the first call's graph can be replayed.
 struct ReplayKey {
-    int32_t kind, order, k, m, prec, form, baby, search, max_iter, bounds_on_device, damping;
+    int32_t kind, order, k, m, prec, form, baby, search, max_iter, bounds_on_device, damping, split_h;
     int64_t n, ld, ldh, ldd, M;
     const void *dH, *dD, *mats, *small;
     double tol, beta, x, emin, emax;   // x: n_elec (mu search) or mu (density)
@@ -354,6 +372,7 @@ std::vector<char> replay_key(int kind, const Plan& pl, chebdm_handle h, const do
     k.m = pl.m;
     k.prec = pl.prec;
     k.form = pl.form;
+    k.split_h = pl.split_h;
     k.baby = pl.baby;
     k.search = pl.search;
     k.max_iter = pl.max_iter;
@@ -528,7 +547,13 @@ int moments_on_device(chebdm_handle h, const Plan& pl, int* n_gemm) {
     const int k = pl.k, L = pl.order;
     int lmax = (L >= 1) ? (L - 1) / k : 0;
     if (lmax > pl.m - 1) lmax = pl.m - 1;
-    auto lptr = [&](int l) -> void* { return l == 1 ? tslot(h, pl, k) : rslot(h, pl, l - 2); };
+    // T_{lk} lives in R slot l - 2 (overwritten later by the block sums), except T_{hk} of a
+    // split giant-step chain, which is kept in slot k + m
+    auto lptr = [&](int l) -> void* {
+        if (l == 1) return tslot(h, pl, k);
+        if (pl.split_h > 0 && l == pl.split_h) return slot(h, pl, (int64_t)k + pl.m);
+        return rslot(h, pl, l - 2);
+    };
     // the ladder T_{lk} = T_l(T_k) is the same Chebyshev recurrence in Y = T_k, so it takes the
     // baby steps' schedule (stage-parallel or sequential)
     Chain ch(h, pl, n_gemm);
@@ -572,7 +597,28 @@ int giant_steps(chebdm_handle h, const Plan& pl, double* dD, int64_t ldd, int* n
     } else {
         void* Y = k >= 1 ? tslot(h, pl, k) : nullptr;
         Chain ch(h, pl, n_gemm);
-        if (pl.form == CHEBDM_GIANT_COMPOSITION) {
+        if (pl.form == CHEBDM_GIANT_COMPOSITION && pl.split_h > 0) {
+            // two Clenshaw chains in Y = T_k, advanced together (two products per launch):
+            // S_A = sum_{l<h} T_l(Y) R''_l over R slots 0..h-1 and S_B = sum_{j<m-h} T_j(Y) R'_j
+            // over R slots h..m-1 (blocks rearranged by launch_split_blocks), then
+            // D = S_A + T_h(Y) S_B with T_h(Y) = T_{hk} kept from the ladder.
+            const int hs = pl.split_h;
+            const int la = hs, lb = m - hs;   // chain lengths (terms)
+            auto step = [&](int base, int len, int l) {   // Clenshaw step l of the chain at R slot base
+                const void* b2 = (l + 2 <= len - 1) ? rslot(h, pl, base + l + 2) : nullptr;
+                const double a = l >= 1 ? 2.0 : 1.0;
+                ch.add(Y, rslot(h, pl, base + l + 1), b2, -1.0, rslot(h, pl, base + l), 1.0, a, 0.0,
+                       rslot(h, pl, base + l), pl.ld, 0);
+            };
+            for (int t = 0; t < la - 1; ++t) {
+                step(0, la, la - 2 - t);
+                if (t < lb - 1) step(hs, lb, lb - 2 - t);
+                CHECK(ch.flush());
+            }
+            ch.add(slot(h, pl, (int64_t)k + m), rslot(h, pl, hs), nullptr, 0.0, rslot(h, pl, 0), 1.0, 1.0, 0.0, dD,
+                   ldd, 1);
+            CHECK(ch.flush());
+        } else if (pl.form == CHEBDM_GIANT_COMPOSITION) {
             // Clenshaw over l with Y = T_k: B_{m-1} = R_{m-1};
             // B_l = R_l + 2 Y B_{l+1} - B_{l+2} (in place in R_l); D = R_0 + Y B_1 - B_2.
             for (int l = m - 2; l >= 1; --l) {
@@ -869,7 +915,8 @@ int chebdm_mu_search(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, 
     CHECK(plan_quadrature(pl, beta, emin, emax));
     CHECK(ensure_small(h, pl.M));
     pl.ld = round_up(n, 128);
-    CHECK(ensure_mats(h, pl, pl.k + pl.m));
+    pl.split_h = two_chain_split(pl, dD != nullptr);
+    CHECK(ensure_mats(h, pl, pl.k + pl.m + (pl.split_h > 0 ? 1 : 0)));
     const int slot = dD ? 0 : 1;
     const std::vector<char> key = replay_key(slot, pl, h, dH, ldh, dD, dD ? ldd : 0, beta, n_elec, bounds_dev,
                                              emin, emax);
@@ -888,6 +935,7 @@ int chebdm_mu_search(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, 
         if (dD) {
             HIP_TRY(launch_fermi_coeffs(order, pl.M, h->scal, h->ftab, h->c, h->stream, pl.damping));
             HIP_TRY(launch_block_coeffs(h->c, order, pl.k, pl.m, pl.form, h->coef, h->stream));
+            if (pl.split_h > 0) HIP_TRY(launch_split_blocks(h->coef, pl.k, pl.m, pl.split_h, h->stream));
             CHECK(giant_steps(h, pl, dD, ldd, &pl.n_gemm));
         }
         return 0;
@@ -916,7 +964,8 @@ int chebdm_workspace_size(chebdm_handle h, int64_t n, int32_t order, const chebd
     CHECK(plan_split(pl));
     const int64_t ld = round_up(n, 128);
     const int64_t M = opts && opts->n_quad > 0 ? opts->n_quad : (int64_t)1 << 16;
-    *bytes = (size_t)(pl.k + pl.m) * (size_t)ld * (size_t)ld * pl.elem + small_bytes_for(M);
+    const int64_t slots = pl.k + pl.m + (pl.form == CHEBDM_GIANT_COMPOSITION && pl.m >= 4 ? 1 : 0);
+    *bytes = (size_t)slots * (size_t)ld * (size_t)ld * pl.elem + small_bytes_for(M);
     return CHEBDM_OK;
 }
 

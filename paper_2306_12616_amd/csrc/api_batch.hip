@@ -296,8 +296,12 @@ int chebdm_batch_create(chebdm_handle h, int32_t count, const int64_t* n, int32_
     chebdm_default_opts(&o);
     if (opts) o = *opts;
     if (o.prec < CHEBDM_FP64 || o.prec > CHEBDM_BF16X6) return fail(CHEBDM_ERR_ARG, "unknown precision");
-    if (o.giant_form != CHEBDM_GIANT_COMPOSITION)
-        return fail(CHEBDM_ERR_UNSUPPORTED, "the batched path uses the composition form only");
+    if (o.giant_form == CHEBDM_GIANT_POWER || o.giant_form == CHEBDM_GIANT_TWO_CHAINS)
+        return fail(CHEBDM_ERR_UNSUPPORTED, "the batched path uses the composition form in one chain only");
+    if (o.giant_form < CHEBDM_GIANT_COMPOSITION || o.giant_form > CHEBDM_GIANT_TWO_CHAINS)
+        return fail(CHEBDM_ERR_ARG, "unknown giant-step form");
+    if (o.bounds != CHEBDM_BOUNDS_GERSHGORIN)
+        return fail(CHEBDM_ERR_UNSUPPORTED, "the batched path computes Gershgorin bounds only");
     if (o.n_quad != 0) return fail(CHEBDM_ERR_UNSUPPORTED, "the batched path sizes the quadrature per problem");
     if (o.search != CHEBDM_SEARCH_BISECTION && o.search != CHEBDM_SEARCH_NEWTON)
         return fail(CHEBDM_ERR_ARG, "unknown mu search");

@@ -95,6 +95,8 @@ hipError_t launch_fermi_coeffs(int order, int M, const DevScalars* s, double* f_
                                hipStream_t st, int damping = 0);
 hipError_t launch_block_coeffs(const double* c, int order, int k, int m, int form, double* coef,
                                hipStream_t st);
+// composition-form blocks rearranged for two Clenshaw chains split at h (m - h <= h)
+hipError_t launch_split_blocks(double* coef, int k, int m, int h, hipStream_t st);
 hipError_t launch_assemble_moments(const double* tr_baby, const double* gram, int k, int m,
                                    int order, int64_t n, double* tau, hipStream_t st);
 hipError_t launch_dct3(const double* tau, int order, int M, double* w, double* x_tab, hipStream_t st,

@@ -212,6 +212,28 @@ hipError_t launch_fermi_coeffs(int order, int M, const DevScalars* s, double* f_
     return hipGetLastError();
 }
 
+// Two Clenshaw chains for the giant steps: with T_{h+j} = 2 T_h T_j - T_{h-j} (eq. "identity"
+// with a = h, b = j), sum_{l<m} T_l(Y) R_l = sum_{l<h} T_l(Y) R''_l + T_h(Y) sum_{j<m-h} T_j(Y) R'_j,
+// R'_0 = R_h, R'_j = 2 R_{h+j}, R''_{h-j} = R_{h-j} - R_{h+j} (1 <= j < m - h <= h).  Applied to
+// the block coefficients in place: block h + j then holds R'_j.
+namespace {
+__global__ void k_split_blocks(double* __restrict__ coef, int k, int m, int h) {
+    const int i = threadIdx.x;
+    if (i >= k) return;
+    for (int j = 1; h + j < m; ++j) {
+        const double up = coef[(h + j) * k + i];
+        coef[(h - j) * k + i] -= up;
+        coef[(h + j) * k + i] = 2.0 * up;
+    }
+}
+}  // namespace
+
+hipError_t launch_split_blocks(double* coef, int k, int m, int h, hipStream_t st) {
+    if (k > kMaxBlocks || m > kMaxBlocks || h < 1 || m - h > h) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_split_blocks, dim3(1), dim3(64), 0, st, coef, k, m, h);
+    return hipGetLastError();
+}
+
 hipError_t launch_block_coeffs(const double* c, int order, int k, int m, int form, double* coef,
                                hipStream_t st) {
     if (k > kMaxBlocks || m > kMaxBlocks) return hipErrorInvalidValue;

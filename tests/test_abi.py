@@ -107,11 +107,14 @@ def test_block_split_override_and_limits(lib):
 
 
 def test_workspace_size_needs_no_device(lib):
-    # (k + m) ld^2 elements plus the small buffers; k = m = 23 at order 512, ld = 4096 at n = 4000
+    # (k + m + 1) ld^2 elements plus the small buffers; k = m = 23 at order 512, ld = 4096 at
+    # n = 4000 (the extra matrix is T_h(T_k) of the two-chain giant steps; none for the power form)
     small = chebdm.chebdm_workspace_size(1, 0)
     f64 = chebdm.chebdm_workspace_size(4000, 512)
     f32 = chebdm.chebdm_workspace_size(4000, 512, chebdm.make_opts("fp32"))
-    assert f64 - small >= 46 * 4096 * 4096 * 8 - 2 * 128 * 128 * 8
-    assert f64 - f32 == 46 * 4096 * 4096 * 4
+    power = chebdm.chebdm_workspace_size(4000, 512, chebdm.make_opts("fp64", "power"))
+    assert f64 - small >= 47 * 4096 * 4096 * 8 - 2 * 128 * 128 * 8
+    assert f64 - f32 == 47 * 4096 * 4096 * 4
+    assert f64 - power == 4096 * 4096 * 8
     with pytest.raises(chebdm.ChebdmError):
         chebdm.chebdm_workspace_size(0, 10)

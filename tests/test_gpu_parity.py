@@ -220,6 +220,11 @@ MU_CASES = [
     (520, "highdos", 255, 60.0, 260.0, "composition", "bisection"),
     (300, "gaussmix6", 200, 80.0, 101.5, "composition", "newton"),
     (520, "highdos", 255, 60.0, 260.0, "composition", "newton"),
+    # giant steps forced to one chain, or to two chains (m = 4, 5 and 10: the smallest splits)
+    (256, "uniform", 128, 50.0, 128.0, "one_chain", "bisection"),
+    (200, "uniform", 15, 20.0, 100.5, "two_chains", "bisection"),
+    (200, "gaussmix6", 24, 20.0, 100.5, "two_chains", "bisection"),
+    (333, "highdos", 99, 40.0, 166.5, "two_chains", "newton"),
 ]
 
 
@@ -477,3 +482,20 @@ def test_mu_search_tight_binding(cd, handle, kind, bounds):
          f"max|D-D_oracle|={err:.1e}")
     assert err <= 1e-10
     assert abs(t_or - ne) <= 1e-9
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 1e-5), ("bf16x3", 2e-5)])
+def test_one_and_two_giant_chains_agree(cd, handle, prec, tol):
+    # same polynomial, different association: D agrees to rounding; same product count
+    n, order, beta = 700, 512, 100.0
+    h, q, lam = synth.hamiltonian(n, "gaussmix6", seed=2000)
+    H = _dev(h)
+    out = {}
+    for form in ("one_chain", "two_chains"):
+        mu, D, info = cd.chebdm_mu_search(handle, H, beta, n / 2, order, cd.make_opts(prec, form))
+        out[form] = (mu, D.cpu().numpy(), info)
+    (mu1, d1, i1), (mu2, d2, i2) = out["one_chain"], out["two_chains"]
+    assert mu1 == mu2 and i1["n_gemm"] == i2["n_gemm"] and i1["iters"] == i2["iters"]
+    err = float(np.max(np.abs(d1 - d2)))
+    _say(f"  {prec}: max|D_one - D_two| = {err:.2e}, n_gemm {i1['n_gemm']}")
+    assert err <= tol
