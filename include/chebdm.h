@@ -313,13 +313,17 @@ int chebdm_block_coeffs(chebdm_handle h, const double* c, int32_t order, int32_t
  * afterwards; the caller's pointers, beta and N_e are read from a table
  * uploaded before each replay, so the graph is reused across calls).  Per
  * problem it computes exactly what chebdm_mu_search computes (Gershgorin
- * bounds, sequential baby steps, ladder and Gram moments, the mu search,
- * composition-form giant steps); every product step of all problems is one
- * persistent launch over a list of (problem, tile) items.
+ * bounds, or Lanczos bounds inside them with opts->bounds, sequential baby
+ * steps, ladder and Gram moments, the mu search, composition-form giant steps
+ * in one chain); every product step of all problems is one persistent launch
+ * over a list of (problem, tile) items.
  *
  * chebdm_batch_create: count problems of sizes n[p] (1..65535), order >= 2
- *   (k, m >= 2); opts: prec any, giant_form must be COMPOSITION, n_quad 0,
- *   search sets the initial search mode (0 or 1, see chebdm_batch_set_search);
+ *   (k, m >= 2); opts: prec any, giant_form COMPOSITION or ONE_CHAIN, n_quad 0,
+ *   search sets the initial search mode (0 or 1, see chebdm_batch_set_search),
+ *   bounds / lanczos_steps / bounds_margin as for one problem (the Lanczos
+ *   workspace is count x lanczos_work(max n) doubles, about 350 KB per problem
+ *   at n = 1024 and 40 steps);
  *   max_quad caps the per-problem quadrature M (0 = 65536; a problem whose
  *   rule asks for more reports CHEBDM_ERR_ARG in its status).  Allocates
  *   sum_p (k+m) ld_p^2 workspace elements (ld_p = round_up(n_p, 128)).

@@ -489,9 +489,8 @@ int lanczos_on_device(chebdm_handle h, const double* dH, int64_t n, int64_t ldh,
     std::vector<char> key(sizeof(lk));
     std::memcpy(key.data(), &lk, sizeof(lk));
     int unused = 0;
-    const LanczosWork L = lanczos_layout(h->lz, n, k);
     return run_replayed(h, 3, key, &unused, [&]() -> int {
-        HIP_TRY(launch_lanczos(dH, n, ldh, k, margin, seed, L, h->scal, h->stream));
+        HIP_TRY(launch_lanczos(dH, n, ldh, k, margin, seed, h->lz, h->scal, h->stream));
         return 0;
     });
 }

@@ -2,7 +2,7 @@
 // common order, run as one HIP graph (captured on first use, replayed after).
 //
 // Per problem the device runs the same hot path as chebdm_mu_search:
-// Gershgorin bounds, H~, sequential baby steps T_2..T_k, ladder T_{2k}..,
+// Gershgorin bounds (then Lanczos bounds inside them, if asked), H~, sequential baby steps T_2..T_k, ladder T_{2k}..,
 // Gram moments, DCT-III + bisection, coefficients at the found mu, block
 // sums, Clenshaw giant steps into the caller's D.  Every product step of all
 // problems is one persistent launch over a shared list of (problem, tile)
@@ -74,6 +74,11 @@ struct chebdm_batch_ctx {
     const float* mlp_w = nullptr;
     double mlp_delta = 0.02;
     float *feat = nullptr, *mu_hat = nullptr, *mlp_work = nullptr;
+    // Lanczos bounds (opts.bounds): per-problem workspace, steps and margin; lz == nullptr: Gershgorin
+    double* lz = nullptr;
+    int64_t lz_stride = 0;
+    int lz_steps = 0;
+    double lz_margin = 0.01;
     // graphs: [0] with the density, [1] moments and mu only
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
@@ -194,6 +199,19 @@ int enqueue(chebdm_batch_ctx* b, hipStream_t st, bool prof, bool with_density) {
     HIP_TRY(launch_batch_zero(b->counters, b->steps, st));
     if (with_density) HIP_TRY(launch_batch_patch(d, b->tab, const_cast<void*>(step_descs(b, b->steps - 1)), st));
     HIP_TRY(launch_batch_bounds(d, b->tab, b->geo, b->colsum, b->scal, st));
+    if (b->lz) {
+        LanczosRun r{};
+        r.tab = b->tab;
+        r.geo = b->geo;
+        r.s = b->scal;
+        r.base = b->lz;
+        r.stride = b->lz_stride;
+        r.nmax = d.nmax;
+        r.steps = b->lz_steps;
+        r.margin = b->lz_margin;
+        r.seed = 0;
+        HIP_TRY(launch_lanczos_run(r, d.count, st));
+    }
     HIP_TRY(launch_batch_setup(d, b->tab, b->geo, b->scal, b->mq, b->tol, b->max_iter, st));
     HIP_TRY(launch_batch_shift(d, b->tab, b->geo, b->scal, b->mats, st));
     for (int s = 0; s < b->steps_pre; ++s) CHECK(gemm_step(b, s, st, prof));
@@ -300,8 +318,12 @@ int chebdm_batch_create(chebdm_handle h, int32_t count, const int64_t* n, int32_
         return fail(CHEBDM_ERR_UNSUPPORTED, "the batched path uses the composition form in one chain only");
     if (o.giant_form < CHEBDM_GIANT_COMPOSITION || o.giant_form > CHEBDM_GIANT_TWO_CHAINS)
         return fail(CHEBDM_ERR_ARG, "unknown giant-step form");
-    if (o.bounds != CHEBDM_BOUNDS_GERSHGORIN)
-        return fail(CHEBDM_ERR_UNSUPPORTED, "the batched path computes Gershgorin bounds only");
+    if (o.bounds != CHEBDM_BOUNDS_GERSHGORIN && o.bounds != CHEBDM_BOUNDS_LANCZOS)
+        return fail(CHEBDM_ERR_ARG, "unknown bounds method");
+    if (o.lanczos_steps < 0 || o.lanczos_steps > kMaxLanczosSteps)
+        return fail(CHEBDM_ERR_ARG, "lanczos_steps must be in [0, 128]");
+    if (!(o.bounds_margin >= 0.0) || !std::isfinite(o.bounds_margin))
+        return fail(CHEBDM_ERR_ARG, "bounds_margin must be finite and >= 0");
     if (o.n_quad != 0) return fail(CHEBDM_ERR_UNSUPPORTED, "the batched path sizes the quadrature per problem");
     if (o.search != CHEBDM_SEARCH_BISECTION && o.search != CHEBDM_SEARCH_NEWTON)
         return fail(CHEBDM_ERR_ARG, "unknown mu search");
@@ -355,6 +377,17 @@ int chebdm_batch_create(chebdm_handle h, int32_t count, const int64_t* n, int32_
     if (hipStreamCreateWithFlags(&b->bs, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&b->ready, hipEventDisableTiming) != hipSuccess)
         return bail(fail(CHEBDM_ERR_HIP, "cannot create the batch stream"));
+    if (o.bounds == CHEBDM_BOUNDS_LANCZOS) {
+        b->lz_steps = o.lanczos_steps ? o.lanczos_steps : 40;
+        b->lz_margin = o.bounds_margin > 0.0 ? o.bounds_margin : 0.01;
+        b->lz_stride = (lanczos_work_doubles(nmax, b->lz_steps) + 31) / 32 * 32;
+        const size_t lz_bytes = sizeof(double) * (size_t)b->lz_stride * (size_t)count;
+        if (hipMalloc(&b->lz, lz_bytes) != hipSuccess) {
+            b->lz = nullptr;
+            (void)hipGetLastError();
+            return bail(fail(CHEBDM_ERR_OOM, "cannot allocate " + std::to_string(lz_bytes) + " bytes of Lanczos workspace"));
+        }
+    }
     b->mats_bytes = (size_t)tot * b->elem;
     if (hipMalloc(&b->mats, b->mats_bytes) != hipSuccess) {
         b->mats = nullptr;
@@ -440,6 +473,7 @@ int chebdm_batch_destroy(chebdm_batch b) {
     if (b->items) (void)hipFree(b->items);
     if (b->dev) (void)hipFree(b->dev);
     if (b->mats) (void)hipFree(b->mats);
+    if (b->lz) (void)hipFree(b->lz);
     if (b->host) (void)hipHostFree(b->host);
     if (b->ready) (void)hipEventDestroy(b->ready);
     if (b->bs) (void)hipStreamDestroy(b->bs);

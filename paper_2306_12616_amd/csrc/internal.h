@@ -84,11 +84,12 @@ struct LanczosWork {          // views into one device buffer of lanczos_work_do
     int32_t* state;            // [0]: steps done at a breakdown (0: none), [1]: steps done
 };
 int64_t lanczos_work_doubles(int64_t n, int steps);
-LanczosWork lanczos_layout(double* base, int64_t n, int steps);
+__host__ __device__ LanczosWork lanczos_layout(double* base, int64_t n, int steps);
 // Overwrites s->emin / s->emax (which must hold the Gershgorin bounds) with the Lanczos bounds.
-// steps in [1, min(n, kMaxLanczosSteps)].
+// steps in [1, min(n, kMaxLanczosSteps)]; work: lanczos_work_doubles(n, steps) doubles laid out
+// by lanczos_layout(work, n, steps).
 hipError_t launch_lanczos(const double* H, int64_t n, int64_t ldh, int steps, double margin, uint64_t seed,
-                          const LanczosWork& L, DevScalars* s, hipStream_t st);
+                          double* work, DevScalars* s, hipStream_t st);
 
 // ---- coefficients / decomposition / moments / bisection (k_cheb.hip)
 hipError_t launch_fermi_coeffs(int order, int M, const DevScalars* s, double* f_tab, double* c_out,
@@ -140,6 +141,23 @@ struct BatchGeom {         // fixed for a plan
     int32_t tile;          // product tile edge: 64 or 32 (chosen by the tuner)
     int32_t ntile;         // ceil(n / tile)
 };
+
+// Lanczos bounds of a batch (k_lanczos.hip): problem p uses tab[p].H / ldh, geo[p].n, s[p] and
+// the workspace base + p * stride (stride >= lanczos_work_doubles(nmax, steps)), laid out by
+// lanczos_layout(.., n_p, min(steps, n_p)).  With tab == nullptr: one problem (H, n, ldh).
+struct LanczosRun {
+    const BatchProblem* tab;
+    const BatchGeom* geo;
+    const double* H;
+    int64_t n, ldh;
+    DevScalars* s;
+    double* base;
+    int64_t stride, nmax;
+    int32_t steps, pad;
+    double margin;
+    uint64_t seed;
+};
+hipError_t launch_lanczos_run(const LanczosRun& r, int count, hipStream_t st);
 
 struct TileItem {          // one tile of one problem's product in a step
     int32_t p;             // problem

@@ -20,6 +20,10 @@
 // partials, so the result does not depend on scheduling.  The tridiagonal
 // extremes come from Sturm-sequence multisection (Barth, Martin, Wilkinson 1967)
 // in one work-group.
+//
+// The same kernels serve one problem and a batch of problems of different n
+// (the batched form): blockIdx.y (blockIdx.z for the projections) selects the
+// problem, whose workspace, scalars and step count min(steps, n) are its own.
 #include <cmath>
 
 #include "internal.h"
@@ -35,6 +39,36 @@ constexpr int kRowsPerWave = 2;
 constexpr int kRowsPerBlock = (kNT / 64) * kRowsPerWave;
 constexpr double kBreakdown = 1e-12;
 
+__host__ __device__ inline int64_t blocks_of(int64_t n, int64_t per) { return (n + per - 1) / per; }
+
+// One problem of a run: its matrix, size, scalars, workspace views and step count.
+struct LzProblem {
+    const double* H;
+    int64_t n, ldh;
+    DevScalars* s;
+    LanczosWork L;
+    int k, nbv, nbr;
+};
+
+__device__ inline LzProblem problem_of(const LanczosRun& r, int p) {
+    LzProblem q;
+    if (r.tab) {
+        q.H = r.tab[p].H;
+        q.ldh = r.tab[p].ldh;
+        q.n = r.geo[p].n;
+    } else {
+        q.H = r.H;
+        q.ldh = r.ldh;
+        q.n = r.n;
+    }
+    q.s = r.s + p;
+    q.k = (int)(q.n < r.steps ? q.n : r.steps);
+    q.L = lanczos_layout(r.base + (int64_t)p * r.stride, q.n, q.k);
+    q.nbv = (int)blocks_of(q.n, kSlice);
+    q.nbr = (int)blocks_of(q.n, kRowsPerBlock);
+    return q;
+}
+
 __device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t i) {
     uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -49,56 +83,56 @@ __device__ inline double sum_partials(const double* __restrict__ p, int count, d
     return block_sum<kNT>(acc, smem);
 }
 
-__global__ void __launch_bounds__(kNT)
-k_lz_init(int64_t n, uint64_t seed, double* __restrict__ w, double* __restrict__ pn, int32_t* __restrict__ state) {
+__global__ void __launch_bounds__(kNT) k_lz_init(const LanczosRun r) {
     __shared__ double smem[kNT / 64];
+    const LzProblem q = problem_of(r, blockIdx.y);
+    if ((int)blockIdx.x >= q.nbv) return;
     const int64_t base = (int64_t)blockIdx.x * kSlice;
     double acc = 0.0;
 #pragma unroll
-    for (int q = 0; q < kSlice / kNT; ++q) {
-        const int64_t e = base + q * kNT + threadIdx.x;
-        if (e < n) {
-            const uint64_t z = splitmix64_at(seed, (uint64_t)e);
+    for (int c = 0; c < kSlice / kNT; ++c) {
+        const int64_t e = base + c * kNT + threadIdx.x;
+        if (e < q.n) {
+            const uint64_t z = splitmix64_at(r.seed, (uint64_t)e);
             const double u = 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
-            w[e] = u;
+            q.L.w[e] = u;
             acc += u * u;
         }
     }
     acc = block_sum<kNT>(acc, smem);
-    if (threadIdx.x == 0) pn[blockIdx.x] = acc;
+    if (threadIdx.x == 0) q.L.pn[blockIdx.x] = acc;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        state[0] = 0;   // steps done at a breakdown (0: none)
-        state[1] = 0;   // steps done in total
+        q.L.state[0] = 0;   // steps done at a breakdown (0: none)
+        q.L.state[1] = 0;   // steps done in total
     }
 }
 
 // beta = ||w|| from the partial norms; v_j = w / beta; w2 = (H w) / beta; partial v_j . w2.
-__global__ void __launch_bounds__(kNT)
-k_lz_matvec(const double* __restrict__ H, int64_t n, int64_t ldh, int j, double* __restrict__ V,
-            const double* __restrict__ w, double* __restrict__ w2, double* __restrict__ pa,
-            const double* __restrict__ pn, int nbv, double* __restrict__ beta, int32_t* __restrict__ state,
-            const DevScalars* __restrict__ s) {
+__global__ void __launch_bounds__(kNT) k_lz_matvec(const LanczosRun r, int j) {
     __shared__ double smem[kNT / 64];
     __shared__ double part[kNT / 64];
-    if (state[0]) return;
-    const double bt = sqrt(sum_partials(pn, nbv, smem));
+    const LzProblem q = problem_of(r, blockIdx.y);
+    if (j >= q.k || (int)blockIdx.x >= q.nbr || q.L.state[0]) return;
+    const int64_t n = q.n;
+    const double bt = sqrt(sum_partials(q.L.pn, q.nbv, smem));
     if (j > 0) {
-        const double scale = fmax(fabs(s->emin), fabs(s->emax));
+        const double scale = fmax(fabs(q.s->emin), fabs(q.s->emax));
         const bool broke = !(bt > kBreakdown * scale);
         if (blockIdx.x == 0 && threadIdx.x == 0) {
-            beta[j - 1] = bt;
-            if (broke) state[0] = j;
+            q.L.beta[j - 1] = bt;
+            if (broke) q.L.state[0] = j;
         }
         if (broke) return;
     }
+    const double* __restrict__ w = q.L.w;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlock + wave * kRowsPerWave;
     double y[kRowsPerWave];
 #pragma unroll
     for (int t = 0; t < kRowsPerWave; ++t) y[t] = 0.0;
     if (r0 < n) {
-        const double* h0 = H + r0 * ldh;
-        const double* h1 = H + (r0 + 1 < n ? r0 + 1 : r0) * ldh;
+        const double* h0 = q.H + r0 * q.ldh;
+        const double* h1 = q.H + (r0 + 1 < n ? r0 + 1 : r0) * q.ldh;
 #pragma unroll 4
         for (int64_t c = lane; c < n; c += 64) {
             const double x = w[c];
@@ -108,16 +142,16 @@ k_lz_matvec(const double* __restrict__ H, int64_t n, int64_t ldh, int j, double*
     }
 #pragma unroll
     for (int t = 0; t < kRowsPerWave; ++t) y[t] = wave_sum(y[t]);
-    double contrib = 0.0;
     if (lane == 0) {
+        double contrib = 0.0;
 #pragma unroll
         for (int t = 0; t < kRowsPerWave; ++t) {
-            const int64_t r = r0 + t;
-            if (r < n) {
-                const double v = w[r] / bt;
+            const int64_t row = r0 + t;
+            if (row < n) {
+                const double v = w[row] / bt;
                 const double z = y[t] / bt;
-                V[(int64_t)j * n + r] = v;
-                w2[r] = z;
+                q.L.V[(int64_t)j * n + row] = v;
+                q.L.w2[row] = z;
                 contrib += v * z;
             }
         }
@@ -127,76 +161,74 @@ k_lz_matvec(const double* __restrict__ H, int64_t n, int64_t ldh, int j, double*
     if (threadIdx.x == 0) {
         double acc = 0.0;
 #pragma unroll
-        for (int q = 0; q < kNT / 64; ++q) acc += part[q];
-        pa[blockIdx.x] = acc;
+        for (int c = 0; c < kNT / 64; ++c) acc += part[c];
+        q.L.pa[blockIdx.x] = acc;
     }
 }
 
-__global__ void __launch_bounds__(kNT)
-k_lz_alpha(int j, const double* __restrict__ pa, int nbr, double* __restrict__ alpha,
-           const int32_t* __restrict__ state) {
+__global__ void __launch_bounds__(kNT) k_lz_alpha(const LanczosRun r, int j) {
     __shared__ double smem[kNT / 64];
-    if (state[0]) return;
-    const double a = sum_partials(pa, nbr, smem);
-    if (threadIdx.x == 0) alpha[j] = a;
+    const LzProblem q = problem_of(r, blockIdx.y);
+    if (j >= q.k || q.L.state[0]) return;
+    const double a = sum_partials(q.L.pa, q.nbr, smem);
+    if (threadIdx.x == 0) q.L.alpha[j] = a;
 }
 
 // x = w2 - alpha_j v_j - beta_{j-1} v_{j-1} on a slice (stored by the blockIdx.y == 0 row
 // of blocks); partial v_i . x for i = blockIdx.y.
-__global__ void __launch_bounds__(kNT)
-k_lz_proj(int64_t n, int j, const double* __restrict__ V, const double* __restrict__ w2,
-          const double* __restrict__ alpha, const double* __restrict__ beta, double* __restrict__ w,
-          double* __restrict__ pc, int nbv, const int32_t* __restrict__ state) {
+__global__ void __launch_bounds__(kNT) k_lz_proj(const LanczosRun r, int j) {
     __shared__ double smem[kNT / 64];
-    if (state[0]) return;
+    const LzProblem q = problem_of(r, blockIdx.z);
+    if (j >= q.k || (int)blockIdx.x >= q.nbv || q.L.state[0]) return;
+    const int64_t n = q.n;
     const int i = blockIdx.y;
-    const double a = alpha[j], bm = j > 0 ? beta[j - 1] : 0.0;
-    const double* vj = V + (int64_t)j * n;
-    const double* vm = V + (int64_t)(j > 0 ? j - 1 : 0) * n;
-    const double* vi = V + (int64_t)i * n;
+    const double a = q.L.alpha[j], bm = j > 0 ? q.L.beta[j - 1] : 0.0;
+    const double* vj = q.L.V + (int64_t)j * n;
+    const double* vm = q.L.V + (int64_t)(j > 0 ? j - 1 : 0) * n;
+    const double* vi = q.L.V + (int64_t)i * n;
     const int64_t base = (int64_t)blockIdx.x * kSlice;
     double acc = 0.0;
 #pragma unroll
-    for (int q = 0; q < kSlice / kNT; ++q) {
-        const int64_t e = base + q * kNT + threadIdx.x;
+    for (int c = 0; c < kSlice / kNT; ++c) {
+        const int64_t e = base + c * kNT + threadIdx.x;
         if (e < n) {
-            double x = w2[e] - a * vj[e];
+            double x = q.L.w2[e] - a * vj[e];
             if (j > 0) x -= bm * vm[e];
-            if (i == 0) w[e] = x;
+            if (i == 0) q.L.w[e] = x;
             acc += vi[e] * x;
         }
     }
     acc = block_sum<kNT>(acc, smem);
-    if (threadIdx.x == 0) pc[(int64_t)i * nbv + blockIdx.x] = acc;
+    if (threadIdx.x == 0) q.L.pc[(int64_t)i * q.nbv + blockIdx.x] = acc;
 }
 
 // c_i = sum of the partials; w -= sum_{i<=j} c_i v_i on a slice; partial ||w||^2.
-__global__ void __launch_bounds__(kNT)
-k_lz_reorth(int64_t n, int j, const double* __restrict__ V, double* __restrict__ w,
-            const double* __restrict__ pc, int nbv, double* __restrict__ pn, const int32_t* __restrict__ state) {
+__global__ void __launch_bounds__(kNT) k_lz_reorth(const LanczosRun r, int j) {
     __shared__ double smem[kNT / 64];
     __shared__ double c[kMaxLanczosSteps];
-    if (state[0]) return;
+    const LzProblem q = problem_of(r, blockIdx.y);
+    if (j >= q.k || (int)blockIdx.x >= q.nbv || q.L.state[0]) return;
+    const int64_t n = q.n;
     for (int i = threadIdx.x; i <= j; i += kNT) {
         double acc = 0.0;
-        for (int b = 0; b < nbv; ++b) acc += pc[(int64_t)i * nbv + b];
+        for (int b = 0; b < q.nbv; ++b) acc += q.L.pc[(int64_t)i * q.nbv + b];
         c[i] = acc;
     }
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSlice;
     double acc = 0.0;
 #pragma unroll
-    for (int q = 0; q < kSlice / kNT; ++q) {
-        const int64_t e = base + q * kNT + threadIdx.x;
+    for (int t = 0; t < kSlice / kNT; ++t) {
+        const int64_t e = base + t * kNT + threadIdx.x;
         if (e < n) {
-            double x = w[e];
-            for (int i = 0; i <= j; ++i) x -= c[i] * V[(int64_t)i * n + e];
-            w[e] = x;
+            double x = q.L.w[e];
+            for (int i = 0; i <= j; ++i) x -= c[i] * q.L.V[(int64_t)i * n + e];
+            q.L.w[e] = x;
             acc += x * x;
         }
     }
     acc = block_sum<kNT>(acc, smem);
-    if (threadIdx.x == 0) pn[blockIdx.x] = acc;
+    if (threadIdx.x == 0) q.L.pn[blockIdx.x] = acc;
 }
 
 // Number of eigenvalues of the tridiagonal (a, b) below x (Sturm sequence of the LDL^T pivots).
@@ -217,26 +249,25 @@ __device__ inline int sturm_count(const double* a, const double* b, int k, doubl
 constexpr int kFinalNT = 128;   // wave 0: theta_min, wave 1: theta_max
 constexpr int kRounds = 12;     // 65-way multisection: 65^12 > 2^72
 
-__global__ void __launch_bounds__(kFinalNT)
-k_lz_final(int steps, const double* __restrict__ alpha, double* __restrict__ beta, const double* __restrict__ pn,
-           int nbv, int32_t* __restrict__ state, double margin, DevScalars* __restrict__ s) {
+__global__ void __launch_bounds__(kFinalNT) k_lz_final(const LanczosRun r) {
     __shared__ double a[kMaxLanczosSteps], b[kMaxLanczosSteps];
     __shared__ double theta[2];
     __shared__ double smem[kFinalNT / 64];
     __shared__ double r_last;
-    const int done = state[0];
-    const int k = done ? done : steps;
+    const LzProblem q = problem_of(r, blockIdx.y);
+    const int done = q.L.state[0];
+    const int k = done ? done : q.k;
     double acc = 0.0;
-    for (int q = threadIdx.x; q < nbv; q += kFinalNT) acc += pn[q];
+    for (int c = threadIdx.x; c < q.nbv; c += kFinalNT) acc += q.L.pn[c];
     acc = block_sum<kFinalNT>(acc, smem);
     if (threadIdx.x == 0) {
-        r_last = done ? beta[k - 1] : sqrt(acc);
-        if (!done) beta[k - 1] = r_last;
-        state[1] = k;
+        r_last = done ? q.L.beta[k - 1] : sqrt(acc);
+        if (!done) q.L.beta[k - 1] = r_last;
+        q.L.state[1] = k;
     }
     for (int i = threadIdx.x; i < k; i += kFinalNT) {
-        a[i] = alpha[i];
-        b[i] = i + 1 < k ? beta[i] : 0.0;
+        a[i] = q.L.alpha[i];
+        b[i] = i + 1 < k ? q.L.beta[i] : 0.0;
     }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -262,29 +293,29 @@ k_lz_final(int steps, const double* __restrict__ alpha, double* __restrict__ bet
     if (lane == 0) theta[wave] = wave == 0 ? lo : hi;   // outer side of the final interval
     __syncthreads();
     if (threadIdx.x == 0) {
-        const double g_lo = s->emin, g_hi = s->emax;
+        const double g_lo = q.s->emin, g_hi = q.s->emax;
         double e_lo = theta[0] - r_last, e_hi = theta[1] + r_last;
-        const double pad = margin * (e_hi - e_lo);
+        const double pad = r.margin * (e_hi - e_lo);
         e_lo = fmax(e_lo - pad, g_lo);
         e_hi = fmin(e_hi + pad, g_hi);
         if (!(e_lo <= e_hi)) {
             e_lo = g_lo;
             e_hi = g_hi;
         }
-        s->emin = e_lo;
-        s->emax = e_hi;
+        q.s->emin = e_lo;
+        q.s->emax = e_hi;
     }
 }
 
 }  // namespace
 
 int64_t lanczos_work_doubles(int64_t n, int steps) {
-    const int64_t nbv = (n + kSlice - 1) / kSlice, nbr = (n + kRowsPerBlock - 1) / kRowsPerBlock;
+    const int64_t nbv = blocks_of(n, kSlice), nbr = blocks_of(n, kRowsPerBlock);
     return (int64_t)steps * n + 2 * n + nbr + (int64_t)steps * nbv + nbv + 2 * (int64_t)steps + 2;
 }
 
-LanczosWork lanczos_layout(double* base, int64_t n, int steps) {
-    const int64_t nbv = (n + kSlice - 1) / kSlice, nbr = (n + kRowsPerBlock - 1) / kRowsPerBlock;
+__host__ __device__ LanczosWork lanczos_layout(double* base, int64_t n, int steps) {
+    const int64_t nbv = blocks_of(n, kSlice), nbr = blocks_of(n, kRowsPerBlock);
     LanczosWork L;
     double* p = base;
     L.V = p;
@@ -307,26 +338,37 @@ LanczosWork lanczos_layout(double* base, int64_t n, int steps) {
     return L;
 }
 
-hipError_t launch_lanczos(const double* H, int64_t n, int64_t ldh, int steps, double margin, uint64_t seed,
-                          const LanczosWork& L, DevScalars* s, hipStream_t st) {
-    if (steps < 1 || steps > kMaxLanczosSteps || steps > n) return hipErrorInvalidValue;
-    const int nbv = (int)((n + kSlice - 1) / kSlice);
-    const int nbr = (int)((n + kRowsPerBlock - 1) / kRowsPerBlock);
-    hipLaunchKernelGGL(k_lz_init, dim3(nbv), dim3(kNT), 0, st, n, seed, L.w, L.pn, L.state);
+hipError_t launch_lanczos_run(const LanczosRun& r, int count, hipStream_t st) {
+    if (r.steps < 1 || r.steps > kMaxLanczosSteps || count < 1 || count > 65535 || r.nmax < 1) return hipErrorInvalidValue;
+    if (r.stride < lanczos_work_doubles(r.nmax, r.steps)) return hipErrorInvalidValue;
+    const int nbv = (int)blocks_of(r.nmax, kSlice), nbr = (int)blocks_of(r.nmax, kRowsPerBlock);
+    const int steps = (int)(r.nmax < r.steps ? r.nmax : r.steps);
+    hipLaunchKernelGGL(k_lz_init, dim3(nbv, count), dim3(kNT), 0, st, r);
     for (int j = 0; j < steps; ++j) {
-        hipLaunchKernelGGL(k_lz_matvec, dim3(nbr), dim3(kNT), 0, st, H, n, ldh, j, L.V, (const double*)L.w, L.w2,
-                           L.pa, (const double*)L.pn, nbv, L.beta, L.state, (const DevScalars*)s);
-        hipLaunchKernelGGL(k_lz_alpha, dim3(1), dim3(kNT), 0, st, j, (const double*)L.pa, nbr, L.alpha,
-                           (const int32_t*)L.state);
-        hipLaunchKernelGGL(k_lz_proj, dim3(nbv, j + 1), dim3(kNT), 0, st, n, j, (const double*)L.V,
-                           (const double*)L.w2, (const double*)L.alpha, (const double*)L.beta, L.w, L.pc, nbv,
-                           (const int32_t*)L.state);
-        hipLaunchKernelGGL(k_lz_reorth, dim3(nbv), dim3(kNT), 0, st, n, j, (const double*)L.V, L.w,
-                           (const double*)L.pc, nbv, L.pn, (const int32_t*)L.state);
+        hipLaunchKernelGGL(k_lz_matvec, dim3(nbr, count), dim3(kNT), 0, st, r, j);
+        hipLaunchKernelGGL(k_lz_alpha, dim3(1, count), dim3(kNT), 0, st, r, j);
+        hipLaunchKernelGGL(k_lz_proj, dim3(nbv, j + 1, count), dim3(kNT), 0, st, r, j);
+        hipLaunchKernelGGL(k_lz_reorth, dim3(nbv, count), dim3(kNT), 0, st, r, j);
     }
-    hipLaunchKernelGGL(k_lz_final, dim3(1), dim3(kFinalNT), 0, st, steps, (const double*)L.alpha, L.beta,
-                       (const double*)L.pn, nbv, L.state, margin, s);
+    hipLaunchKernelGGL(k_lz_final, dim3(1, count), dim3(kFinalNT), 0, st, r);
     return hipGetLastError();
+}
+
+hipError_t launch_lanczos(const double* H, int64_t n, int64_t ldh, int steps, double margin, uint64_t seed,
+                          double* work, DevScalars* s, hipStream_t st) {
+    if (steps < 1 || steps > kMaxLanczosSteps || steps > n) return hipErrorInvalidValue;
+    LanczosRun r{};
+    r.H = H;
+    r.n = n;
+    r.ldh = ldh;
+    r.s = s;
+    r.base = work;
+    r.stride = lanczos_work_doubles(n, steps);
+    r.nmax = n;
+    r.steps = steps;
+    r.margin = margin;
+    r.seed = seed;
+    return launch_lanczos_run(r, 1, st);
 }
 
 }  // namespace chebdm

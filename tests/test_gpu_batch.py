@@ -203,3 +203,43 @@ def test_batch_jackson_damping_matches_oracle(cd, handle):
         assert float(np.max(np.abs(Ds[p].cpu().numpy() - ref))) <= 1e-10
         assert abs(ch.trace_of_series(c, ch.moments_from_eigs(lam, lo, hi, order)) - nes[p]) <= 1e-9
     batch.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_batch_lanczos_bounds_match_single_and_oracle(cd, handle, prec, tol):
+    # per-problem Lanczos bounds inside the batch graph: the same kernels as the single-problem
+    # call (so the same bounds bit for bit), then every problem held to the oracle at them
+    sizes = [33, 96, 257, 600, 130, 5]
+    order = 128
+    laws = ["uniform", "gaussmix6", "highdos"]
+    probs = [synth.hamiltonian(n, laws[i % 3], seed=900 + i) for i, n in enumerate(sizes)]
+    Hs = [_dev(h) for h, _, _ in probs]
+    betas = [30.0 + 10 * i for i in range(len(sizes))]
+    nes = [0.5 * n + 0.5 for n in sizes]
+    batch = cd.Batch(handle, sizes, order, cd.make_opts(prec, bounds="lanczos"))
+    mu, Ds, status, iters, trace = batch.mu_search(Hs, betas, nes)
+    _, _, _, beta_s = batch.stats()
+    for p, n in enumerate(sizes):
+        h, q, lam = probs[p]
+        lo, hi, _, _ = cd.chebdm_bounds_lanczos(handle, Hs[p], 40, 0.01, 0)
+        rlo, rhi, _, _ = ch.lanczos_bounds(h, 40, 0.01, 0)
+        scale = max(abs(rlo), abs(rhi))
+        assert abs(lo - rlo) <= 1e-10 * scale and abs(hi - rhi) <= 1e-10 * scale
+        assert beta_s[p] == betas[p] * (0.5 * (hi - lo)), (p, beta_s[p], betas[p] * 0.5 * (hi - lo))
+        assert status[p] == 0, (p, status[p])
+        cen, a = ch.scaling(lo, hi)
+        M = ch.quadrature_size(order, betas[p] * a)
+        err, t_err = _check_problem(q, lam, Ds[p], mu[p], order, betas[p], nes[p], (lo, hi), M, tol,
+                                    1e-9 if prec == "fp64" else 1e-5 * n)
+        _say(f"  p={p} n={n} [{lo:.4f}, {hi:.4f}] err={err:.1e} t_err={t_err:.1e}")
+    batch.close()
+
+
+def test_batch_rejects_unsupported_options(cd, handle):
+    for kw in ({"giant": "power"}, {"giant": "two_chains"}, {"n_quad": 4096}):
+        with pytest.raises(cd.ChebdmError) as e:
+            cd.Batch(handle, [64, 80], 32, cd.make_opts("fp64", **kw))
+        assert e.value.code == -6, kw
+    with pytest.raises(cd.ChebdmError) as e:
+        cd.Batch(handle, [64, 80], 32, cd.make_opts("fp64", bounds="lanczos", lanczos_steps=200))
+    assert e.value.code == -1
