@@ -246,7 +246,20 @@ def batch_row(cd, handle, torch, prec="fp32", order=256, reps=3):
     prof = cd.chebdm_profile_read(handle)
     cd.chebdm_profile_enable(handle, False)
     info = b.info()
+    _, _, _, beta_s = b.stats()
     b.close()
+    # the same batch with per-problem Lanczos bounds (40 steps) inside the graph
+    bl = cd.Batch(handle, sizes, order, cd.make_opts(prec, bounds="lanczos"))
+    bl.tune()
+    bl.mu_search(Hs, betas, nes, Ds)
+    _, _, _, beta_s_lz = bl.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, _, status_lz, _, _ = bl.mu_search(Hs, betas, nes, Ds)
+    torch.cuda.synchronize()
+    dt_lz = (time.perf_counter() - t0) / reps
+    bl.close()
     r = roofline_of(prof, prec)
     return {"workload": f"512 Hamiltonians, n uniform on {{96..1024}} step 32, beta on [30,200], N_e=n/2, "
                         f"order {order}, {prec}, one graph per batch",
@@ -255,7 +268,10 @@ def batch_row(cd, handle, torch, prec="fp32", order=256, reps=3):
             "gemm_tflops": r["achieved"] if r else None, "gemm_frac_of_peak": r["frac"] if r else None,
             "phases_ms_eager": {"gemm": round(prof["gemm_ms"], 2), "gram": round(prof["gram_ms"], 2),
                                 "combine": round(prof["combine_ms"], 2)},
-            "tuner": tune}
+            "tuner": tune, "median_beta_scaled": round(float(np.median(beta_s)), 1),
+            "lanczos_bounds": {"dm_per_s": round(512 / dt_lz, 1), "ms_per_batch": round(1e3 * dt_lz, 2),
+                               "all_ok": bool(np.all(status_lz == 0)),
+                               "median_beta_scaled": round(float(np.median(beta_s_lz)), 1)}}
 
 
 def learned_row(cd, handle, torch, order=256, chunks=20, chunk=1024, eval_count=1024, eval_n=500, epochs=40):
