@@ -79,17 +79,35 @@ struct PtrList {
 constexpr int kGramThreads = 256;
 constexpr int kGramMax = 48;   // rows / columns of G handled (3 MFMA blocks of 16)
 
-__device__ __forceinline__ f64x2 load2(const double* p) { return *reinterpret_cast<const f64x2*>(p); }
-__device__ __forceinline__ f64x2 load2(const float* p) {
-    const f32x2 v = *reinterpret_cast<const f32x2*>(p);
-    return f64x2{(double)v[0], (double)v[1]};
+// VW consecutive elements of one matrix per lane, widened to float64
+template <int VW> struct Lane;
+template <> struct Lane<2> { using V = f64x2; };
+template <> struct Lane<4> { using V = f64x4; };
+template <int VW>
+__device__ __forceinline__ typename Lane<VW>::V loadv(const double* p) {
+    return *reinterpret_cast<const typename Lane<VW>::V*>(p);
+}
+template <int VW>
+__device__ __forceinline__ typename Lane<VW>::V loadv(const float* p) {
+    typename Lane<VW>::V out;
+    if constexpr (VW == 2) {
+        const f32x2 v = *reinterpret_cast<const f32x2*>(p);
+        out = f64x2{(double)v[0], (double)v[1]};
+    } else {
+        const f32x4 v = *reinterpret_cast<const f32x4*>(p);
+        out = f64x4{(double)v[0], (double)v[1], (double)v[2], (double)v[3]};
+    }
+    return out;
 }
 
-template <typename T, int FM, int FN>
+// Chunks of CH = 4 VW consecutive elements: lane group lq holds elements lq VW .. lq VW + VW-1
+// of each of its matrices (VW = 4: every (matrix, chunk) is one whole 128-byte line in float64).
+template <typename T, int FM, int FN, int VW = 4>
 __global__ void __launch_bounds__(kGramThreads)
 k_gram_partial(const PtrList<T> lm, int nl, const PtrList<T> tm, int nt, int64_t nchunk,
                double* __restrict__ partial) {
-    constexpr int CH = 8;   // elements per chunk: 4 lane groups x 2
+    using V = typename Lane<VW>::V;
+    constexpr int CH = 4 * VW;
     __shared__ double red[FM * 16][FN * 16 + 1];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lq = lane >> 4;
@@ -102,12 +120,12 @@ k_gram_partial(const PtrList<T> lm, int nl, const PtrList<T> tm, int nt, int64_t
 #pragma unroll
     for (int f = 0; f < FM; ++f) {
         const int li = f * 16 + lr;
-        pa[f] = lm.p[li < nl ? li : 0] + lq * 2;
+        pa[f] = lm.p[li < nl ? li : 0] + lq * VW;
     }
 #pragma unroll
     for (int g = 0; g < FN; ++g) {
         const int ti = g * 16 + lr;
-        pb[g] = tm.p[ti < nt ? ti : 0] + lq * 2;
+        pb[g] = tm.p[ti < nt ? ti : 0] + lq * VW;
     }
     f64x4 acc[FM][FN];
 #pragma unroll
@@ -115,22 +133,22 @@ k_gram_partial(const PtrList<T> lm, int nl, const PtrList<T> tm, int nt, int64_t
 #pragma unroll
         for (int g = 0; g < FN; ++g) acc[f][g] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-    // four chunks per iteration: all their loads are issued before the first MFMA
-    constexpr int U = 4;
+    // U chunks per iteration: all their loads are issued before the first MFMA
+    constexpr int U = 8 / VW;
     int64_t c = c_begin;
     for (; c + U <= c_end; c += U) {
-        f64x2 a[U][FM], b[U][FN];
+        V a[U][FM], b[U][FN];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
 #pragma unroll
-            for (int f = 0; f < FM; ++f) a[u][f] = load2(pa[f] + (c + u) * CH);
+            for (int f = 0; f < FM; ++f) a[u][f] = loadv<VW>(pa[f] + (c + u) * CH);
 #pragma unroll
-            for (int g = 0; g < FN; ++g) b[u][g] = load2(pb[g] + (c + u) * CH);
+            for (int g = 0; g < FN; ++g) b[u][g] = loadv<VW>(pb[g] + (c + u) * CH);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int s = 0; s < 2; ++s)
+            for (int s = 0; s < VW; ++s)
 #pragma unroll
                 for (int f = 0; f < FM; ++f)
 #pragma unroll
@@ -139,13 +157,13 @@ k_gram_partial(const PtrList<T> lm, int nl, const PtrList<T> tm, int nt, int64_t
     }
     for (; c < c_end; ++c) {
         const int64_t e = c * CH;
-        f64x2 a[FM], b[FN];
+        V a[FM], b[FN];
 #pragma unroll
-        for (int f = 0; f < FM; ++f) a[f] = load2(pa[f] + e);
+        for (int f = 0; f < FM; ++f) a[f] = loadv<VW>(pa[f] + e);
 #pragma unroll
-        for (int g = 0; g < FN; ++g) b[g] = load2(pb[g] + e);
+        for (int g = 0; g < FN; ++g) b[g] = loadv<VW>(pb[g] + e);
 #pragma unroll
-        for (int s = 0; s < 2; ++s)
+        for (int s = 0; s < VW; ++s)
 #pragma unroll
             for (int f = 0; f < FM; ++f)
 #pragma unroll
@@ -231,11 +249,11 @@ template <typename T>
 hipError_t launch_gram(const T* const* lmats, int nl, const T* const* tmats, int nt, int64_t nelem,
                        double* partial, int64_t partial_cap, double* G, hipStream_t st) {
     if (nl <= 0 || nt <= 0) return hipSuccess;
-    if (nl > kGramMax || nt > kGramMax || nelem % 8 != 0) return hipErrorInvalidValue;
+    if (nl > kGramMax || nt > kGramMax || nelem % 16 != 0) return hipErrorInvalidValue;
     PtrList<T> L{}, Tm{};
     for (int i = 0; i < nl; ++i) L.p[i] = lmats[i];
     for (int i = 0; i < nt; ++i) Tm.p[i] = tmats[i];
-    const int64_t nchunk = nelem / 8;
+    const int64_t nchunk = nelem / 16;
     int64_t nblocks = 1024;
     if (nblocks * 4 > nchunk) nblocks = (nchunk + 3) / 4;
     if (nblocks < 1) nblocks = 1;
