@@ -169,17 +169,39 @@ k_batch_traces(const BatchGeom* __restrict__ geo, const T* __restrict__ mats, in
     if (threadIdx.x == 0) trb[(int64_t)p * k + i] = acc;
 }
 
-__device__ __forceinline__ f64x2b ld2(const double* p) { return *reinterpret_cast<const f64x2b*>(p); }
-__device__ __forceinline__ f64x2b ld2(const float* p) {
-    typedef float f32x2 __attribute__((ext_vector_type(2)));
-    const f32x2 v = *reinterpret_cast<const f32x2*>(p);
-    return f64x2b{(double)v[0], (double)v[1]};
+// VW consecutive elements of one matrix per lane (32 bytes: 4 float64 or 8 float32), widened
+// to float64, loaded as 16-byte vectors
+template <int VW>
+struct GLane {
+    double v[VW];
+};
+template <int VW>
+__device__ __forceinline__ GLane<VW> gload(const double* p) {   // one 32-byte vector load
+    static_assert(VW == 4, "float64 lanes hold four elements");
+    const f64x4 x = *reinterpret_cast<const f64x4*>(p);
+    GLane<VW> out;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) out.v[t] = x[t];
+    return out;
+}
+template <int VW>
+__device__ __forceinline__ GLane<VW> gload(const float* p) {
+    GLane<VW> out;
+#pragma unroll
+    for (int c = 0; c < VW / 4; ++c) {
+        const f32x4 x = *reinterpret_cast<const f32x4*>(p + 4 * c);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) out.v[4 * c + t] = (double)x[t];
+    }
+    return out;
 }
 
 constexpr int kGM = 48;
 
 // G[l][i] = <L_l, T_i>, L_1 = T_k (slot k-1), L_l = T_{lk} (slot k+l-2), T_i in slot i-1.
-template <typename T, int FM, int FN>
+// Chunks of 4 VW elements: lane group lq holds VW consecutive elements of each of its matrices,
+// so every (matrix, chunk) is one whole 128-byte line.
+template <typename T, int FM, int FN, int VW = 32 / (int)sizeof(T)>
 __global__ void __launch_bounds__(256)
 k_batch_gram(const BatchGeom* __restrict__ geo, const T* __restrict__ mats, int k, int nl,
              double* __restrict__ partial) {
@@ -189,7 +211,8 @@ k_batch_gram(const BatchGeom* __restrict__ geo, const T* __restrict__ mats, int 
     const T* base = mats + geo[p].off;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lq = lane >> 4;
-    const int64_t nchunk = n * ld / 8;
+    constexpr int CH = 4 * VW;
+    const int64_t nchunk = n * ld / CH;
     const int64_t gw = (int64_t)blockIdx.x * 4 + wave, nw = (int64_t)gridDim.x * 4;
     const int64_t c0 = nchunk * gw / nw, c1 = nchunk * (gw + 1) / nw;
     const T* pa[FM];
@@ -199,55 +222,55 @@ k_batch_gram(const BatchGeom* __restrict__ geo, const T* __restrict__ mats, int 
         int l = f * 16 + lr + 1;                 // L index 1..nl
         if (l > nl) l = 1;
         const int64_t slot = (l == 1) ? k - 1 : k + l - 2;
-        pa[f] = base + slot * stride + lq * 2;
+        pa[f] = base + slot * stride + lq * VW;
     }
 #pragma unroll
     for (int g = 0; g < FN; ++g) {
         int i = g * 16 + lr + 1;                 // T index 1..k
         if (i > k) i = 1;
-        pb[g] = base + (int64_t)(i - 1) * stride + lq * 2;
+        pb[g] = base + (int64_t)(i - 1) * stride + lq * VW;
     }
     f64x4 acc[FM][FN];
 #pragma unroll
     for (int f = 0; f < FM; ++f)
 #pragma unroll
         for (int g = 0; g < FN; ++g) acc[f][g] = f64x4{0.0, 0.0, 0.0, 0.0};
-    // four chunks per iteration: all their loads are issued before the first MFMA
-    constexpr int U = 4;
+    // two chunks per iteration: all their loads are issued before the first MFMA
+    constexpr int U = 2;
     int64_t c = c0;
     for (; c + U <= c1; c += U) {
-        f64x2b a[U][FM], b[U][FN];
+        GLane<VW> a[U][FM], b[U][FN];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
 #pragma unroll
-            for (int f = 0; f < FM; ++f) a[u][f] = ld2(pa[f] + (c + u) * 8);
+            for (int f = 0; f < FM; ++f) a[u][f] = gload<VW>(pa[f] + (c + u) * CH);
 #pragma unroll
-            for (int g = 0; g < FN; ++g) b[u][g] = ld2(pb[g] + (c + u) * 8);
+            for (int g = 0; g < FN; ++g) b[u][g] = gload<VW>(pb[g] + (c + u) * CH);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int s = 0; s < 2; ++s)
+            for (int s = 0; s < VW; ++s)
 #pragma unroll
                 for (int f = 0; f < FM; ++f)
 #pragma unroll
                     for (int g = 0; g < FN; ++g)
-                        acc[f][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][f][s], b[u][g][s], acc[f][g], 0, 0, 0);
+                        acc[f][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][f].v[s], b[u][g].v[s], acc[f][g], 0, 0, 0);
     }
     for (; c < c1; ++c) {
-        const int64_t e = c * 8;
-        f64x2b a[FM], b[FN];
+        const int64_t e = c * CH;
+        GLane<VW> a[FM], b[FN];
 #pragma unroll
-        for (int f = 0; f < FM; ++f) a[f] = ld2(pa[f] + e);
+        for (int f = 0; f < FM; ++f) a[f] = gload<VW>(pa[f] + e);
 #pragma unroll
-        for (int g = 0; g < FN; ++g) b[g] = ld2(pb[g] + e);
+        for (int g = 0; g < FN; ++g) b[g] = gload<VW>(pb[g] + e);
 #pragma unroll
-        for (int s = 0; s < 2; ++s)
+        for (int s = 0; s < VW; ++s)
 #pragma unroll
             for (int f = 0; f < FM; ++f)
 #pragma unroll
                 for (int g = 0; g < FN; ++g)
-                    acc[f][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[f][s], b[g][s], acc[f][g], 0, 0, 0);
+                    acc[f][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[f].v[s], b[g].v[s], acc[f][g], 0, 0, 0);
     }
     // float64 MFMA output: row lq + 4r, column lr of each 16 x 16 block; waves add in order
     for (int w = 0; w < 4; ++w) {

@@ -79,34 +79,40 @@ struct PtrList {
 constexpr int kGramThreads = 256;
 constexpr int kGramMax = 48;   // rows / columns of G handled (3 MFMA blocks of 16)
 
-// VW consecutive elements of one matrix per lane, widened to float64
-template <int VW> struct Lane;
-template <> struct Lane<2> { using V = f64x2; };
-template <> struct Lane<4> { using V = f64x4; };
+// VW consecutive elements of one matrix per lane (32 bytes: 4 float64 or 8 float32), widened
+// to float64, loaded as 16-byte vectors
 template <int VW>
-__device__ __forceinline__ typename Lane<VW>::V loadv(const double* p) {
-    return *reinterpret_cast<const typename Lane<VW>::V*>(p);
+struct Lane {
+    double v[VW];
+};
+template <int VW>
+__device__ __forceinline__ Lane<VW> loadv(const double* p) {   // one 32-byte vector load
+    static_assert(VW == 4, "float64 lanes hold four elements");
+    const f64x4 x = *reinterpret_cast<const f64x4*>(p);
+    Lane<VW> out;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) out.v[t] = x[t];
+    return out;
 }
 template <int VW>
-__device__ __forceinline__ typename Lane<VW>::V loadv(const float* p) {
-    typename Lane<VW>::V out;
-    if constexpr (VW == 2) {
-        const f32x2 v = *reinterpret_cast<const f32x2*>(p);
-        out = f64x2{(double)v[0], (double)v[1]};
-    } else {
-        const f32x4 v = *reinterpret_cast<const f32x4*>(p);
-        out = f64x4{(double)v[0], (double)v[1], (double)v[2], (double)v[3]};
+__device__ __forceinline__ Lane<VW> loadv(const float* p) {
+    Lane<VW> out;
+#pragma unroll
+    for (int c = 0; c < VW / 4; ++c) {
+        const f32x4 x = *reinterpret_cast<const f32x4*>(p + 4 * c);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) out.v[4 * c + t] = (double)x[t];
     }
     return out;
 }
 
 // Chunks of CH = 4 VW consecutive elements: lane group lq holds elements lq VW .. lq VW + VW-1
-// of each of its matrices (VW = 4: every (matrix, chunk) is one whole 128-byte line in float64).
-template <typename T, int FM, int FN, int VW = 4>
+// of each of its matrices, so every (matrix, chunk) is one whole 128-byte line.
+template <typename T, int FM, int FN, int VW = 32 / (int)sizeof(T)>
 __global__ void __launch_bounds__(kGramThreads)
 k_gram_partial(const PtrList<T> lm, int nl, const PtrList<T> tm, int nt, int64_t nchunk,
                double* __restrict__ partial) {
-    using V = typename Lane<VW>::V;
+    using V = Lane<VW>;
     constexpr int CH = 4 * VW;
     __shared__ double red[FM * 16][FN * 16 + 1];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -133,8 +139,8 @@ k_gram_partial(const PtrList<T> lm, int nl, const PtrList<T> tm, int nt, int64_t
 #pragma unroll
         for (int g = 0; g < FN; ++g) acc[f][g] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-    // U chunks per iteration: all their loads are issued before the first MFMA
-    constexpr int U = 8 / VW;
+    // U chunks per iteration (64 bytes per lane and matrix): all loads issue before the first MFMA
+    constexpr int U = 2;
     int64_t c = c_begin;
     for (; c + U <= c_end; c += U) {
         V a[U][FM], b[U][FN];
@@ -153,7 +159,7 @@ k_gram_partial(const PtrList<T> lm, int nl, const PtrList<T> tm, int nt, int64_t
                 for (int f = 0; f < FM; ++f)
 #pragma unroll
                     for (int g = 0; g < FN; ++g)
-                        acc[f][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][f][s], b[u][g][s], acc[f][g], 0, 0, 0);
+                        acc[f][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][f].v[s], b[u][g].v[s], acc[f][g], 0, 0, 0);
     }
     for (; c < c_end; ++c) {
         const int64_t e = c * CH;
@@ -168,7 +174,7 @@ k_gram_partial(const PtrList<T> lm, int nl, const PtrList<T> tm, int nt, int64_t
             for (int f = 0; f < FM; ++f)
 #pragma unroll
                 for (int g = 0; g < FN; ++g)
-                    acc[f][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[f][s], b[g][s], acc[f][g], 0, 0, 0);
+                    acc[f][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[f].v[s], b[g].v[s], acc[f][g], 0, 0, 0);
     }
     // v_mfma_f64_16x16x4f64 leaves G row 16f + lq + 4r, column 16g + lr in lane (lr, lq),
     // register r; waves add in a fixed order
@@ -249,11 +255,12 @@ template <typename T>
 hipError_t launch_gram(const T* const* lmats, int nl, const T* const* tmats, int nt, int64_t nelem,
                        double* partial, int64_t partial_cap, double* G, hipStream_t st) {
     if (nl <= 0 || nt <= 0) return hipSuccess;
-    if (nl > kGramMax || nt > kGramMax || nelem % 16 != 0) return hipErrorInvalidValue;
+    constexpr int64_t CH = 4 * (32 / (int64_t)sizeof(T));   // elements per chunk
+    if (nl > kGramMax || nt > kGramMax || nelem % CH != 0) return hipErrorInvalidValue;
     PtrList<T> L{}, Tm{};
     for (int i = 0; i < nl; ++i) L.p[i] = lmats[i];
     for (int i = 0; i < nt; ++i) Tm.p[i] = tmats[i];
-    const int64_t nchunk = nelem / 16;
+    const int64_t nchunk = nelem / CH;
     int64_t nblocks = 1024;
     if (nblocks * 4 > nchunk) nblocks = (nchunk + 3) / 4;
     if (nblocks < 1) nblocks = 1;
