@@ -185,14 +185,13 @@ __device__ __forceinline__ GLane<VW> gload(const double* p) {   // one 32-byte v
     return out;
 }
 template <int VW>
-__device__ __forceinline__ GLane<VW> gload(const float* p) {
+__device__ __forceinline__ GLane<VW> gload(const float* p) {    // one 32-byte vector load
+    static_assert(VW == 8, "float32 lanes hold eight elements");
+    typedef float f32x8v __attribute__((ext_vector_type(8)));
+    const f32x8v x = *reinterpret_cast<const f32x8v*>(p);
     GLane<VW> out;
 #pragma unroll
-    for (int c = 0; c < VW / 4; ++c) {
-        const f32x4 x = *reinterpret_cast<const f32x4*>(p + 4 * c);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) out.v[4 * c + t] = (double)x[t];
-    }
+    for (int t = 0; t < 8; ++t) out.v[t] = (double)x[t];
     return out;
 }
 

@@ -95,14 +95,13 @@ __device__ __forceinline__ Lane<VW> loadv(const double* p) {   // one 32-byte ve
     return out;
 }
 template <int VW>
-__device__ __forceinline__ Lane<VW> loadv(const float* p) {
+__device__ __forceinline__ Lane<VW> loadv(const float* p) {    // one 32-byte vector load
+    static_assert(VW == 8, "float32 lanes hold eight elements");
+    typedef float f32x8v __attribute__((ext_vector_type(8)));
+    const f32x8v x = *reinterpret_cast<const f32x8v*>(p);
     Lane<VW> out;
 #pragma unroll
-    for (int c = 0; c < VW / 4; ++c) {
-        const f32x4 x = *reinterpret_cast<const f32x4*>(p + 4 * c);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) out.v[4 * c + t] = (double)x[t];
-    }
+    for (int t = 0; t < 8; ++t) out.v[t] = (double)x[t];
     return out;
 }
 
