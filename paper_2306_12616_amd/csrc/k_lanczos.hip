@@ -14,9 +14,9 @@
 // Gershgorin interval alone if the intersection is empty).
 //
 // Kernels per step: the product H v_j (one wavefront per two rows, H read once
-// along rows), alpha (one work-group), the three-term update with the partial
-// projections v_i . w (a grid of slices x (j + 1)), and the reorthogonalisation
-// with the partial norm.  Every reduction is a fixed-order sum of per-block
+// along rows), alpha (one work-group; folded into the next kernel up to n = 8192),
+// the three-term update with the partial projections v_i . w (a grid of slices
+// x (j + 1)), and the reorthogonalisation with the partial norm.  Every reduction is a fixed-order sum of per-block
 // partials, so the result does not depend on scheduling.  The tridiagonal
 // extremes come from Sturm-sequence multisection (Barth, Martin, Wilkinson 1967)
 // in one work-group.
@@ -175,14 +175,22 @@ __global__ void __launch_bounds__(kNT) k_lz_alpha(const LanczosRun r, int j) {
 }
 
 // x = w2 - alpha_j v_j - beta_{j-1} v_{j-1} on a slice (stored by the blockIdx.y == 0 row
-// of blocks); partial v_i . x for i = blockIdx.y.
-__global__ void __launch_bounds__(kNT) k_lz_proj(const LanczosRun r, int j) {
+// of blocks); partial v_i . x for i = blockIdx.y.  With fuse_alpha every block folds the
+// alpha partials itself (the same fixed order as k_lz_alpha) and block (0, 0) stores alpha_j.
+__global__ void __launch_bounds__(kNT) k_lz_proj(const LanczosRun r, int j, int fuse_alpha) {
     __shared__ double smem[kNT / 64];
     const LzProblem q = problem_of(r, blockIdx.z);
     if (j >= q.k || (int)blockIdx.x >= q.nbv || q.L.state[0]) return;
     const int64_t n = q.n;
     const int i = blockIdx.y;
-    const double a = q.L.alpha[j], bm = j > 0 ? q.L.beta[j - 1] : 0.0;
+    double a;
+    if (fuse_alpha) {
+        a = sum_partials(q.L.pa, q.nbr, smem);
+        if (blockIdx.x == 0 && i == 0 && threadIdx.x == 0) q.L.alpha[j] = a;
+    } else {
+        a = q.L.alpha[j];
+    }
+    const double bm = j > 0 ? q.L.beta[j - 1] : 0.0;
     const double* vj = q.L.V + (int64_t)j * n;
     const double* vm = q.L.V + (int64_t)(j > 0 ? j - 1 : 0) * n;
     const double* vi = q.L.V + (int64_t)i * n;
@@ -343,11 +351,14 @@ hipError_t launch_lanczos_run(const LanczosRun& r, int count, hipStream_t st) {
     if (r.stride < lanczos_work_doubles(r.nmax, r.steps)) return hipErrorInvalidValue;
     const int nbv = (int)blocks_of(r.nmax, kSlice), nbr = (int)blocks_of(r.nmax, kRowsPerBlock);
     const int steps = (int)(r.nmax < r.steps ? r.nmax : r.steps);
+    // up to 1024 alpha partials (n <= 8192) every projection block folds them itself: one
+    // launch per step fewer; beyond that one work-group folds them once
+    const int fuse = nbr <= 1024 ? 1 : 0;
     hipLaunchKernelGGL(k_lz_init, dim3(nbv, count), dim3(kNT), 0, st, r);
     for (int j = 0; j < steps; ++j) {
         hipLaunchKernelGGL(k_lz_matvec, dim3(nbr, count), dim3(kNT), 0, st, r, j);
-        hipLaunchKernelGGL(k_lz_alpha, dim3(1, count), dim3(kNT), 0, st, r, j);
-        hipLaunchKernelGGL(k_lz_proj, dim3(nbv, j + 1, count), dim3(kNT), 0, st, r, j);
+        if (!fuse) hipLaunchKernelGGL(k_lz_alpha, dim3(1, count), dim3(kNT), 0, st, r, j);
+        hipLaunchKernelGGL(k_lz_proj, dim3(nbv, j + 1, count), dim3(kNT), 0, st, r, j, fuse);
         hipLaunchKernelGGL(k_lz_reorth, dim3(nbv, count), dim3(kNT), 0, st, r, j);
     }
     hipLaunchKernelGGL(k_lz_final, dim3(1, count), dim3(kFinalNT), 0, st, r);
