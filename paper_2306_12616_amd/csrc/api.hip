@@ -157,6 +157,14 @@ int ensure_mats(chebdm_handle h, const Plan& pl, int64_t count) {
         h->mats_bytes = bytes;
         h->lay_ld = -1;
     }
+    // split-bf16 products: partial accumulators of K-sliced tail tiles
+    if ((pl.prec == CHEBDM_BF16X3 || pl.prec == CHEBDM_BF16X6) && !h->gemm_scratch) {
+        if (hipMalloc(&h->gemm_scratch, kGemmScratchBytes) != hipSuccess) {
+            h->gemm_scratch = nullptr;
+            (void)hipGetLastError();
+            return fail(CHEBDM_ERR_OOM, "cannot allocate the product scratch");
+        }
+    }
     // The kernels rely on a zero padding outside each n x n block; a new
     // layout (n, leading dimension, element size or a larger count) is cleared once.
     if (h->lay_n != pl.n || h->lay_ld != pl.ld || h->lay_elem != pl.elem || h->lay_count < count) {
@@ -333,7 +341,8 @@ struct Chain {
         hipError_t e = hipSuccess;
         if (pl.elem == 8) e = launch_gemm_f64(b64, pl.n, pl.ld, h->stream);
         else e = launch_gemm_f32(b32, pl.n, pl.ld,
-                                 pl.prec == CHEBDM_BF16X6 ? 2 : (pl.prec == CHEBDM_BF16X3 ? 1 : 0), h->stream);
+                                 pl.prec == CHEBDM_BF16X6 ? 2 : (pl.prec == CHEBDM_BF16X3 ? 1 : 0), h->stream,
+                                 h->gemm_scratch, h->gemm_scratch ? kGemmScratchBytes : 0);
         b64.count = 0;
         b32.count = 0;
         HIP_TRY(e);
@@ -714,6 +723,7 @@ int chebdm_destroy(chebdm_handle h) {
     if (h->mats) (void)hipFree(h->mats);
     if (h->small) (void)hipFree(h->small);
     if (h->lz) (void)hipFree(h->lz);
+    if (h->gemm_scratch) (void)hipFree(h->gemm_scratch);
     if (h->mlp_work) (void)hipFree(h->mlp_work);
     if (h->h_scal) (void)hipHostFree(h->h_scal);
     delete h;
@@ -965,6 +975,7 @@ int chebdm_workspace_size(chebdm_handle h, int64_t n, int32_t order, const chebd
     const int64_t M = opts && opts->n_quad > 0 ? opts->n_quad : (int64_t)1 << 16;
     const int64_t slots = pl.k + pl.m + (pl.form == CHEBDM_GIANT_COMPOSITION && pl.m >= 4 ? 1 : 0);
     *bytes = (size_t)slots * (size_t)ld * (size_t)ld * pl.elem + small_bytes_for(M);
+    if (pl.prec == CHEBDM_BF16X3 || pl.prec == CHEBDM_BF16X6) *bytes += kGemmScratchBytes;
     return CHEBDM_OK;
 }
 

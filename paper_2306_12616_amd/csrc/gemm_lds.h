@@ -37,9 +37,9 @@ struct SplitTerms<P_BF16X6> {
 // (r >> SWZ) & 3 (a bank swizzle; use with PAD = 0).
 // LDB = 2 keeps two LDS stages: step s + 1 is written into one while step s is read from the
 // other, so one barrier per K step suffices (LDB = 1: two, around the single stage).
-template <int P, int DEPTH = 2, int PAD = 8, int SWZ = 0, int LDB = 1, int IGLP = -1, int TO = 0>
+template <int P, int DEPTH = 2, int PAD = 8, int SWZ = 0, int LDB = 1, int IGLP = -1>
 __device__ __forceinline__ void gemm_tile_lds(const GemmDesc<float>& g, int64_t n, int64_t ld, int64_t kpad, int ti,
-                                              int tj) {
+                                              int tj, int64_t s0 = 0, int64_t s1 = -1, f32x4* part = nullptr) {
     static_assert(P == P_BF16X3 || P == P_BF16X6, "split-bf16 precisions only");
     static_assert(DEPTH == 1 || DEPTH == 2, "prefetch depth 1 or 2");
     static_assert(LDB == 1 || (LDB == 2 && DEPTH == 2), "two LDS stages need two register stages");
@@ -59,7 +59,8 @@ __device__ __forceinline__ void gemm_tile_lds(const GemmDesc<float>& g, int64_t 
     const int srow = tid >> 1, sk = (tid & 1) * 16;
     const float* __restrict__ ga = g.A + ((int64_t)ti * BM + srow) * ld + sk;
     const float* __restrict__ gb = g.B + ((int64_t)tj * BM + srow) * ld + sk;
-    const int64_t steps = kpad / KC;
+    // K steps [s0, s1) of KC (s1 < 0: all); both even
+    const int64_t steps = s1 < 0 ? kpad / KC : s1;
     struct Stage {
         f32x4 a[4], b[4];
     };
@@ -111,21 +112,6 @@ __device__ __forceinline__ void gemm_tile_lds(const GemmDesc<float>& g, int64_t 
                 a[t][f] = *reinterpret_cast<const bf16x8*>(&lds[buf][0][t][ra][col(ra, lq)]);
                 b[t][f] = *reinterpret_cast<const bf16x8*>(&lds[buf][1][t][rb][col(rb, lq)]);
             }
-        if constexpr (TO) {
-            // term-major order: consecutive MFMAs write different accumulators (no dependent
-            // back-to-back issue); every accumulator still takes its terms in the same order
-            constexpr int NTERM = NT == 2 ? 3 : 6;
-            constexpr int ta[6] = {NT == 2 ? 1 : 2, 0, NT == 2 ? 0 : 1, 1, 0, 0};
-            constexpr int tb[6] = {0, NT == 2 ? 1 : 2, NT == 2 ? 0 : 1, 0, 1, 0};
-#pragma unroll
-            for (int u = 0; u < NTERM; ++u)
-#pragma unroll
-                for (int f = 0; f < 4; ++f)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        acc[f][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ta[u]][f], b[tb[u]][q], acc[f][q], 0, 0, 0);
-            return;
-        }
 #pragma unroll
         for (int f = 0; f < 4; ++f)
 #pragma unroll
@@ -147,10 +133,10 @@ __device__ __forceinline__ void gemm_tile_lds(const GemmDesc<float>& g, int64_t 
 
     if constexpr (DEPTH == 1) {
         Stage r;
-        gload(r, 0);
+        gload(r, s0);
         put(r);
         __syncthreads();
-        for (int64_t s = 0; s < steps; ++s) {
+        for (int64_t s = s0; s < steps; ++s) {
             gload(r, s + 1);
             compute();
             __syncthreads();
@@ -160,12 +146,12 @@ __device__ __forceinline__ void gemm_tile_lds(const GemmDesc<float>& g, int64_t 
     } else if constexpr (LDB == 2) {
         // steps is even; stage 0 holds even steps, stage 1 odd ones
         Stage r0, r1;
-        gload(r0, 0);
-        gload(r1, 1);
+        gload(r0, s0);
+        gload(r1, s0 + 1);
         put(r0, 0);
-        gload(r0, 2);
+        gload(r0, s0 + 2);
         __syncthreads();
-        for (int64_t s = 0; s < steps; s += 2) {
+        for (int64_t s = s0; s < steps; s += 2) {
             compute(0);         // step s
             put(r1, 1);         // step s + 1: stage 1 was last read before the previous barrier
             gload(r1, s + 3);
@@ -178,11 +164,11 @@ __device__ __forceinline__ void gemm_tile_lds(const GemmDesc<float>& g, int64_t 
     } else {
         // steps is even (kpad is a multiple of 64)
         Stage r0, r1;
-        gload(r0, 0);
-        gload(r1, 1);
+        gload(r0, s0);
+        gload(r1, s0 + 1);
         put(r0);
         __syncthreads();
-        for (int64_t s = 0; s < steps; s += 2) {
+        for (int64_t s = s0; s < steps; s += 2) {
             gload(r0, s + 2);   // r0 was consumed: fetch two steps ahead
             compute();          // step s
             __syncthreads();
@@ -195,11 +181,49 @@ __device__ __forceinline__ void gemm_tile_lds(const GemmDesc<float>& g, int64_t 
             __syncthreads();
         }
     }
+    if (part) {
+        // a K slice of the tile: the raw accumulators, lane-native, wave by wave
+        if (!idle) {
+            f32x4* dst = part + (int64_t)wave * 16 * 64;
+#pragma unroll
+            for (int f = 0; f < 4; ++f)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) dst[(f * 4 + q) * 64 + lane] = acc[f][q];
+        }
+        return;
+    }
     // one block row at a time: keeps the kernel within two wavefronts per SIMD, which
     // lets two work-groups per CU alternate around their barriers
     if (!idle)
         tile_epilogue<P, 4, 4, 1>(g, acc, n, ld, (int64_t)ti * BM + wm * 64, (int64_t)tj * BM + wn * 64, diag_tile,
                                   lr, lq);
+}
+
+// Sum of the K-slice partials of one tile in slice order, then the tile's epilogue (the
+// calling 256-thread work-group; wave layout as in gemm_tile_lds).
+template <int P>
+__device__ __forceinline__ void gemm_tile_lds_fix(const GemmDesc<float>& g, int64_t n, int64_t ld, int ti, int tj,
+                                                  const f32x4* part, int nslice) {
+    constexpr int BM = 128;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lr = lane & 15, lq = lane >> 4;
+    const bool diag_tile = ti == tj;
+    if (diag_tile && wm > wn) return;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[f][q] = f32x4{};
+    for (int sl = 0; sl < nslice; ++sl) {
+        const f32x4* src = part + ((int64_t)sl * 4 + wave) * 16 * 64;
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[f][q] += src[(f * 4 + q) * 64 + lane];
+    }
+    tile_epilogue<P, 4, 4, 1>(g, acc, n, ld, (int64_t)ti * BM + wm * 64, (int64_t)tj * BM + wn * 64, diag_tile, lr,
+                              lq);
 }
 
 }  // namespace

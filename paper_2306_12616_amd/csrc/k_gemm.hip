@@ -49,16 +49,17 @@ namespace {
 // (each with its own L2); with XCD = 1 the linear id is permuted so that each
 // XCD walks a contiguous stretch of the row-major upper triangle, whose tiles
 // share A row panels in that XCD's L2.
+__device__ __forceinline__ int xcd_order(int lin, int total) {
+    const int q = total / 8, r = total % 8;
+    const int x = lin % 8, slot = lin / 8;
+    return x * q + (x < r ? x : r) + slot;
+}
+
 template <int XCD>
 __device__ __forceinline__ void tile_of_block(int ntri, int& t, int& z) {
     const int gx = gridDim.x;
     int lin = (int)blockIdx.x + (int)blockIdx.z * gx;
-    if constexpr (XCD) {
-        const int total = gx * (int)gridDim.z;
-        const int q = total / 8, r = total % 8;
-        const int x = lin % 8, slot = lin / 8;
-        lin = x * q + (x < r ? x : r) + slot;
-    }
+    if constexpr (XCD) lin = xcd_order(lin, gx * (int)gridDim.z);
     t = lin % gx;
     z = lin / gx;
     (void)ntri;
@@ -91,7 +92,7 @@ hipError_t launch_cfg(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
 }
 
 // Split-bf16 products with LDS staging: 128 x 128 tiles, 2 x 2 wavefronts.
-template <int P, int XCD, int GB, int DEPTH, int PAD, int SWZ, int LDB, int IGLP, int TO>
+template <int P, int XCD, int GB, int DEPTH, int PAD, int SWZ, int LDB, int IGLP>
 __global__ void __launch_bounds__(256)
 k_gemm_lds(const GemmBatch<float> batch, int64_t n, int64_t ld, int64_t kpad, int ntile) {
     int tlin, z;
@@ -99,19 +100,87 @@ k_gemm_lds(const GemmBatch<float> batch, int64_t n, int64_t ld, int64_t kpad, in
     int ti, tj;
     if constexpr (GB > 0) blocked_tile(tlin, ntile, GB, ti, tj);
     else upper_tile(tlin, ntile, ti, tj);
-    gemm_tile_lds<P, DEPTH, PAD, SWZ, LDB, IGLP, TO>(batch.d[z], n, ld, kpad, ti, tj);
+    gemm_tile_lds<P, DEPTH, PAD, SWZ, LDB, IGLP>(batch.d[z], n, ld, kpad, ti, tj);
+}
+
+// Tail-split launches.  A grouped launch of W 128-tiles fills the chip in rounds of S
+// resident work-groups; when W exceeds a multiple of S by a little, the last round holds a
+// few tiles and takes as long as a full one.  Then the first R S tiles (linear order: product
+// z = lin / ntri, tile lin % ntri) run whole, and each of the remaining ones is cut into K
+// slices run side by side, whose partial accumulators one more launch adds in slice order
+// (fixed order: the result does not depend on scheduling) before the tile's epilogue.
+__device__ __forceinline__ void lin_tile(int lin, int ntri, int ntile, int& z, int& ti, int& tj) {
+    z = lin / ntri;
+    upper_tile(lin % ntri, ntile, ti, tj);
+}
+
+template <int P, int DEPTH, int PAD, int SWZ, int LDB, int IGLP>
+__global__ void __launch_bounds__(256)
+k_gemm_lds_main(const GemmBatch<float> batch, int64_t n, int64_t ld, int64_t kpad, int ntile, int ntri) {
+    const int lin = xcd_order((int)blockIdx.x, (int)gridDim.x);
+    int z, ti, tj;
+    lin_tile(lin, ntri, ntile, z, ti, tj);
+    gemm_tile_lds<P, DEPTH, PAD, SWZ, LDB, IGLP>(batch.d[z], n, ld, kpad, ti, tj);
+}
+
+constexpr int64_t kSlicePart = 4 * 16 * 64;   // f32x4 per K slice of one tile (64 KB)
+
+template <int P, int DEPTH, int PAD, int SWZ, int LDB, int IGLP>
+__global__ void __launch_bounds__(256)
+k_gemm_lds_slice(const GemmBatch<float> batch, int64_t n, int64_t ld, int64_t kpad, int ntile, int ntri, int lin0,
+                 int nslice, f32x4* part) {
+    const int tile = (int)blockIdx.x / nslice, sl = (int)blockIdx.x % nslice;
+    int z, ti, tj;
+    lin_tile(lin0 + tile, ntri, ntile, z, ti, tj);
+    const int64_t units = kpad / 64;   // pairs of 32-wide K steps
+    const int64_t s0 = 2 * (units * sl / nslice), s1 = 2 * (units * (sl + 1) / nslice);
+    gemm_tile_lds<P, DEPTH, PAD, SWZ, LDB, IGLP>(batch.d[z], n, ld, kpad, ti, tj, s0, s1,
+                                                 part + ((int64_t)tile * nslice + sl) * kSlicePart);
+}
+
+template <int P>
+__global__ void __launch_bounds__(256)
+k_gemm_lds_fix(const GemmBatch<float> batch, int64_t n, int64_t ld, int ntile, int ntri, int lin0, int nslice,
+               const f32x4* part) {
+    const int tile = (int)blockIdx.x;
+    int z, ti, tj;
+    lin_tile(lin0 + tile, ntri, ntile, z, ti, tj);
+    gemm_tile_lds_fix<P>(batch.d[z], n, ld, ti, tj, part + (int64_t)tile * nslice * kSlicePart, nslice);
 }
 
 // LDS layout: unpadded 64-byte rows with the 16-byte chunks of row r XOR-swizzled by
 // (r >> 1) & 3 (measured: 522 -> 570 TFLOP/s of bf16 work at N = 4000 against 8-element padding)
-template <int P, int XCD, int GB, int DEPTH = 2, int PAD = 0, int SWZ = 1, int LDB = 1, int IGLP = -1, int TO = 0>
-hipError_t launch_lds(const GemmBatch<float>& b, int64_t n, int64_t ld, hipStream_t st) {
+// Resident work-groups of the LDS kernel: two per CU (two wavefronts per SIMD, <= 80 KB of LDS).
+constexpr int kLdsSlots = 2 * 256;
+
+template <int P, int XCD, int GB, int DEPTH = 2, int PAD = 0, int SWZ = 1, int LDB = 1, int IGLP = -1>
+hipError_t launch_lds(const GemmBatch<float>& b, int64_t n, int64_t ld, hipStream_t st, f32x4* scratch = nullptr,
+                      int64_t scratch_vec = 0) {
     const int64_t kpad = (n + 63) / 64 * 64;
     const int ntile = (int)((n + 127) / 128);
     if (kpad > ld || (int64_t)ntile * 128 > ld) return hipErrorInvalidValue;
-    dim3 grid((unsigned)(ntile * (ntile + 1) / 2), 1, (unsigned)b.count);
-    hipLaunchKernelGGL((k_gemm_lds<P, XCD, GB, DEPTH, PAD, SWZ, LDB, IGLP, TO>), grid, dim3(256), 0, st, b, n, ld,
-                       kpad, ntile);
+    const int ntri = ntile * (ntile + 1) / 2;
+    const int total = ntri * b.count;
+    const int rounds = total / kLdsSlots, rest = total % kLdsSlots;
+    // tail split: a last round under a quarter full, at least 8 K-step pairs per slice
+    int nslice = rest > 0 ? kLdsSlots / rest : 0;
+    if (nslice > 16) nslice = 16;
+    if (nslice > kpad / 64 / 8) nslice = (int)(kpad / 64 / 8);
+    const bool split = rounds >= 1 && rest > 0 && rest * 4 <= kLdsSlots && nslice >= 2 && scratch &&
+                       (int64_t)rest * nslice * kSlicePart <= scratch_vec;
+    if (!split) {
+        dim3 grid((unsigned)ntri, 1, (unsigned)b.count);
+        hipLaunchKernelGGL((k_gemm_lds<P, XCD, GB, DEPTH, PAD, SWZ, LDB, IGLP>), grid, dim3(256), 0, st, b, n, ld,
+                           kpad, ntile);
+        return hipGetLastError();
+    }
+    const int nmain = rounds * kLdsSlots;
+    hipLaunchKernelGGL((k_gemm_lds_main<P, DEPTH, PAD, SWZ, LDB, IGLP>), dim3((unsigned)nmain), dim3(256), 0, st, b, n,
+                       ld, kpad, ntile, ntri);
+    hipLaunchKernelGGL((k_gemm_lds_slice<P, DEPTH, PAD, SWZ, LDB, IGLP>), dim3((unsigned)(rest * nslice)), dim3(256),
+                       0, st, b, n, ld, kpad, ntile, ntri, nmain, nslice, scratch);
+    hipLaunchKernelGGL((k_gemm_lds_fix<P>), dim3((unsigned)rest), dim3(256), 0, st, b, n, ld, ntile, ntri, nmain, nslice,
+                       (const f32x4*)scratch);
     return hipGetLastError();
 }
 
@@ -127,7 +196,8 @@ hipError_t launch_lds(const GemmBatch<float>& b, int64_t n, int64_t ld, hipStrea
 // products 28 -> 42 (48-tiles); N = 2000 single 28 -> 45 (48-tiles); N = 4000: 64-tiles.
 // 48-tiles need ceil(n/48)*48 <= ld; otherwise 64-tiles are used.
 template <int P>
-hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int64_t ld, hipStream_t st) {
+hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int64_t ld, hipStream_t st,
+                      f32x4* scratch = nullptr, int64_t scratch_vec = 0) {
     if (b.count <= 0) return hipSuccess;
     if (b.count > kMaxGroup || ld % 128 != 0) return hipErrorInvalidValue;
     constexpr int KU = P == P_F64 ? 4 : (P == P_F32 ? 8 : 16);
@@ -154,9 +224,9 @@ hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
         // would take 96 KB of LDS, one work-group per CU), 742 -> 754.
         const int64_t t128 = (n + 127) / 128, w128 = t128 * (t128 + 1) / 2 * b.count;
         if constexpr (P == P_BF16X3) {
-            if (w128 >= 100) return launch_lds<P, 1, 0, 2, 0, 1, 2, 0>(b, n, ld, st);
+            if (w128 >= 100) return launch_lds<P, 1, 0, 2, 0, 1, 2, 0>(b, n, ld, st, scratch, scratch_vec);
         } else {
-            if (w128 >= 100 && b.count >= 2) return launch_lds<P, 1, 0, 2, 0, 1, 1, 0>(b, n, ld, st);
+            if (w128 >= 100 && b.count >= 2) return launch_lds<P, 1, 0, 2, 0, 1, 1, 0>(b, n, ld, st, scratch, scratch_vec);
         }
         if (w64 < 300) return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st);
         return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st);
@@ -169,9 +239,12 @@ hipError_t launch_gemm_f64(const GemmBatch<double>& b, int64_t n, int64_t ld, hi
     return launch_any<P_F64>(b, n, ld, st);
 }
 
-hipError_t launch_gemm_f32(const GemmBatch<float>& b, int64_t n, int64_t ld, int split, hipStream_t st) {
-    if (split == 2) return launch_any<P_BF16X6>(b, n, ld, st);
-    if (split == 1) return launch_any<P_BF16X3>(b, n, ld, st);
+hipError_t launch_gemm_f32(const GemmBatch<float>& b, int64_t n, int64_t ld, int split, hipStream_t st,
+                           void* scratch, size_t scratch_bytes) {
+    f32x4* s = static_cast<f32x4*>(scratch);
+    const int64_t sv = (int64_t)(scratch_bytes / sizeof(f32x4));
+    if (split == 2) return launch_any<P_BF16X6>(b, n, ld, st, s, sv);
+    if (split == 1) return launch_any<P_BF16X3>(b, n, ld, st, s, sv);
     return launch_any<P_F32>(b, n, ld, st);
 }
 
