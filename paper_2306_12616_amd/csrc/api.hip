@@ -282,11 +282,12 @@ int resolve_bounds(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, do
     return 0;
 }
 
-// Library's choice between one and two giant-step chains.  Measured (mu search + D, order 512,
-// DM/s one -> two chains): N = 1000 float64 405 -> 412, float32 417 -> 433, split-bf16 354 -> 384;
-// N = 2000 float64 82.5 -> 82.7, float32 107.1 -> 106.0, split-bf16 162 -> 177; N = 4000
-// float64 13.51 -> 13.53, float32 27.00 -> 26.93, split-bf16 43.0 -> 44.9.
-bool two_chains_pay(const Plan& pl) { return !(pl.prec == CHEBDM_FP32 && pl.n >= 1500); }
+// Library's choice between one and two giant-step chains: two wherever they can be used.
+// Measured (mu search + D, order 512, DM/s one -> two chains): N = 1000 float64 407 -> 414,
+// float32 420 -> 436, split-bf16 356 -> 386; N = 2000 float64 82.6 -> 82.8, float32 107.8 ->
+// 111.2, split-bf16 164 -> 179; N = 4000 float64 13.70 -> 13.70, float32 27.12 -> 27.04,
+// split-bf16 48.5 -> 49.6.
+bool two_chains_pay(const Plan& pl) { return pl.n > 0; }
 
 int plan_quadrature(Plan& pl, double beta, double emin, double emax) {
     const double beta_s = beta * 0.5 * (emax - emin);

@@ -211,7 +211,9 @@ hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
         if (w64 < 400) return launch_cfg<P, 64, 1, 1, KU, 1, 4>(b, n, ld, st);
         return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st);
     } else if constexpr (P == P_F32) {
-        if (fits48 && w64 < 1800) return launch_cfg<P, 48, 1, 1, KU, 1, 2>(b, n, ld, st);
+        // N = 2000, two products (w64 = 1056): 64-tiles split 2 ways 70 TFLOP/s against 61 for
+        // 48-tiles split 2 ways
+        if (fits48 && w64 < 1000) return launch_cfg<P, 48, 1, 1, KU, 1, 2>(b, n, ld, st);
         if (w64 < 1800 || n <= 2500) return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st);
         return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st);
     } else {
