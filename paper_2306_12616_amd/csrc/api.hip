@@ -157,8 +157,8 @@ int ensure_mats(chebdm_handle h, const Plan& pl, int64_t count) {
         h->mats_bytes = bytes;
         h->lay_ld = -1;
     }
-    // split-bf16 products: partial accumulators of K-sliced tail tiles
-    if ((pl.prec == CHEBDM_BF16X3 || pl.prec == CHEBDM_BF16X6) && !h->gemm_scratch) {
+    // partial accumulators of K-sliced tail tiles of the products
+    if (!h->gemm_scratch) {
         if (hipMalloc(&h->gemm_scratch, kGemmScratchBytes) != hipSuccess) {
             h->gemm_scratch = nullptr;
             (void)hipGetLastError();
@@ -340,7 +340,8 @@ struct Chain {
         size_t ev;
         CHECK(prof_begin(h, PROF_GEMM, cnt, cnt * sym_product_flop(pl.n), 0.0, &ev));
         hipError_t e = hipSuccess;
-        if (pl.elem == 8) e = launch_gemm_f64(b64, pl.n, pl.ld, h->stream);
+        if (pl.elem == 8) e = launch_gemm_f64(b64, pl.n, pl.ld, h->stream, h->gemm_scratch,
+                                              h->gemm_scratch ? kGemmScratchBytes : 0);
         else e = launch_gemm_f32(b32, pl.n, pl.ld,
                                  pl.prec == CHEBDM_BF16X6 ? 2 : (pl.prec == CHEBDM_BF16X3 ? 1 : 0), h->stream,
                                  h->gemm_scratch, h->gemm_scratch ? kGemmScratchBytes : 0);
@@ -976,7 +977,7 @@ int chebdm_workspace_size(chebdm_handle h, int64_t n, int32_t order, const chebd
     const int64_t M = opts && opts->n_quad > 0 ? opts->n_quad : (int64_t)1 << 16;
     const int64_t slots = pl.k + pl.m + (pl.form == CHEBDM_GIANT_COMPOSITION && pl.m >= 4 ? 1 : 0);
     *bytes = (size_t)slots * (size_t)ld * (size_t)ld * pl.elem + small_bytes_for(M);
-    if (pl.prec == CHEBDM_BF16X3 || pl.prec == CHEBDM_BF16X6) *bytes += kGemmScratchBytes;
+    *bytes += kGemmScratchBytes;
     return CHEBDM_OK;
 }
 

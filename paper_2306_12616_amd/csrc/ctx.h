@@ -48,7 +48,7 @@ struct chebdm_ctx {
     };
     hipStream_t cap = nullptr;   // capture stream
     Replay replay[4];            // mu search with D, mu search without D, density, Lanczos bounds
-    // partial accumulators of K-sliced tail tiles (split-bf16 products), kGemmScratchBytes
+    // partial accumulators of K-sliced tail tiles of the products, kGemmScratchBytes
     void* gemm_scratch = nullptr;
     // Lanczos bounds workspace (basis, work vectors, partials, tridiagonal)
     double* lz = nullptr;

@@ -285,9 +285,13 @@ __device__ __forceinline__ void tile_epilogue(const GemmDesc<typename Traits<P>:
 // ranges in units of two chunks) whose partial sums are added through LDS in
 // a fixed order (deterministic) before the epilogue.  With SK > 1 the routine
 // ends in a work-group barrier, so every thread of the work-group must call it.
+// k_lo, k_hi (multiples of 2 CH; k_hi < 0: kpad): the K range of this call.  part != null:
+// instead of the epilogue, the work-group's summed accumulators are stored there, lane-native,
+// wave tile by wave tile (a K slice of a tile, added up later by gemm_tile_fix).
 template <int P, int BM, int WGM, int WGN, int KU, int SK = 1, int RB = 16>
 __device__ __forceinline__ void gemm_tile(const GemmDesc<typename Traits<P>::T>& g, int64_t n, int64_t ld,
-                                          int64_t kpad, int ti, int tj) {
+                                          int64_t kpad, int ti, int tj, int64_t k_lo = 0, int64_t k_hi = -1,
+                                          typename Traits<P>::Acc* part = nullptr) {
     using T = typename Traits<P>::T;
     using Acc = typename Traits<P>::Acc;
     constexpr int CH = 4 * KU;                 // k per chunk
@@ -326,11 +330,12 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<typename Traits<P>::T>&
     // 2 CH, and the loads past the end are clamped to the last chunks (their
     // values are never used).  Straight-line code lets the compiler wait only
     // for the chunk being consumed while the next one is in flight.
-    int64_t kbeg = 0, kend = kpad;
+    if (k_hi < 0) k_hi = kpad;
+    int64_t kbeg = k_lo, kend = k_hi;
     if constexpr (SK > 1) {
-        const int64_t units = kpad / (2 * CH);
-        kbeg = units * ks / SK * (2 * CH);
-        kend = units * (ks + 1) / SK * (2 * CH);
+        const int64_t units = (k_hi - k_lo) / (2 * CH);
+        kbeg = k_lo + units * ks / SK * (2 * CH);
+        kend = k_lo + units * (ks + 1) / SK * (2 * CH);
     }
     if (kend > kbeg) {
         load(a0, b0, kbeg);
@@ -363,7 +368,48 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<typename Traits<P>::T>&
                 for (int q = 0; q < FN; ++q) acc[f][q] += red[j][wave][f * FN + q][lane];
     }
 
+    if (part) {
+        Acc* dst = part + (int64_t)wave * FM * FN * 64;
+#pragma unroll
+        for (int f = 0; f < FM; ++f)
+#pragma unroll
+            for (int q = 0; q < FN; ++q) dst[(f * FN + q) * 64 + lane] = acc[f][q];
+        return;
+    }
     tile_epilogue<P, FM, FN, (RB < FM ? RB : FM)>(g, acc, n, ld, row0, col0, diag_tile, lr, lq);
+}
+
+// Accumulators of one BM x BM tile per K slice (WGM x WGN wave tiles).
+template <int P, int BM, int WGM, int WGN>
+constexpr int64_t slice_accs() {
+    return (int64_t)WGM * WGN * (BM / WGM / 16) * (BM / WGN / 16) * 64;
+}
+
+// Sum of the nslice K-slice partials of tile (ti, tj) in slice order, then its epilogue, by the
+// WGM x WGN wavefronts of the calling work-group.
+template <int P, int BM, int WGM, int WGN, int RB = 16>
+__device__ __forceinline__ void gemm_tile_fix(const GemmDesc<typename Traits<P>::T>& g, int64_t n, int64_t ld,
+                                              int ti, int tj, const typename Traits<P>::Acc* part, int nslice) {
+    using Acc = typename Traits<P>::Acc;
+    constexpr int WTM = BM / WGM, WTN = BM / WGN;
+    constexpr int FM = WTM / 16, FN = WTN / 16;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wm = wave / WGN, wn = wave % WGN;
+    const int lr = lane & 15, lq = lane >> 4;
+    Acc acc[FM][FN];
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int q = 0; q < FN; ++q) acc[f][q] = Acc{};
+    for (int sl = 0; sl < nslice; ++sl) {
+        const Acc* src = part + (int64_t)sl * slice_accs<P, BM, WGM, WGN>() + (int64_t)wave * FM * FN * 64;
+#pragma unroll
+        for (int f = 0; f < FM; ++f)
+#pragma unroll
+            for (int q = 0; q < FN; ++q) acc[f][q] += src[(f * FN + q) * 64 + lane];
+    }
+    tile_epilogue<P, FM, FN, (RB < FM ? RB : FM)>(g, acc, n, ld, (int64_t)ti * BM + wm * WTM, (int64_t)tj * BM + wn * WTN,
+                                                  ti == tj, lr, lq);
 }
 
 

@@ -116,10 +116,12 @@ hipError_t launch_gram(const T* const* lmats, int nl, const T* const* tmats, int
                        double* partial, int64_t partial_cap, double* G, hipStream_t st);
 
 // ---- matrix products (k_gemm.hip)
-hipError_t launch_gemm_f64(const GemmBatch<double>& b, int64_t n, int64_t ld, hipStream_t st);
-// split: 0 float32 MFMA, 1 bf16x3, 2 bf16x6.  scratch (nullable, kGemmScratchBytes is enough):
-// partial accumulators of K-sliced tail tiles of the split-bf16 LDS kernel
+// scratch (nullable; kGemmScratchBytes is enough): partial accumulators of the K-sliced tiles
+// of a launch's last, nearly empty round (without scratch the launch runs unsplit)
 constexpr size_t kGemmScratchBytes = (size_t)32 << 20;
+hipError_t launch_gemm_f64(const GemmBatch<double>& b, int64_t n, int64_t ld, hipStream_t st,
+                           void* scratch = nullptr, size_t scratch_bytes = 0);
+// split: 0 float32 MFMA, 1 bf16x3, 2 bf16x6
 hipError_t launch_gemm_f32(const GemmBatch<float>& b, int64_t n, int64_t ld, int split, hipStream_t st,
                            void* scratch = nullptr, size_t scratch_bytes = 0);
 

@@ -65,6 +65,12 @@ __device__ __forceinline__ void tile_of_block(int ntri, int& t, int& z) {
     (void)ntri;
 }
 
+// Linear tile lin of a grouped launch: product lin / ntri, upper-triangle tile lin % ntri.
+__device__ __forceinline__ void lin_tile(int lin, int ntri, int ntile, int& z, int& ti, int& tj) {
+    z = lin / ntri;
+    upper_tile(lin % ntri, ntile, ti, tj);
+}
+
 // BM x BM workgroup tiles, blockIdx.x enumerating the upper triangle, blockIdx.z
 // the products of a grouped launch.
 // GB > 0: tiles in blocked_tile order with GB x GB super-blocks; 0: row-major.
@@ -79,15 +85,77 @@ k_gemm(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, int6
     gemm_tile<P, BM, WGM, WGN, KU, SK, RB>(batch.d[z], n, ld, kpad, ti, tj);
 }
 
-template <int P, int BM, int WGM, int WGN, int KU, int XCD, int SK = 1, int GB = 0, int RB = 16>
-hipError_t launch_cfg(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int64_t ld, hipStream_t st) {
+// Tail split of the register-tile launches (the scheme of the LDS kernel below): full rounds of
+// resident work-groups run whole, the few tiles left over run as K slices side by side, and a
+// fix-up launch adds the slices in slice order and runs their epilogues.
+template <int P, int BM, int WGM, int WGN, int KU, int SK, int RB>
+__global__ void __launch_bounds__(64 * WGM * WGN * SK)
+k_gemm_main(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, int64_t kpad, int ntile, int ntri) {
+    const int lin = xcd_order((int)blockIdx.x, (int)gridDim.x);
+    int z, ti, tj;
+    lin_tile(lin, ntri, ntile, z, ti, tj);
+    gemm_tile<P, BM, WGM, WGN, KU, SK, RB>(batch.d[z], n, ld, kpad, ti, tj);
+}
+
+template <int P, int BM, int WGM, int WGN, int KU, int SK, int RB>
+__global__ void __launch_bounds__(64 * WGM * WGN * SK)
+k_gemm_slice(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, int64_t kpad, int ntile, int ntri,
+             int lin0, int nslice, typename Traits<P>::Acc* part) {
+    constexpr int CH = 4 * KU;
+    const int tile = (int)blockIdx.x / nslice, sl = (int)blockIdx.x % nslice;
+    int z, ti, tj;
+    lin_tile(lin0 + tile, ntri, ntile, z, ti, tj);
+    const int64_t units = kpad / (2 * CH);
+    const int64_t k_lo = 2 * CH * (units * sl / nslice), k_hi = 2 * CH * (units * (sl + 1) / nslice);
+    gemm_tile<P, BM, WGM, WGN, KU, SK, RB>(batch.d[z], n, ld, kpad, ti, tj, k_lo, k_hi,
+                                          part + ((int64_t)tile * nslice + sl) * slice_accs<P, BM, WGM, WGN>());
+}
+
+template <int P, int BM, int WGM, int WGN, int RB>
+__global__ void __launch_bounds__(64 * WGM * WGN)
+k_gemm_fix(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, int ntile, int ntri, int lin0,
+           int nslice, const typename Traits<P>::Acc* part) {
+    const int tile = (int)blockIdx.x;
+    int z, ti, tj;
+    lin_tile(lin0 + tile, ntri, ntile, z, ti, tj);
+    gemm_tile_fix<P, BM, WGM, WGN, RB>(batch.d[z], n, ld, ti, tj,
+                                       part + (int64_t)tile * nslice * slice_accs<P, BM, WGM, WGN>(), nslice);
+}
+
+// OCC: wavefronts per SIMD the kernel holds (from its register use); the chip's 1024 SIMDs then
+// keep 1024 OCC / (WGM WGN SK) work-groups resident.
+template <int P, int BM, int WGM, int WGN, int KU, int XCD, int SK = 1, int GB = 0, int RB = 16, int OCC = 1>
+hipError_t launch_cfg(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int64_t ld, hipStream_t st,
+                      void* scratch = nullptr, size_t scratch_bytes = 0) {
+    using Acc = typename Traits<P>::Acc;
     constexpr int CH = 4 * KU;
     const int64_t kpad = (n + 2 * CH - 1) / (2 * CH) * (2 * CH);
     if (kpad > ld || (n + BM - 1) / BM * BM > ld) return hipErrorInvalidValue;
     const int ntile = (int)((n + BM - 1) / BM);
-    dim3 grid((unsigned)(ntile * (ntile + 1) / 2), 1, (unsigned)b.count);
-    hipLaunchKernelGGL((k_gemm<P, BM, WGM, WGN, KU, XCD, SK, GB, RB>), grid, dim3(64 * WGM * WGN * SK), 0, st, b,
-                       n, ld, kpad, ntile);
+    const int ntri = ntile * (ntile + 1) / 2, total = ntri * b.count;
+    const int slots = 1024 * OCC / (WGM * WGN * SK);
+    const int rounds = total / slots, rest = total % slots;
+    const int64_t units = kpad / (2 * CH);
+    int nslice = rest > 0 ? slots / rest : 0;
+    if (nslice > 16) nslice = 16;
+    if (nslice > units / (8 * SK)) nslice = (int)(units / (8 * SK));
+    const int64_t need = (int64_t)rest * nslice * slice_accs<P, BM, WGM, WGN>() * (int64_t)sizeof(Acc);
+    const bool split = rounds >= 1 && rest > 0 && rest * 4 <= slots && nslice >= 2 && scratch &&
+                       need <= (int64_t)scratch_bytes;
+    if (!split) {
+        dim3 grid((unsigned)ntri, 1, (unsigned)b.count);
+        hipLaunchKernelGGL((k_gemm<P, BM, WGM, WGN, KU, XCD, SK, GB, RB>), grid, dim3(64 * WGM * WGN * SK), 0, st, b,
+                           n, ld, kpad, ntile);
+        return hipGetLastError();
+    }
+    Acc* part = static_cast<Acc*>(scratch);
+    const int nmain = rounds * slots;
+    hipLaunchKernelGGL((k_gemm_main<P, BM, WGM, WGN, KU, SK, RB>), dim3((unsigned)nmain), dim3(64 * WGM * WGN * SK), 0,
+                       st, b, n, ld, kpad, ntile, ntri);
+    hipLaunchKernelGGL((k_gemm_slice<P, BM, WGM, WGN, KU, SK, RB>), dim3((unsigned)(rest * nslice)),
+                       dim3(64 * WGM * WGN * SK), 0, st, b, n, ld, kpad, ntile, ntri, nmain, nslice, part);
+    hipLaunchKernelGGL((k_gemm_fix<P, BM, WGM, WGN, RB>), dim3((unsigned)rest), dim3(64 * WGM * WGN), 0, st, b, n, ld,
+                       ntile, ntri, nmain, nslice, (const Acc*)part);
     return hipGetLastError();
 }
 
@@ -109,11 +177,6 @@ k_gemm_lds(const GemmBatch<float> batch, int64_t n, int64_t ld, int64_t kpad, in
 // z = lin / ntri, tile lin % ntri) run whole, and each of the remaining ones is cut into K
 // slices run side by side, whose partial accumulators one more launch adds in slice order
 // (fixed order: the result does not depend on scheduling) before the tile's epilogue.
-__device__ __forceinline__ void lin_tile(int lin, int ntri, int ntile, int& z, int& ti, int& tj) {
-    z = lin / ntri;
-    upper_tile(lin % ntri, ntile, ti, tj);
-}
-
 template <int P, int DEPTH, int PAD, int SWZ, int LDB, int IGLP>
 __global__ void __launch_bounds__(256)
 k_gemm_lds_main(const GemmBatch<float> batch, int64_t n, int64_t ld, int64_t kpad, int ntile, int ntri) {
@@ -197,25 +260,28 @@ hipError_t launch_lds(const GemmBatch<float>& b, int64_t n, int64_t ld, hipStrea
 // 48-tiles need ceil(n/48)*48 <= ld; otherwise 64-tiles are used.
 template <int P>
 hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int64_t ld, hipStream_t st,
-                      f32x4* scratch = nullptr, int64_t scratch_vec = 0) {
+                      void* scratch = nullptr, size_t scratch_bytes = 0) {
     if (b.count <= 0) return hipSuccess;
     if (b.count > kMaxGroup || ld % 128 != 0) return hipErrorInvalidValue;
     constexpr int KU = P == P_F64 ? 4 : (P == P_F32 ? 8 : 16);
     const int64_t t64 = (n + 63) / 64;
     const int64_t w64 = t64 * (t64 + 1) / 2 * b.count;
     const bool fits48 = (n + 47) / 48 * 48 <= ld;
+    // With at least one full round of 64-tiles (w64 >= 1024) the unsplit 64-tile kernel with the
+    // tail split wins (N = 2000, TFLOP/s, two / four / eight products: float64 48.8 / 53.1 / 55.7
+    // against 46.3 / 46.6 / 51.7 for 48-tiles; float32 82.6 / 96.7 / 106.7 against 61.6 / 58.0 /
+    // 60.9); below it the smaller 48-tiles fill the chip better (float64 N = 2000 single: 40.0
+    // against 38.4 for split 64-tiles; N = 1000: 48-tiles, K split 4 ways up to 300 64-tiles).
     if constexpr (P == P_F64) {
-        if (fits48 && w64 < 300) return launch_cfg<P, 48, 1, 1, KU, 1, 4>(b, n, ld, st);
-        if (fits48 && w64 < 1800) return launch_cfg<P, 48, 1, 1, KU, 1, 1>(b, n, ld, st);
-        if (w64 >= 1800 && n <= 2500) return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st);
-        if (w64 < 400) return launch_cfg<P, 64, 1, 1, KU, 1, 4>(b, n, ld, st);
-        return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st);
+        if (w64 >= 1024 && n >= 1500) return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st, scratch, scratch_bytes);
+        if (fits48 && w64 < 300) return launch_cfg<P, 48, 1, 1, KU, 1, 4>(b, n, ld, st, scratch, scratch_bytes);
+        if (fits48) return launch_cfg<P, 48, 1, 1, KU, 1, 1>(b, n, ld, st, scratch, scratch_bytes);
+        if (w64 < 400) return launch_cfg<P, 64, 1, 1, KU, 1, 4>(b, n, ld, st, scratch, scratch_bytes);
+        return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st, scratch, scratch_bytes);
     } else if constexpr (P == P_F32) {
-        // N = 2000, two products (w64 = 1056): 64-tiles split 2 ways 70 TFLOP/s against 61 for
-        // 48-tiles split 2 ways
-        if (fits48 && w64 < 1000) return launch_cfg<P, 48, 1, 1, KU, 1, 2>(b, n, ld, st);
-        if (w64 < 1800 || n <= 2500) return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st);
-        return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st);
+        if (w64 >= 1024) return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st, scratch, scratch_bytes);
+        if (fits48) return launch_cfg<P, 48, 1, 1, KU, 1, 2, 0, 16, 2>(b, n, ld, st, scratch, scratch_bytes);
+        return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st, scratch, scratch_bytes);
     } else {
         // LDS staging (each element split once per work-group, panels two K steps ahead) once
         // there are >= 100 128-tiles: three-term split at N = 4000 390 -> 563 TFLOP/s of bf16
@@ -226,28 +292,27 @@ hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
         // would take 96 KB of LDS, one work-group per CU), 742 -> 754.
         const int64_t t128 = (n + 127) / 128, w128 = t128 * (t128 + 1) / 2 * b.count;
         if constexpr (P == P_BF16X3) {
-            if (w128 >= 100) return launch_lds<P, 1, 0, 2, 0, 1, 2, 0>(b, n, ld, st, scratch, scratch_vec);
+            if (w128 >= 100) return launch_lds<P, 1, 0, 2, 0, 1, 2, 0>(b, n, ld, st, static_cast<f32x4*>(scratch), (int64_t)(scratch_bytes / sizeof(f32x4)));
         } else {
-            if (w128 >= 100 && b.count >= 2) return launch_lds<P, 1, 0, 2, 0, 1, 1, 0>(b, n, ld, st, scratch, scratch_vec);
+            if (w128 >= 100 && b.count >= 2) return launch_lds<P, 1, 0, 2, 0, 1, 1, 0>(b, n, ld, st, static_cast<f32x4*>(scratch), (int64_t)(scratch_bytes / sizeof(f32x4)));
         }
-        if (w64 < 300) return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st);
-        return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st);
+        if (w64 < 300) return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st, scratch, scratch_bytes);
+        return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st, scratch, scratch_bytes);
     }
 }
 
 }  // namespace
 
-hipError_t launch_gemm_f64(const GemmBatch<double>& b, int64_t n, int64_t ld, hipStream_t st) {
-    return launch_any<P_F64>(b, n, ld, st);
+hipError_t launch_gemm_f64(const GemmBatch<double>& b, int64_t n, int64_t ld, hipStream_t st, void* scratch,
+                           size_t scratch_bytes) {
+    return launch_any<P_F64>(b, n, ld, st, scratch, scratch_bytes);
 }
 
 hipError_t launch_gemm_f32(const GemmBatch<float>& b, int64_t n, int64_t ld, int split, hipStream_t st,
                            void* scratch, size_t scratch_bytes) {
-    f32x4* s = static_cast<f32x4*>(scratch);
-    const int64_t sv = (int64_t)(scratch_bytes / sizeof(f32x4));
-    if (split == 2) return launch_any<P_BF16X6>(b, n, ld, st, s, sv);
-    if (split == 1) return launch_any<P_BF16X3>(b, n, ld, st, s, sv);
-    return launch_any<P_F32>(b, n, ld, st);
+    if (split == 2) return launch_any<P_BF16X6>(b, n, ld, st, scratch, scratch_bytes);
+    if (split == 1) return launch_any<P_BF16X3>(b, n, ld, st, scratch, scratch_bytes);
+    return launch_any<P_F32>(b, n, ld, st, scratch, scratch_bytes);
 }
 
 }  // namespace chebdm
