@@ -199,13 +199,13 @@ __device__ __forceinline__ void gemm_tile_lds(const GemmDesc<float>& g, int64_t 
                                   lr, lq);
 }
 
-// Sum of the K-slice partials of one tile in slice order, then the tile's epilogue (the
-// calling 256-thread work-group; wave layout as in gemm_tile_lds).
+// Sum of the K-slice partials of one 64 x 64 wave tile (wave 0..3 of the 2 x 2 layout of
+// gemm_tile_lds) in slice order, then its epilogue, by the calling wavefront.
 template <int P>
 __device__ __forceinline__ void gemm_tile_lds_fix(const GemmDesc<float>& g, int64_t n, int64_t ld, int ti, int tj,
-                                                  const f32x4* part, int nslice) {
+                                                  const f32x4* part, int nslice, int wave) {
     constexpr int BM = 128;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lane = threadIdx.x & 63;
     const int wm = wave >> 1, wn = wave & 1;
     const int lr = lane & 15, lq = lane >> 4;
     const bool diag_tile = ti == tj;
@@ -215,12 +215,18 @@ __device__ __forceinline__ void gemm_tile_lds_fix(const GemmDesc<float>& g, int6
     for (int f = 0; f < 4; ++f)
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[f][q] = f32x4{};
+#pragma unroll 4
     for (int sl = 0; sl < nslice; ++sl) {
         const f32x4* src = part + ((int64_t)sl * 4 + wave) * 16 * 64;
+        f32x4 v[4][4];
 #pragma unroll
         for (int f = 0; f < 4; ++f)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[f][q] += src[(f * 4 + q) * 64 + lane];
+            for (int q = 0; q < 4; ++q) v[f][q] = src[(f * 4 + q) * 64 + lane];
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[f][q] += v[f][q];
     }
     tile_epilogue<P, 4, 4, 1>(g, acc, n, ld, (int64_t)ti * BM + wm * 64, (int64_t)tj * BM + wn * 64, diag_tile, lr,
                               lq);

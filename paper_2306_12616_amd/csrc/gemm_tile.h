@@ -401,12 +401,18 @@ __device__ __forceinline__ void gemm_tile_fix(const GemmDesc<typename Traits<P>:
     for (int f = 0; f < FM; ++f)
 #pragma unroll
         for (int q = 0; q < FN; ++q) acc[f][q] = Acc{};
+#pragma unroll 2
     for (int sl = 0; sl < nslice; ++sl) {
         const Acc* src = part + (int64_t)sl * slice_accs<P, BM, WGM, WGN>() + (int64_t)wave * FM * FN * 64;
+        Acc v[FM][FN];
 #pragma unroll
         for (int f = 0; f < FM; ++f)
 #pragma unroll
-            for (int q = 0; q < FN; ++q) acc[f][q] += src[(f * FN + q) * 64 + lane];
+            for (int q = 0; q < FN; ++q) v[f][q] = src[(f * FN + q) * 64 + lane];
+#pragma unroll
+        for (int f = 0; f < FM; ++f)
+#pragma unroll
+            for (int q = 0; q < FN; ++q) acc[f][q] += v[f][q];
     }
     tile_epilogue<P, FM, FN, (RB < FM ? RB : FM)>(g, acc, n, ld, (int64_t)ti * BM + wm * WTM, (int64_t)tj * BM + wn * WTN,
                                                   ti == tj, lr, lq);

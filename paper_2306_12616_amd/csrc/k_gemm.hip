@@ -201,14 +201,15 @@ k_gemm_lds_slice(const GemmBatch<float> batch, int64_t n, int64_t ld, int64_t kp
                                                  part + ((int64_t)tile * nslice + sl) * kSlicePart);
 }
 
+// one 64-thread work-group per wave tile: four times the work-groups of one per tile
 template <int P>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64)
 k_gemm_lds_fix(const GemmBatch<float> batch, int64_t n, int64_t ld, int ntile, int ntri, int lin0, int nslice,
                const f32x4* part) {
-    const int tile = (int)blockIdx.x;
+    const int tile = (int)blockIdx.x >> 2, wave = (int)blockIdx.x & 3;
     int z, ti, tj;
     lin_tile(lin0 + tile, ntri, ntile, z, ti, tj);
-    gemm_tile_lds_fix<P>(batch.d[z], n, ld, ti, tj, part + (int64_t)tile * nslice * kSlicePart, nslice);
+    gemm_tile_lds_fix<P>(batch.d[z], n, ld, ti, tj, part + (int64_t)tile * nslice * kSlicePart, nslice, wave);
 }
 
 // LDS layout: unpadded 64-byte rows with the 16-byte chunks of row r XOR-swizzled by
@@ -242,8 +243,8 @@ hipError_t launch_lds(const GemmBatch<float>& b, int64_t n, int64_t ld, hipStrea
                        ld, kpad, ntile, ntri);
     hipLaunchKernelGGL((k_gemm_lds_slice<P, DEPTH, PAD, SWZ, LDB, IGLP>), dim3((unsigned)(rest * nslice)), dim3(256),
                        0, st, b, n, ld, kpad, ntile, ntri, nmain, nslice, scratch);
-    hipLaunchKernelGGL((k_gemm_lds_fix<P>), dim3((unsigned)rest), dim3(256), 0, st, b, n, ld, ntile, ntri, nmain, nslice,
-                       (const f32x4*)scratch);
+    hipLaunchKernelGGL((k_gemm_lds_fix<P>), dim3((unsigned)(rest * 4)), dim3(64), 0, st, b, n, ld, ntile, ntri, nmain,
+                       nslice, (const f32x4*)scratch);
     return hipGetLastError();
 }
 
