@@ -286,16 +286,18 @@ hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
     } else {
         // LDS staging (each element split once per work-group, panels two K steps ahead) once
         // there are >= 100 128-tiles: three-term split at N = 4000 390 -> 563 TFLOP/s of bf16
-        // work, N = 2000 four products 289 -> 532; the six-term split gains only with several
-        // products per launch (N = 2000, four: 498 -> 688; N = 4000 single: 749 vs 709).
-        // Three-term: two LDS stages (one barrier per K step) and the compiler's MFMA/LDS
-        // interleave (iglp 0), 591 -> 617 at N = 4000; six-term: interleave only (two stages
-        // would take 96 KB of LDS, one work-group per CU), 742 -> 754.
+        // work, N = 2000 four products 289 -> 532.  Three-term: two LDS stages (one barrier per
+        // K step) and the compiler's MFMA/LDS interleave (iglp 0), 591 -> 617 at N = 4000;
+        // six-term: interleave only (two stages would take 96 KB of LDS, one work-group per
+        // CU), 742 -> 754.  With the tail split the six-term LDS kernel also wins for single
+        // products (mu search + D, N = 4000: 27.2 -> 36.1 DM/s; N = 2000: 105.9 -> 119.7).
         const int64_t t128 = (n + 127) / 128, w128 = t128 * (t128 + 1) / 2 * b.count;
+        f32x4* sc = static_cast<f32x4*>(scratch);
+        const int64_t sv = (int64_t)(scratch_bytes / sizeof(f32x4));
         if constexpr (P == P_BF16X3) {
-            if (w128 >= 100) return launch_lds<P, 1, 0, 2, 0, 1, 2, 0>(b, n, ld, st, static_cast<f32x4*>(scratch), (int64_t)(scratch_bytes / sizeof(f32x4)));
+            if (w128 >= 100) return launch_lds<P, 1, 0, 2, 0, 1, 2, 0>(b, n, ld, st, sc, sv);
         } else {
-            if (w128 >= 100 && b.count >= 2) return launch_lds<P, 1, 0, 2, 0, 1, 1, 0>(b, n, ld, st, static_cast<f32x4*>(scratch), (int64_t)(scratch_bytes / sizeof(f32x4)));
+            if (w128 >= 100) return launch_lds<P, 1, 0, 2, 0, 1, 1, 0>(b, n, ld, st, sc, sv);
         }
         if (w64 < 300) return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st, scratch, scratch_bytes);
         return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st, scratch, scratch_bytes);
