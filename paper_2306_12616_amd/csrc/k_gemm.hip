@@ -214,6 +214,21 @@ k_gemm_lds_fix(const GemmBatch<float> batch, int64_t n, int64_t ld, int ntile, i
 
 // LDS layout: unpadded 64-byte rows with the 16-byte chunks of row r XOR-swizzled by
 // (r >> 1) & 3 (measured: 522 -> 570 TFLOP/s of bf16 work at N = 4000 against 8-element padding)
+// Rounds of tile work a launch of W tiles takes on S slots: full rounds, plus a small tail when
+// the last round is split into K slices (under a quarter full, after a full round), else one more.
+__host__ inline double rounds_of(int64_t W, int64_t S) {
+    const int64_t full = W / S, rest = W % S;
+    if (rest == 0) return (double)full;
+    return (double)full + ((full >= 1 && rest * 4 <= S) ? 0.15 : 1.0);
+}
+
+// 64-tiles from one full round on: one wavefront per tile (1024 slots) or the K split over two
+// (512 slots, half a tile's time each, plus the split's cost `over`), whichever quantises better
+// (N = 1500 eight products, float64: 44.2 -> 50.0 TFLOP/s; N = 3000 four: 54.0 -> 58.9).
+__host__ inline bool k_split_quantises_better(int64_t w64, double over) {
+    return rounds_of(w64, 512) * 0.5 * over < rounds_of(w64, 1024);
+}
+
 // Resident work-groups of the LDS kernel: two per CU (two wavefronts per SIMD, <= 80 KB of LDS).
 constexpr int kLdsSlots = 2 * 256;
 
@@ -274,13 +289,21 @@ hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
     // 60.9); below it the smaller 48-tiles fill the chip better (float64 N = 2000 single: 40.0
     // against 38.4 for split 64-tiles; N = 1000: 48-tiles, K split 4 ways up to 300 64-tiles).
     if constexpr (P == P_F64) {
-        if (w64 >= 1024 && n >= 1500) return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st, scratch, scratch_bytes);
+        if (w64 >= 1024 && n >= 1500) {
+            if (k_split_quantises_better(w64, 1.10))
+                return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st, scratch, scratch_bytes);
+            return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st, scratch, scratch_bytes);
+        }
         if (fits48 && w64 < 300) return launch_cfg<P, 48, 1, 1, KU, 1, 4>(b, n, ld, st, scratch, scratch_bytes);
         if (fits48) return launch_cfg<P, 48, 1, 1, KU, 1, 1>(b, n, ld, st, scratch, scratch_bytes);
         if (w64 < 400) return launch_cfg<P, 64, 1, 1, KU, 1, 4>(b, n, ld, st, scratch, scratch_bytes);
         return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st, scratch, scratch_bytes);
     } else if constexpr (P == P_F32) {
-        if (w64 >= 1024) return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st, scratch, scratch_bytes);
+        if (w64 >= 1024) {
+            if (k_split_quantises_better(w64, 1.15))
+                return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st, scratch, scratch_bytes);
+            return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st, scratch, scratch_bytes);
+        }
         if (fits48) return launch_cfg<P, 48, 1, 1, KU, 1, 2, 0, 16, 2>(b, n, ld, st, scratch, scratch_bytes);
         return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st, scratch, scratch_bytes);
     } else {
