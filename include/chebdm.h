@@ -64,9 +64,12 @@ enum chebdm_prec {
                        /* float32 accumulation: about float32 accuracy       */
 };
 
-/* Order of the baby-step products T_2..T_k (both give the same matrices). */
+/* Order of the baby-step products T_2..T_k and of the mu search's ladder T_2k, T_3k, ...
+   (both orders give the same matrices up to rounding). */
 enum chebdm_baby {
-    CHEBDM_BABY_AUTO = 0,       /* stages for CHEBDM_FP64, sequential otherwise           */
+    CHEBDM_BABY_AUTO = 0,       /* baby steps: stages for CHEBDM_FP64, sequential         */
+                                /* otherwise; ladder: stages for CHEBDM_FP64 and          */
+                                /* CHEBDM_FP32, sequential for the split-bf16 precisions  */
     CHEBDM_BABY_STAGES = 1,     /* Algorithm 1: ceil(log2 k) stages of independent        */
                                 /* products T_{i+u} = 2 T_i T_u - T_{i-u}, one launch each */
     CHEBDM_BABY_SEQUENTIAL = 2  /* T_{i+1} = 2 T_1 T_i - T_{i-1}: errors grow ~i instead  */

@@ -73,7 +73,7 @@ int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 struct Plan {
     int64_t n = 0, ld = 0;
     int order = 0, k = 1, m = 1, M = 0;
-    int prec = CHEBDM_FP64, form = CHEBDM_GIANT_COMPOSITION, baby = CHEBDM_BABY_STAGES;
+    int prec = CHEBDM_FP64, form = CHEBDM_GIANT_COMPOSITION, baby = CHEBDM_BABY_STAGES, ladder = CHEBDM_BABY_STAGES;
     int max_iter = 200;
     int search = CHEBDM_SEARCH_BISECTION;
     int damping = CHEBDM_DAMPING_NONE;
@@ -225,6 +225,16 @@ int check_opts(const chebdm_opts* o, Plan& pl) {
     pl.baby = o->baby_steps != CHEBDM_BABY_AUTO
                   ? o->baby_steps
                   : (o->prec == CHEBDM_FP64 ? CHEBDM_BABY_STAGES : CHEBDM_BABY_SEQUENTIAL);
+    // The ladder T_{lk} = T_l(T_k) multiplies O(1)-norm matrices in either order, and with
+    // float32 products the stages cost it no accuracy (moments at N = 1000 within a factor of 2
+    // of the sequential order's; the baby steps' sequential order keeps its edge only because it
+    // multiplies by T_1, whose norm is far below 1 on loose bounds).  The split-bf16 products
+    // lose about an order of magnitude in the moments when staged, so they keep the sequential
+    // ladder.
+    pl.ladder = o->baby_steps != CHEBDM_BABY_AUTO
+                    ? o->baby_steps
+                    : (o->prec == CHEBDM_FP64 || o->prec == CHEBDM_FP32 ? CHEBDM_BABY_STAGES
+                                                                         : CHEBDM_BABY_SEQUENTIAL);
     pl.prec = o->prec;
     pl.form = o->giant_form == CHEBDM_GIANT_POWER ? CHEBDM_GIANT_POWER : CHEBDM_GIANT_COMPOSITION;
     pl.chains = o->giant_form == CHEBDM_GIANT_ONE_CHAIN ? 1 : (o->giant_form == CHEBDM_GIANT_TWO_CHAINS ? 2 : 0);
@@ -366,7 +376,7 @@ void* rslot(chebdm_handle h, const Plan& pl, int l) { return slot(h, pl, pl.k + 
 // Everything a captured device sequence depends on: if two calls agree on all of it, every
 // kernel argument of their sequences agrees, and the first call's graph can be replayed.
 struct ReplayKey {
-    int32_t kind, order, k, m, prec, form, baby, search, max_iter, bounds_on_device, damping, split_h;
+    int32_t kind, order, k, m, prec, form, baby, ladder, search, max_iter, bounds_on_device, damping, split_h;
     int64_t n, ld, ldh, ldd, M;
     const void *dH, *dD, *mats, *small;
     double tol, beta, x, emin, emax;   // x: n_elec (mu search) or mu (density)
@@ -385,6 +395,7 @@ std::vector<char> replay_key(int kind, const Plan& pl, chebdm_handle h, const do
     k.form = pl.form;
     k.split_h = pl.split_h;
     k.baby = pl.baby;
+    k.ladder = pl.ladder;
     k.search = pl.search;
     k.max_iter = pl.max_iter;
     k.damping = pl.damping;
@@ -564,10 +575,10 @@ int moments_on_device(chebdm_handle h, const Plan& pl, int* n_gemm) {
         if (pl.split_h > 0 && l == pl.split_h) return slot(h, pl, (int64_t)k + pl.m);
         return rslot(h, pl, l - 2);
     };
-    // the ladder T_{lk} = T_l(T_k) is the same Chebyshev recurrence in Y = T_k, so it takes the
-    // baby steps' schedule (stage-parallel or sequential)
+    // the ladder T_{lk} = T_l(T_k) is the same Chebyshev recurrence in Y = T_k, with a schedule
+    // of its own (stage-parallel unless the caller asks for the sequential order)
     Chain ch(h, pl, n_gemm);
-    CHECK(chebyshev_powers(ch, pl, lptr, lmax, pl.baby == CHEBDM_BABY_STAGES));
+    CHECK(chebyshev_powers(ch, pl, lptr, lmax, pl.ladder == CHEBDM_BABY_STAGES));
     const int64_t stride = pl.ld * pl.ld;
     HIP_TRY(launch_traces(tslot(h, pl, 1), stride, k, pl.n, pl.ld, pl.elem == 8, h->trb, h->stream));
     if (lmax >= 1) {

@@ -330,6 +330,38 @@ def test_baby_schedules_match_oracle(cd, handle, baby, n, order):
     assert err <= 1e-10
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_reduced_precision_ladder_schedules(cd, handle, prec):
+    # The mu search's ladder T_{lk} = T_l(T_k) runs in stages by default for float32 products
+    # (whose baby steps stay sequential): both ladder orders hold the moments to the
+    # reduced-precision bound against the oracle, the staged one within a factor of 2 of the
+    # sequential one's error and in fewer launches.  The split-bf16 products keep the sequential
+    # ladder by default (staged, their moment error grows about eightfold).
+    n, order = 1000, 512
+    _say(f"ladder schedules {prec} n={n} order={order}")
+    h, q, lam = synth.hamiltonian(n, "gaussmix6", seed=77)
+    H = _dev(h)
+    lo, hi = cd.chebdm_bounds(handle, H)
+    ref = ch.moments_from_eigs(lam, lo, hi, order)
+    res = {}
+    for baby in ("auto", "sequential"):
+        cd.chebdm_profile_enable(handle, True)
+        tau = cd.chebdm_moments(handle, H, order, cd.make_opts(prec, baby=baby))
+        prof = cd.chebdm_profile_read(handle)
+        cd.chebdm_profile_enable(handle, False)
+        res[baby] = (float(np.max(np.abs(tau - ref))), prof["gemm_launches"], prof["gemm_products"])
+        _say(f"  {baby:10s} max|tau - tau_oracle| = {res[baby][0]:.3e} in {res[baby][1]} launches "
+             f"({res[baby][2]} products)")
+    assert res["auto"][2] == res["sequential"][2]
+    for err, _, _ in res.values():
+        assert err <= 1e-5 * n
+    if prec == "fp32":
+        assert res["auto"][1] < res["sequential"][1]
+        assert res["auto"][0] <= 2.0 * res["sequential"][0]
+    else:
+        assert res["auto"][:2] == res["sequential"][:2]
+
+
 def test_profile_counts_products(cd, handle):
     h, q, lam = synth.hamiltonian(300, "uniform", seed=31)
     H = _dev(h)
