@@ -67,13 +67,20 @@ enum chebdm_prec {
 /* Order of the baby-step products T_2..T_k and of the mu search's ladder T_2k, T_3k, ...
    (both orders give the same matrices up to rounding). */
 enum chebdm_baby {
-    CHEBDM_BABY_AUTO = 0,       /* baby steps: stages for CHEBDM_FP64, sequential         */
-                                /* otherwise; ladder: stages for CHEBDM_FP64 and          */
-                                /* CHEBDM_FP32, sequential for the split-bf16 precisions  */
+    CHEBDM_BABY_AUTO = 0,       /* baby steps: stages for CHEBDM_FP64, odd chains for     */
+                                /* CHEBDM_FP32, sequential for the split-bf16 precisions; */
+                                /* ladder: stages for CHEBDM_FP64 and CHEBDM_FP32,        */
+                                /* sequential for the split-bf16 precisions               */
     CHEBDM_BABY_STAGES = 1,     /* Algorithm 1: ceil(log2 k) stages of independent        */
                                 /* products T_{i+u} = 2 T_i T_u - T_{i-u}, one launch each */
-    CHEBDM_BABY_SEQUENTIAL = 2  /* T_{i+1} = 2 T_1 T_i - T_{i-1}: errors grow ~i instead  */
+    CHEBDM_BABY_SEQUENTIAL = 2, /* T_{i+1} = 2 T_1 T_i - T_{i-1}: errors grow ~i instead  */
                                 /* of ~i^2, which matters for float32 / bf16 products     */
+    CHEBDM_BABY_ODD_CHAINS = 3  /* T_2..T_s one by one, then s interleaved chains         */
+                                /* T_{i+s} = 2 T_s T_i - T_{|i-s|}, one launch of s       */
+                                /* products per round; s odd >= 3, chosen for the fewest  */
+                                /* launches (5 for k = 23).  T_s of odd s is as small as  */
+                                /* T_1 where the spectrum sits well inside the bounds, so */
+                                /* the errors stay those of the sequential order          */
 };
 
 /* How the giant steps combine the blocks (all give the same polynomial). */

@@ -205,7 +205,7 @@ int check_opts(const chebdm_opts* o, Plan& pl) {
                     "the power form is float64 only: its coefficients grow like 2^m |c|");
     if (o->k_override < 0 || o->n_quad < 0 || o->max_iter < 0 || !(o->tol >= 0.0))
         return fail(CHEBDM_ERR_ARG, "negative option");
-    if (o->baby_steps < CHEBDM_BABY_AUTO || o->baby_steps > CHEBDM_BABY_SEQUENTIAL)
+    if (o->baby_steps < CHEBDM_BABY_AUTO || o->baby_steps > CHEBDM_BABY_ODD_CHAINS)
         return fail(CHEBDM_ERR_ARG, "unknown baby-step schedule");
     if (o->search != CHEBDM_SEARCH_BISECTION && o->search != CHEBDM_SEARCH_NEWTON)
         return fail(CHEBDM_ERR_ARG, "unknown mu search");
@@ -222,9 +222,15 @@ int check_opts(const chebdm_opts* o, Plan& pl) {
     pl.bounds = o->bounds;
     pl.lz_steps = o->lanczos_steps ? o->lanczos_steps : 40;
     pl.lz_margin = o->bounds_margin > 0.0 ? o->bounds_margin : 0.01;
+    // Float32 baby steps go in odd chains: the stages lose to the sequential order on loose
+    // bounds (float32 CPU model, N = 1000, Gershgorin: 1.5e-4 against 2.4e-7), where T_1 and
+    // every odd T_s are small; chains of step 3, 5 or 7 match the sequential order there and
+    // every order agrees on tight bounds.  The split-bf16 products stay sequential (their
+    // chains double the error, and they sit closer to their tolerance).
     pl.baby = o->baby_steps != CHEBDM_BABY_AUTO
                   ? o->baby_steps
-                  : (o->prec == CHEBDM_FP64 ? CHEBDM_BABY_STAGES : CHEBDM_BABY_SEQUENTIAL);
+                  : (o->prec == CHEBDM_FP64 ? CHEBDM_BABY_STAGES
+                                            : (o->prec == CHEBDM_FP32 ? CHEBDM_BABY_ODD_CHAINS : CHEBDM_BABY_SEQUENTIAL));
     // The ladder T_{lk} = T_l(T_k) multiplies O(1)-norm matrices in either order, and with
     // float32 products the stages cost it no accuracy (moments at N = 1000 within a factor of 2
     // of the sequential order's; the baby steps' sequential order keeps its edge only because it
@@ -367,6 +373,21 @@ struct Chain {
 void* tslot(chebdm_handle h, const Plan& pl, int i) { return slot(h, pl, i - 1); }
 // R_l lives in slot k + l.
 void* rslot(chebdm_handle h, const Plan& pl, int l) { return slot(h, pl, pl.k + l); }
+
+// Step s of the odd-chain schedule for P_2..P_K: the odd s >= 3 with the fewest launches,
+// (s - 1) one-product launches and ceil((K - s) / s) rounds of s; ties go to the smaller s.
+// Returns 0 (plain sequential order) when K is too small for a chain round.
+int odd_chain_step(int K) {
+    int best = 0, best_launches = K - 1;
+    for (int s = 3; s < K; s += 2) {
+        const int launches = (s - 1) + (K - s + s - 1) / s;
+        if (launches < best_launches) {
+            best = s;
+            best_launches = launches;
+        }
+    }
+    return best;
+}
 
 // Baby steps T_2..T_k in the stages of Algorithm 1: stage 1 makes T_2; stage
 // s >= 2 makes T_{2^{s-2}+i} and T_{2^{s-1}+i} from already known T's.  The
@@ -522,13 +543,25 @@ int lanczos_on_device(chebdm_handle h, const double* dH, int64_t n, int64_t ldh,
 // Stages (Algorithm 1, Sec. III.B): stage s forms P_{v+1..2v} (v = 2^{s-1}) from P_1..P_v by
 // P_{i+u} = 2 P_i P_u - P_{i-u} and P_{i+v} = 2 P_v P_i - P_{v-i} (u = v/2, u < i <= v); the
 // products of a stage are independent and go out as one grouped launch.
+// Odd chains: P_2..P_s sequentially, then P_{i+s} = 2 P_s P_i - P_{|i-s|} for the s products of
+// each round (their operands come from earlier rounds).
 template <class Slot>
-int chebyshev_powers(Chain& ch, const Plan& pl, Slot slot, int K, bool stages) {
+int chebyshev_powers(Chain& ch, const Plan& pl, Slot slot, int K, int sched) {
     if (K < 2) return 0;
-    if (!stages) {
-        for (int i = 1; i < K; ++i) {
+    const int cs = sched == CHEBDM_BABY_ODD_CHAINS ? odd_chain_step(K) : 0;
+    if (sched == CHEBDM_BABY_SEQUENTIAL || sched == CHEBDM_BABY_ODD_CHAINS) {
+        const int seq_end = cs > 0 ? cs : K;
+        for (int i = 1; i < seq_end; ++i) {
             ch.add(slot(1), slot(i), i == 1 ? nullptr : slot(i - 1), -1.0, nullptr, 0.0, 2.0, i == 1 ? -1.0 : 0.0,
                    slot(i + 1), pl.ld, 0);
+            CHECK(ch.flush());
+        }
+        for (int g0 = seq_end + 1; g0 <= K; g0 += cs) {
+            for (int i = g0; i < g0 + cs && i <= K; ++i) {
+                const int j = i - cs, r = j > cs ? j - cs : cs - j;
+                ch.add(slot(cs), slot(j), r == 0 ? nullptr : slot(r), -1.0, nullptr, 0.0, 2.0, r == 0 ? -1.0 : 0.0,
+                       slot(i), pl.ld, 0);
+            }
             CHECK(ch.flush());
         }
         return 0;
@@ -559,8 +592,7 @@ int chebyshev_powers(Chain& ch, const Plan& pl, Slot slot, int K, bool stages) {
 
 int baby_steps(chebdm_handle h, const Plan& pl, int* n_gemm) {
     Chain ch(h, pl, n_gemm);
-    return chebyshev_powers(ch, pl, [&](int i) -> void* { return tslot(h, pl, i); }, pl.k,
-                            pl.baby == CHEBDM_BABY_STAGES);
+    return chebyshev_powers(ch, pl, [&](int i) -> void* { return tslot(h, pl, i); }, pl.k, pl.baby);
 }
 
 // Ladder T_{2k}, ..., T_{lmax k} (T_{lk} in R slot l-2) and the moments tau_0..tau_L.
@@ -578,7 +610,7 @@ int moments_on_device(chebdm_handle h, const Plan& pl, int* n_gemm) {
     // the ladder T_{lk} = T_l(T_k) is the same Chebyshev recurrence in Y = T_k, with a schedule
     // of its own (stage-parallel unless the caller asks for the sequential order)
     Chain ch(h, pl, n_gemm);
-    CHECK(chebyshev_powers(ch, pl, lptr, lmax, pl.ladder == CHEBDM_BABY_STAGES));
+    CHECK(chebyshev_powers(ch, pl, lptr, lmax, pl.ladder));
     const int64_t stride = pl.ld * pl.ld;
     HIP_TRY(launch_traces(tslot(h, pl, 1), stride, k, pl.n, pl.ld, pl.elem == 8, h->trb, h->stream));
     if (lmax >= 1) {

@@ -317,8 +317,8 @@ def test_density_is_exactly_symmetric(cd, handle, prec):
     assert np.array_equal(d, d.T)
 
 
-@pytest.mark.parametrize("baby", ["stages", "sequential"])
-@pytest.mark.parametrize("n,order", [(256, 128), (700, 512)])
+@pytest.mark.parametrize("baby", ["stages", "sequential", "odd_chains"])
+@pytest.mark.parametrize("n,order", [(256, 128), (700, 512), (300, 2048)])   # k = 12, 23, 46: chain steps 3, 5, 7
 def test_baby_schedules_match_oracle(cd, handle, baby, n, order):
     _say(f"baby={baby} n={n} order={order}")
     h, q, lam = synth.hamiltonian(n, "gaussmix6", seed=40 + n)
@@ -360,6 +360,28 @@ def test_reduced_precision_ladder_schedules(cd, handle, prec):
         assert res["auto"][0] <= 2.0 * res["sequential"][0]
     else:
         assert res["auto"][:2] == res["sequential"][:2]
+
+
+@pytest.mark.parametrize("bounds", ["gershgorin", "lanczos"])
+def test_float32_baby_schedules(cd, handle, bounds):
+    # float32 baby steps default to odd chains: as accurate as the sequential order (within a
+    # factor of 2) on loose and on tight bounds, in fewer launches
+    n, order, beta, mu = 1000, 512, 100.0, 0.02
+    _say(f"float32 baby schedules n={n} order={order} bounds={bounds}")
+    h, q, lam = synth.hamiltonian(n, "gaussmix6", seed=91)
+    H = _dev(h)
+    res = {}
+    for baby in ("auto", "sequential"):
+        cd.chebdm_profile_enable(handle, True)
+        D, info = cd.chebdm_density(handle, H, beta, mu, order, cd.make_opts("fp32", baby=baby, bounds=bounds))
+        prof = cd.chebdm_profile_read(handle)
+        cd.chebdm_profile_enable(handle, False)
+        ref, _ = _oracle_density(q, lam, order, beta, mu, info["emin"], info["emax"], info["n_quad"])
+        res[baby] = (float(np.max(np.abs(D.cpu().numpy() - ref))), prof["gemm_launches"], prof["gemm_products"])
+        _say(f"  {baby:10s} max|D - D_oracle| = {res[baby][0]:.3e} in {res[baby][1]} launches")
+    assert res["auto"][2] == res["sequential"][2] and res["auto"][1] < res["sequential"][1]
+    assert res["auto"][0] <= 1e-5 and res["sequential"][0] <= 1e-5
+    assert res["auto"][0] <= 2.0 * res["sequential"][0]
 
 
 def test_profile_counts_products(cd, handle):
