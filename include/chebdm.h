@@ -86,16 +86,24 @@ enum chebdm_baby {
 /* How the giant steps combine the blocks (all give the same polynomial). */
 enum chebdm_giant {
     CHEBDM_GIANT_COMPOSITION = 0, /* sum_l T_l(T_k) R_l by Clenshaw over l (default);  */
-                                  /* the library picks one or two chains (below)      */
+                                  /* the library picks one, two or four chains (below; */
+                                  /* four while a product has < 1024 64-tiles)        */
     CHEBDM_GIANT_POWER = 1,       /* paper's sum_j T_k^j S_j by Horner (eq. "ansatz") */
     CHEBDM_GIANT_ONE_CHAIN = 2,   /* composition form, one Clenshaw chain: m-1 steps  */
-    CHEBDM_GIANT_TWO_CHAINS = 3   /* composition form as two chains of about m/2      */
+    CHEBDM_GIANT_TWO_CHAINS = 3,  /* composition form as two chains of about m/2      */
                                   /* steps run side by side, joined by one product    */
                                   /* with T_h(T_k), h = ceil(m/2) (via eq. "identity"),*/
                                   /* when that matrix comes from the moment ladder:   */
                                   /* chebdm_mu_search with D and m >= 4; otherwise one */
                                   /* chain.  Same m-1 products, half the sequential   */
                                   /* launches, two products per launch.               */
+    CHEBDM_GIANT_FOUR_CHAINS = 4  /* both halves of the two chains split again at     */
+                                  /* q = ceil(h/2) the same way: four chains of about */
+                                  /* m/4 steps side by side, then one launch of two   */
+                                  /* products with T_q(T_k), then the product with    */
+                                  /* T_h(T_k).  Needs m >= 8 and the ladder as above; */
+                                  /* otherwise as CHEBDM_GIANT_TWO_CHAINS.  Same m-1  */
+                                  /* products in about m/4 + 2 launches.              */
 };
 
 /* How chebdm_mu_search finds mu~ on the quadrature trace t(mu~) (both stop
@@ -287,7 +295,8 @@ int chebdm_mu_search(chebdm_handle h, const double* dH, int64_t n, int64_t ldh,
  * Device memory a call of chebdm_density / chebdm_mu_search / chebdm_moments
  * with these sizes and options makes the handle hold (it keeps the largest it
  * has needed): the matrix workspace, (k + m) ld^2 elements (k + m + 1 for
- * the composition form with m >= 4: the two-chain giant steps keep T_h(T_k))
+ * the composition form with m >= 4: the two-chain giant steps keep T_h(T_k);
+ * k + m + 2 where the giant steps go in four chains: they also keep T_q(T_k))
  * with ld = round_up(n, 128) and 8 (float64) or 4 bytes per element, plus the
  * small buffers sized for opts->n_quad quadrature nodes (2^16 when 0), plus
  * 32 MB of product scratch (partial sums of K-sliced product tiles).

@@ -26,7 +26,7 @@ ERR_ARG, ERR_HIP, ERR_OOM, ERR_NONFINITE, ERR_BRACKET, ERR_UNSUPPORTED = -1, -2,
 _PREC_NAMES = {"fp64": FP64, "f64": FP64, "fp32": FP32, "f32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6}
 _BABY_NAMES = {"auto": 0, "stages": 1, "sequential": 2, "odd_chains": 3}
 _FORM_NAMES = {"composition": COMPOSITION, "clenshaw": COMPOSITION, "power": POWER, "horner": POWER,
-               "one_chain": 2, "two_chains": 3}
+               "one_chain": 2, "two_chains": 3, "four_chains": 4}
 
 
 class Opts(ctypes.Structure):

@@ -80,6 +80,7 @@ struct Plan {
     int bounds = CHEBDM_BOUNDS_GERSHGORIN, lz_steps = 40;
     int chains = 0;    // composition form: 0 library's choice, 1 or 2 chains
     int split_h = 0;   // > 0: giant steps as two Clenshaw chains joined by T_h(T_k) (extra slot k + m)
+    int split_q = 0;   // > 0: each half split again at q, joined by T_q(T_k) (extra slot k + m + 1)
     double lz_margin = 0.01;
     double tol = 1e-10;
     size_t elem = 8;
@@ -198,7 +199,7 @@ int check_opts(const chebdm_opts* o, Plan& pl) {
     chebdm_default_opts(&d);
     if (!o) o = &d;
     if (o->prec < CHEBDM_FP64 || o->prec > CHEBDM_BF16X6) return fail(CHEBDM_ERR_ARG, "unknown precision");
-    if (o->giant_form < CHEBDM_GIANT_COMPOSITION || o->giant_form > CHEBDM_GIANT_TWO_CHAINS)
+    if (o->giant_form < CHEBDM_GIANT_COMPOSITION || o->giant_form > CHEBDM_GIANT_FOUR_CHAINS)
         return fail(CHEBDM_ERR_ARG, "unknown giant-step form");
     if (o->giant_form == CHEBDM_GIANT_POWER && o->prec != CHEBDM_FP64)
         return fail(CHEBDM_ERR_UNSUPPORTED,
@@ -243,7 +244,10 @@ int check_opts(const chebdm_opts* o, Plan& pl) {
                                                                          : CHEBDM_BABY_SEQUENTIAL);
     pl.prec = o->prec;
     pl.form = o->giant_form == CHEBDM_GIANT_POWER ? CHEBDM_GIANT_POWER : CHEBDM_GIANT_COMPOSITION;
-    pl.chains = o->giant_form == CHEBDM_GIANT_ONE_CHAIN ? 1 : (o->giant_form == CHEBDM_GIANT_TWO_CHAINS ? 2 : 0);
+    pl.chains = o->giant_form == CHEBDM_GIANT_ONE_CHAIN    ? 1
+                : o->giant_form == CHEBDM_GIANT_TWO_CHAINS ? 2
+                : o->giant_form == CHEBDM_GIANT_FOUR_CHAINS ? 4
+                                                            : 0;
     pl.elem = o->prec == CHEBDM_FP64 ? 8 : 4;
     pl.max_iter = o->max_iter ? o->max_iter : 200;
     pl.tol = o->tol > 0.0 ? o->tol : 1e-10;
@@ -323,6 +327,29 @@ int two_chain_split(const Plan& pl, bool ladder_and_density) {
     return (pl.m + 1) / 2;
 }
 
+// Library's choice between two and four chains where both are possible: four while one product
+// holds less than a full round of 64-tiles (1024: 256 CUs at one wavefront per SIMD), where two
+// products per launch still leave the chip part idle.  Measured (mu search + D, order 512, DM/s
+// two -> four chains): N = 1000 float64 412 -> 432, float32 515 -> 543, split-bf16 387 -> 423;
+// N = 2000 float64 87.3 -> 89.4, float32 140.7 -> 146.4, split-bf16 179.8 -> 189.5; N = 4000
+// (2016 tiles per product) within noise: 13.75 -> 13.71, 27.05 -> 27.07, 52.6 -> 52.4.
+bool four_chains_pay(const Plan& pl) {
+    const int64_t t = round_up(pl.n, 128) / 64;
+    return t * (t + 1) / 2 < 1024;
+}
+
+// Second split point of the four-chain giant steps, or 0: both halves of the two chains (blocks
+// 0..h-1 and h..m-1, the second no longer than the first) split at q = ceil(h/2).  Needs m >= 8
+// (q >= 2; the last chain may be a single block) and T_q(T_k) from the ladder.
+int four_chain_split(const Plan& pl, int split_h) {
+    if (split_h == 0 || pl.m < 8 || pl.chains == 1 || pl.chains == 2) return 0;
+    if (pl.chains == 0 && !four_chains_pay(pl)) return 0;
+    return (split_h + 1) / 2;
+}
+
+// Slots the giant-step chains keep beyond the k + m of the plan: T_h(T_k), and T_q(T_k).
+int extra_chain_slots(const Plan& pl) { return (pl.split_h > 0 ? 1 : 0) + (pl.split_q > 0 ? 1 : 0); }
+
 // ---------------------------------------------------------------- GEMM helper
 
 struct Chain {
@@ -397,7 +424,7 @@ int odd_chain_step(int K) {
 // Everything a captured device sequence depends on: if two calls agree on all of it, every
 // kernel argument of their sequences agrees, and the first call's graph can be replayed.
 struct ReplayKey {
-    int32_t kind, order, k, m, prec, form, baby, ladder, search, max_iter, bounds_on_device, damping, split_h;
+    int32_t kind, order, k, m, prec, form, baby, ladder, search, max_iter, bounds_on_device, damping, split_h, split_q;
     int64_t n, ld, ldh, ldd, M;
     const void *dH, *dD, *mats, *small;
     double tol, beta, x, emin, emax;   // x: n_elec (mu search) or mu (density)
@@ -415,6 +442,7 @@ std::vector<char> replay_key(int kind, const Plan& pl, chebdm_handle h, const do
     k.prec = pl.prec;
     k.form = pl.form;
     k.split_h = pl.split_h;
+    k.split_q = pl.split_q;
     k.baby = pl.baby;
     k.ladder = pl.ladder;
     k.search = pl.search;
@@ -605,6 +633,7 @@ int moments_on_device(chebdm_handle h, const Plan& pl, int* n_gemm) {
     auto lptr = [&](int l) -> void* {
         if (l == 1) return tslot(h, pl, k);
         if (pl.split_h > 0 && l == pl.split_h) return slot(h, pl, (int64_t)k + pl.m);
+        if (pl.split_q > 0 && l == pl.split_q) return slot(h, pl, (int64_t)k + pl.m + 1);
         return rslot(h, pl, l - 2);
     };
     // the ladder T_{lk} = T_l(T_k) is the same Chebyshev recurrence in Y = T_k, with a schedule
@@ -650,7 +679,34 @@ int giant_steps(chebdm_handle h, const Plan& pl, double* dD, int64_t ldd, int* n
     } else {
         void* Y = k >= 1 ? tslot(h, pl, k) : nullptr;
         Chain ch(h, pl, n_gemm);
-        if (pl.form == CHEBDM_GIANT_COMPOSITION && pl.split_h > 0) {
+        if (pl.form == CHEBDM_GIANT_COMPOSITION && pl.split_q > 0) {
+            // four Clenshaw chains in Y = T_k, advanced together (up to four products per launch):
+            // blocks [0, q), [q, h), [h, h+q), [h+q, m) after both splits; then
+            // U_A = S_0 + T_q(Y) S_q and U_B = S_h + T_q(Y) S_{h+q} in one launch (in place in
+            // R slots 0 and h), then D = U_A + T_h(Y) U_B.
+            const int hs = pl.split_h, qs = pl.split_q;
+            const int base[4] = {0, qs, hs, hs + qs};
+            const int len[4] = {qs, hs - qs, qs, m - hs - qs};
+            auto step = [&](int b, int n_l, int l) {
+                const void* b2 = (l + 2 <= n_l - 1) ? rslot(h, pl, b + l + 2) : nullptr;
+                const double a = l >= 1 ? 2.0 : 1.0;
+                ch.add(Y, rslot(h, pl, b + l + 1), b2, -1.0, rslot(h, pl, b + l), 1.0, a, 0.0, rslot(h, pl, b + l),
+                       pl.ld, 0);
+            };
+            for (int t = 0; t < qs - 1; ++t) {
+                for (int c = 0; c < 4; ++c)
+                    if (t < len[c] - 1) step(base[c], len[c], len[c] - 2 - t);
+                CHECK(ch.flush());
+            }
+            const void* Tq = slot(h, pl, (int64_t)k + m + 1);
+            ch.add(Tq, rslot(h, pl, qs), nullptr, 0.0, rslot(h, pl, 0), 1.0, 1.0, 0.0, rslot(h, pl, 0), pl.ld, 0);
+            ch.add(Tq, rslot(h, pl, hs + qs), nullptr, 0.0, rslot(h, pl, hs), 1.0, 1.0, 0.0, rslot(h, pl, hs), pl.ld,
+                   0);
+            CHECK(ch.flush());
+            ch.add(slot(h, pl, (int64_t)k + m), rslot(h, pl, hs), nullptr, 0.0, rslot(h, pl, 0), 1.0, 1.0, 0.0, dD,
+                   ldd, 1);
+            CHECK(ch.flush());
+        } else if (pl.form == CHEBDM_GIANT_COMPOSITION && pl.split_h > 0) {
             // two Clenshaw chains in Y = T_k, advanced together (two products per launch):
             // S_A = sum_{l<h} T_l(Y) R''_l over R slots 0..h-1 and S_B = sum_{j<m-h} T_j(Y) R'_j
             // over R slots h..m-1 (blocks rearranged by launch_split_blocks), then
@@ -970,7 +1026,8 @@ int chebdm_mu_search(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, 
     CHECK(ensure_small(h, pl.M));
     pl.ld = round_up(n, 128);
     pl.split_h = two_chain_split(pl, dD != nullptr);
-    CHECK(ensure_mats(h, pl, pl.k + pl.m + (pl.split_h > 0 ? 1 : 0)));
+    pl.split_q = four_chain_split(pl, pl.split_h);
+    CHECK(ensure_mats(h, pl, pl.k + pl.m + extra_chain_slots(pl)));
     const int slot = dD ? 0 : 1;
     const std::vector<char> key = replay_key(slot, pl, h, dH, ldh, dD, dD ? ldd : 0, beta, n_elec, bounds_dev,
                                              emin, emax);
@@ -990,6 +1047,11 @@ int chebdm_mu_search(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, 
             HIP_TRY(launch_fermi_coeffs(order, pl.M, h->scal, h->ftab, h->c, h->stream, pl.damping));
             HIP_TRY(launch_block_coeffs(h->c, order, pl.k, pl.m, pl.form, h->coef, h->stream));
             if (pl.split_h > 0) HIP_TRY(launch_split_blocks(h->coef, pl.k, pl.m, pl.split_h, h->stream));
+            if (pl.split_q > 0) {
+                HIP_TRY(launch_split_blocks(h->coef, pl.k, pl.split_h, pl.split_q, h->stream));
+                HIP_TRY(launch_split_blocks(h->coef + (int64_t)pl.split_h * pl.k, pl.k, pl.m - pl.split_h,
+                                            pl.split_q, h->stream));
+            }
             CHECK(giant_steps(h, pl, dD, ldd, &pl.n_gemm));
         }
         return 0;
@@ -1018,7 +1080,9 @@ int chebdm_workspace_size(chebdm_handle h, int64_t n, int32_t order, const chebd
     CHECK(plan_split(pl));
     const int64_t ld = round_up(n, 128);
     const int64_t M = opts && opts->n_quad > 0 ? opts->n_quad : (int64_t)1 << 16;
-    const int64_t slots = pl.k + pl.m + (pl.form == CHEBDM_GIANT_COMPOSITION && pl.m >= 4 ? 1 : 0);
+    const bool comp = pl.form == CHEBDM_GIANT_COMPOSITION && pl.chains != 1;
+    const bool four = comp && pl.m >= 8 && (pl.chains == 4 || (pl.chains == 0 && four_chains_pay(pl)));
+    const int64_t slots = pl.k + pl.m + (comp && pl.m >= 4 ? 1 : 0) + (four ? 1 : 0);
     *bytes = (size_t)slots * (size_t)ld * (size_t)ld * pl.elem + small_bytes_for(M);
     *bytes += kGemmScratchBytes;
     return CHEBDM_OK;

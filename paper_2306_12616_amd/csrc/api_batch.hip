@@ -314,9 +314,10 @@ int chebdm_batch_create(chebdm_handle h, int32_t count, const int64_t* n, int32_
     chebdm_default_opts(&o);
     if (opts) o = *opts;
     if (o.prec < CHEBDM_FP64 || o.prec > CHEBDM_BF16X6) return fail(CHEBDM_ERR_ARG, "unknown precision");
-    if (o.giant_form == CHEBDM_GIANT_POWER || o.giant_form == CHEBDM_GIANT_TWO_CHAINS)
+    if (o.giant_form == CHEBDM_GIANT_POWER || o.giant_form == CHEBDM_GIANT_TWO_CHAINS ||
+        o.giant_form == CHEBDM_GIANT_FOUR_CHAINS)
         return fail(CHEBDM_ERR_UNSUPPORTED, "the batched path uses the composition form in one chain only");
-    if (o.giant_form < CHEBDM_GIANT_COMPOSITION || o.giant_form > CHEBDM_GIANT_TWO_CHAINS)
+    if (o.giant_form < CHEBDM_GIANT_COMPOSITION || o.giant_form > CHEBDM_GIANT_FOUR_CHAINS)
         return fail(CHEBDM_ERR_ARG, "unknown giant-step form");
     if (o.bounds != CHEBDM_BOUNDS_GERSHGORIN && o.bounds != CHEBDM_BOUNDS_LANCZOS)
         return fail(CHEBDM_ERR_ARG, "unknown bounds method");

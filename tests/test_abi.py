@@ -108,13 +108,21 @@ def test_block_split_override_and_limits(lib):
 
 def test_workspace_size_needs_no_device(lib):
     # (k + m + 1) ld^2 elements plus the small buffers; k = m = 23 at order 512, ld = 4096 at
-    # n = 4000 (the extra matrix is T_h(T_k) of the two-chain giant steps; none for the power form)
+    # n = 4000 (the extra matrix is T_h(T_k) of the two-chain giant steps, the library's choice at
+    # this size; four chains keep T_q(T_k) too, one chain and the power form neither)
     small = chebdm.chebdm_workspace_size(1, 0)
     f64 = chebdm.chebdm_workspace_size(4000, 512)
     f32 = chebdm.chebdm_workspace_size(4000, 512, chebdm.make_opts("fp32"))
     power = chebdm.chebdm_workspace_size(4000, 512, chebdm.make_opts("fp64", "power"))
+    four = chebdm.chebdm_workspace_size(4000, 512, chebdm.make_opts("fp64", "four_chains"))
+    one = chebdm.chebdm_workspace_size(4000, 512, chebdm.make_opts("fp64", "one_chain"))
     assert f64 - small >= 47 * 4096 * 4096 * 8 - 2 * 128 * 128 * 8
     assert f64 - f32 == 47 * 4096 * 4096 * 4
+    assert four - f64 == 4096 * 4096 * 8 and f64 - one == 4096 * 4096 * 8
     assert f64 - power == 4096 * 4096 * 8
+    # at n = 2000 (528 64-tiles per product) the library takes four chains
+    f64_2k = chebdm.chebdm_workspace_size(2000, 512)
+    one_2k = chebdm.chebdm_workspace_size(2000, 512, chebdm.make_opts("fp64", "one_chain"))
+    assert f64_2k - one_2k == 2 * 2048 * 2048 * 8
     with pytest.raises(chebdm.ChebdmError):
         chebdm.chebdm_workspace_size(0, 10)

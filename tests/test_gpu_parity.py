@@ -225,6 +225,11 @@ MU_CASES = [
     (200, "uniform", 15, 20.0, 100.5, "two_chains", "bisection"),
     (200, "gaussmix6", 24, 20.0, 100.5, "two_chains", "bisection"),
     (333, "highdos", 99, 40.0, 166.5, "two_chains", "newton"),
+    # four chains: m = 8, 9 (last chain a single block), 10, and 23
+    (200, "uniform", 63, 20.0, 100.5, "four_chains", "bisection"),
+    (200, "gaussmix6", 80, 20.0, 100.5, "four_chains", "bisection"),
+    (257, "highdos", 99, 40.0, 128.5, "four_chains", "newton"),
+    (300, "gaussmix6", 512, 80.0, 150.5, "four_chains", "bisection"),
 ]
 
 
@@ -545,11 +550,13 @@ def test_one_and_two_giant_chains_agree(cd, handle, prec, tol):
     h, q, lam = synth.hamiltonian(n, "gaussmix6", seed=2000)
     H = _dev(h)
     out = {}
-    for form in ("one_chain", "two_chains"):
+    for form in ("one_chain", "two_chains", "four_chains"):
         mu, D, info = cd.chebdm_mu_search(handle, H, beta, n / 2, order, cd.make_opts(prec, form))
         out[form] = (mu, D.cpu().numpy(), info)
-    (mu1, d1, i1), (mu2, d2, i2) = out["one_chain"], out["two_chains"]
-    assert mu1 == mu2 and i1["n_gemm"] == i2["n_gemm"] and i1["iters"] == i2["iters"]
-    err = float(np.max(np.abs(d1 - d2)))
-    _say(f"  {prec}: max|D_one - D_two| = {err:.2e}, n_gemm {i1['n_gemm']}")
-    assert err <= tol
+    mu1, d1, i1 = out["one_chain"]
+    for form in ("two_chains", "four_chains"):
+        mu2, d2, i2 = out[form]
+        assert mu1 == mu2 and i1["n_gemm"] == i2["n_gemm"] and i1["iters"] == i2["iters"]
+        err = float(np.max(np.abs(d1 - d2)))
+        _say(f"  {prec}: max|D_one - D_{form}| = {err:.2e}, n_gemm {i1['n_gemm']}")
+        assert err <= tol
