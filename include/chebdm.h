@@ -75,7 +75,8 @@ enum chebdm_baby {
                                 /* products T_{i+u} = 2 T_i T_u - T_{i-u}, one launch each */
     CHEBDM_BABY_SEQUENTIAL = 2, /* T_{i+1} = 2 T_1 T_i - T_{i-1}: errors grow ~i instead  */
                                 /* of ~i^2, which matters for float32 / bf16 products     */
-    CHEBDM_BABY_ODD_CHAINS = 3  /* T_2..T_s one by one, then s interleaved chains         */
+    CHEBDM_BABY_ODD_CHAINS = 3  /* T_2..T_s (the same way with a smaller step, or one by  */
+                                /* one), then s interleaved chains                       */
                                 /* T_{i+s} = 2 T_s T_i - T_{|i-s|}, one launch of s       */
                                 /* products per round; s odd >= 3, chosen for the fewest  */
                                 /* launches (5 for k = 23).  T_s of odd s is as small as  */

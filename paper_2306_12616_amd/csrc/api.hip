@@ -401,9 +401,9 @@ void* tslot(chebdm_handle h, const Plan& pl, int i) { return slot(h, pl, i - 1);
 // R_l lives in slot k + l.
 void* rslot(chebdm_handle h, const Plan& pl, int l) { return slot(h, pl, pl.k + l); }
 
-// Step s of the odd-chain schedule for P_2..P_K: the odd s >= 3 with the fewest launches,
-// (s - 1) one-product launches and ceil((K - s) / s) rounds of s; ties go to the smaller s.
-// Returns 0 (plain sequential order) when K is too small for a chain round.
+// Step s of the odd-chain schedule for P_2..P_K: the odd s >= 3 with the fewest launches when
+// P_2..P_s take s - 1 one-product launches, plus ceil((K - s) / s) rounds of s; ties go to the
+// smaller s.  Returns 0 (plain sequential order) when K is too small for a chain round.
 int odd_chain_step(int K) {
     int best = 0, best_launches = K - 1;
     for (int s = 3; s < K; s += 2) {
@@ -571,20 +571,24 @@ int lanczos_on_device(chebdm_handle h, const double* dH, int64_t n, int64_t ldh,
 // Stages (Algorithm 1, Sec. III.B): stage s forms P_{v+1..2v} (v = 2^{s-1}) from P_1..P_v by
 // P_{i+u} = 2 P_i P_u - P_{i-u} and P_{i+v} = 2 P_v P_i - P_{v-i} (u = v/2, u < i <= v); the
 // products of a stage are independent and go out as one grouped launch.
-// Odd chains: P_2..P_s sequentially, then P_{i+s} = 2 P_s P_i - P_{|i-s|} for the s products of
-// each round (their operands come from earlier rounds).
+// Odd chains: P_2..P_s (by the same rule with a smaller step, or sequentially), then
+// P_{i+s} = 2 P_s P_i - P_{|i-s|} for the s products of each round (their operands come from
+// earlier rounds).
 template <class Slot>
 int chebyshev_powers(Chain& ch, const Plan& pl, Slot slot, int K, int sched) {
     if (K < 2) return 0;
     const int cs = sched == CHEBDM_BABY_ODD_CHAINS ? odd_chain_step(K) : 0;
     if (sched == CHEBDM_BABY_SEQUENTIAL || sched == CHEBDM_BABY_ODD_CHAINS) {
-        const int seq_end = cs > 0 ? cs : K;
-        for (int i = 1; i < seq_end; ++i) {
-            ch.add(slot(1), slot(i), i == 1 ? nullptr : slot(i - 1), -1.0, nullptr, 0.0, 2.0, i == 1 ? -1.0 : 0.0,
-                   slot(i + 1), pl.ld, 0);
-            CHECK(ch.flush());
+        if (cs > 0) {
+            CHECK(chebyshev_powers(ch, pl, slot, cs, CHEBDM_BABY_ODD_CHAINS));   // P_2..P_s
+        } else {
+            for (int i = 1; i < K; ++i) {
+                ch.add(slot(1), slot(i), i == 1 ? nullptr : slot(i - 1), -1.0, nullptr, 0.0, 2.0,
+                       i == 1 ? -1.0 : 0.0, slot(i + 1), pl.ld, 0);
+                CHECK(ch.flush());
+            }
         }
-        for (int g0 = seq_end + 1; g0 <= K; g0 += cs) {
+        for (int g0 = cs + 1; cs > 0 && g0 <= K; g0 += cs) {
             for (int i = g0; i < g0 + cs && i <= K; ++i) {
                 const int j = i - cs, r = j > cs ? j - cs : cs - j;
                 ch.add(slot(cs), slot(j), r == 0 ? nullptr : slot(r), -1.0, nullptr, 0.0, 2.0, r == 0 ? -1.0 : 0.0,
