@@ -1045,7 +1045,7 @@ int chebdm_mu_search(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, 
         size_t ev = (size_t)-1;
         if (h->prof) CHECK(prof_begin(h, PROF_SEARCH, 0, 0.0, 0.0, &ev));
         HIP_TRY(launch_dct3(h->tau, order, pl.M, h->w, h->xtab, h->stream, pl.damping));
-        HIP_TRY(launch_bisect(h->w, h->xtab, pl.M, h->scal, pl.search, h->stream));
+        HIP_TRY(launch_bisect(h->w, h->xtab, pl.M, h->scal, pl.search, h->ftab, h->stream));
         if (h->prof) CHECK(prof_end(h, ev));
         if (dD) {
             HIP_TRY(launch_fermi_coeffs(order, pl.M, h->scal, h->ftab, h->c, h->stream, pl.damping));

@@ -228,7 +228,8 @@ int enqueue(chebdm_batch_ctx* b, hipStream_t st, bool prof, bool with_density) {
         HIP_TRY(launch_batch_features(d, b->geo, b->tau, b->scal, b->feat, st));
         HIP_TRY(launch_mlp_forward(b->mlp_w, b->feat, d.count, b->mu_hat, b->mlp_work, st));
     }
-    HIP_TRY(launch_batch_search(d, b->tau, b->mq, b->w, b->x, b->scal, b->search_mode, b->mu_hat, b->mlp_delta, st));
+    HIP_TRY(launch_batch_search(d, b->tau, b->mq, b->w, b->x, b->scal, b->search_mode, b->mu_hat, b->mlp_delta,
+                                b->ftab, st));
     if (prof) CHECK(prof_end(b->h, ev));
     if (!with_density) {
         HIP_TRY(launch_batch_finish(d, b->tab, b->geo, b->scal, b->mu, b->trD, 0, st));

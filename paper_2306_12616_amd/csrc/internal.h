@@ -102,7 +102,8 @@ hipError_t launch_assemble_moments(const double* tr_baby, const double* gram, in
                                    int order, int64_t n, double* tau, hipStream_t st);
 hipError_t launch_dct3(const double* tau, int order, int M, double* w, double* x_tab, hipStream_t st,
                        int damping = 0);
-hipError_t launch_bisect(const double* w, const double* x_tab, int M, DevScalars* s, int mode,
+// scratch: M doubles of device memory, free during the call (the Fermi table's buffer)
+hipError_t launch_bisect(const double* w, const double* x_tab, int M, DevScalars* s, int mode, double* scratch,
                          hipStream_t st);
 
 // ---- block sums and Gram contractions (k_combine.hip)
@@ -191,8 +192,6 @@ hipError_t launch_batch_shift(const BatchDims& d, const BatchProblem* tab, const
 hipError_t launch_batch_patch(const BatchDims& d, const BatchProblem* tab, void* final_descs, hipStream_t st);
 hipError_t launch_batch_moments(const BatchDims& d, const BatchGeom* geo, const void* mats, double* trb,
                                 double* partial, int gram_blocks, double* gram, double* tau, hipStream_t st);
-hipError_t launch_batch_bisect(const BatchDims& d, const double* tau, const int64_t* mq, double* w, double* x,
-                               DevScalars* s, hipStream_t st);
 hipError_t launch_batch_coeffs(const BatchDims& d, const int64_t* mq, const DevScalars* s, double* ftab, double* c,
                                double* coef, hipStream_t st);
 hipError_t launch_batch_combine(const BatchDims& d, const BatchGeom* geo, const double* coef, void* mats,
@@ -216,6 +215,8 @@ hipError_t launch_mlp_adam(float* w, const float* g, float* m, float* v, int64_t
 // verify [mu_hat - delta, mu_hat + delta], Newton inside it, else bisection on [-1, 1]
 hipError_t launch_batch_features(const BatchDims& d, const BatchGeom* geo, const double* tau, const DevScalars* s,
                                  float* feat, hipStream_t st);
+// scratch: count x mcap doubles of device memory, free during the call
 hipError_t launch_batch_search(const BatchDims& d, const double* tau, const int64_t* mq, double* w, double* x,
-                               DevScalars* s, int mode, const float* mu_hat, double delta, hipStream_t st);
+                               DevScalars* s, int mode, const float* mu_hat, double delta, double* scratch,
+                               hipStream_t st);
 }  // namespace chebdm

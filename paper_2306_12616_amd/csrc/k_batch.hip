@@ -348,13 +348,13 @@ constexpr int kBisect = 512;
 __global__ void __launch_bounds__(kBisect)
 k_batch_search(const int64_t* __restrict__ mq, int64_t mcap, const double* __restrict__ w,
                const double* __restrict__ x, DevScalars* s, int mode, const float* __restrict__ mu_hat,
-               double delta) {
+               double delta, double* __restrict__ scratch) {
     __shared__ double smem[kBisect / 64];
     const int p = blockIdx.x;
     DevScalars& d = s[p];
     if (d.status != 0) return;
     const double guess = mode == 2 ? (double)mu_hat[p] : 0.0;
-    mu_search_one<kBisect>(mq[p], w + p * mcap, x + p * mcap, d, mode, guess, delta, smem);
+    mu_search_one<kBisect>(mq[p], w + p * mcap, x + p * mcap, d, mode, guess, delta, smem, scratch + p * mcap);
 }
 
 // network inputs of problem p: tau_1..tau_62 / n, N_e / n, log(beta') / 4
@@ -641,17 +641,13 @@ hipError_t launch_batch_moments(const BatchDims& d, const BatchGeom* geo, const 
     return moments_t<float>(d, geo, (const float*)mats, trb, partial, gram_blocks, gram, tau, st);
 }
 
-hipError_t launch_batch_bisect(const BatchDims& d, const double* tau, const int64_t* mq, double* w, double* x,
-                               DevScalars* s, hipStream_t st) {
-    return launch_batch_search(d, tau, mq, w, x, s, 0, nullptr, 0.0, st);
-}
-
 hipError_t launch_batch_search(const BatchDims& d, const double* tau, const int64_t* mq, double* w, double* x,
-                               DevScalars* s, int mode, const float* mu_hat, double delta, hipStream_t st) {
+                               DevScalars* s, int mode, const float* mu_hat, double delta, double* scratch,
+                               hipStream_t st) {
     hipLaunchKernelGGL(k_batch_dct3, dim3((unsigned)((d.mcap + 255) / 256), (unsigned)d.count), dim3(256),
                        sizeof(double) * (size_t)(d.order + 1), st, tau, d.order, mq, d.mcap, w, x, d.damping);
     hipLaunchKernelGGL(k_batch_search, dim3((unsigned)d.count), dim3(kBisect), 0, st, mq, d.mcap, (const double*)w,
-                       (const double*)x, s, mode, mu_hat, delta);
+                       (const double*)x, s, mode, mu_hat, delta, scratch);
     return hipGetLastError();
 }
 

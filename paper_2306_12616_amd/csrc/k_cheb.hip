@@ -186,11 +186,13 @@ k_dct3(const double* __restrict__ tau, int order, int64_t M, double* __restrict_
 
 constexpr int kBisectThreads = 1024;
 
-// mu search of one problem (modes 0 bisection / 1 safeguarded Newton, search_dev.h)
+// mu search of one problem (modes 0 bisection / 1 safeguarded Newton, search_dev.h); scratch:
+// M doubles for the tail sums
 __global__ void __launch_bounds__(kBisectThreads)
-k_bisect(const double* __restrict__ w, const double* __restrict__ x, int64_t M, DevScalars* s, int mode) {
+k_bisect(const double* __restrict__ w, const double* __restrict__ x, int64_t M, DevScalars* s, int mode,
+         double* __restrict__ scratch) {
     __shared__ double smem[kBisectThreads / 64];
-    mu_search_one<kBisectThreads>(M, w, x, *s, mode, 0.0, 0.0, smem);
+    mu_search_one<kBisectThreads>(M, w, x, *s, mode, 0.0, 0.0, smem, scratch);
 }
 
 }  // namespace
@@ -255,10 +257,10 @@ hipError_t launch_dct3(const double* tau, int order, int M, double* w, double* x
     return hipGetLastError();
 }
 
-hipError_t launch_bisect(const double* w, const double* x_tab, int M, DevScalars* s, int mode,
+hipError_t launch_bisect(const double* w, const double* x_tab, int M, DevScalars* s, int mode, double* scratch,
                          hipStream_t st) {
     if (mode < 0 || mode > 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_bisect, dim3(1), dim3(kBisectThreads), 0, st, w, x_tab, (int64_t)M, s, mode);
+    hipLaunchKernelGGL(k_bisect, dim3(1), dim3(kBisectThreads), 0, st, w, x_tab, (int64_t)M, s, mode, scratch);
     return hipGetLastError();
 }
 

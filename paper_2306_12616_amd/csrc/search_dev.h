@@ -30,21 +30,96 @@ namespace {
 // The nodes are ordered in x, so whole wavefronts skip the exponential except near mu~.
 constexpr double kSat = 50.0;
 
-// Nodes j = threadIdx.x + i NT in increasing i; the loads of U consecutive i are issued
-// together (the search is a chain of dependent passes, so load latency is what it waits on).
-// Slots past M add w = 0 with an in-range x, which leaves the sum unchanged.
+// Saturated tails by blocks of kQBlock consecutive nodes.  The nodes x_j = cos(pi (j + 1/2) / M)
+// fall with j, so for a given mu~ the nodes split into a head (z > kSat: skipped), a window and a
+// tail (z < -kSat: occupation exactly 1).  tail_sums stores in blk[b] the sum of w over blocks
+// b..nb-1 (blk[nb] = 0), once per search; a pass then visits only the blocks that meet the window
+// (found from arccos of its ends, widened by two nodes) and adds the tail as one suffix sum.  It
+// classifies every node as the full pass does, so only the order of the additions changes.
+constexpr int kQBlock = 256;
+
+// blk: nb + 1 doubles of global scratch, nb = ceil(M / kQBlock).  Deterministic.
+template <int NT>
+__device__ void tail_sums(const double* __restrict__ w, int64_t M, double* __restrict__ blk) {
+    __shared__ double chunk[NT];
+    const int64_t nb = (M + kQBlock - 1) / kQBlock;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int64_t b = wid; b < nb; b += NT / 64) {   // one wavefront per block
+        double v = 0.0;
+#pragma unroll
+        for (int u = 0; u < kQBlock / 64; ++u) {
+            const int64_t j = b * kQBlock + u * 64 + lane;
+            v += j < M ? w[j] : 0.0;
+        }
+        v = wave_sum(v);
+        if (lane == 0) blk[b] = v;
+    }
+    __syncthreads();
+    // suffix sums: thread i owns blocks [i C, (i + 1) C)
+    const int64_t C = (nb + NT - 1) / NT, b0 = threadIdx.x * C, b1 = b0 + C < nb ? b0 + C : nb;
+    double own = 0.0;
+    for (int64_t b = b0; b < b1; ++b) own += blk[b];
+    chunk[threadIdx.x] = own;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = NT - 1; i >= 0; --i) {
+            const double v = chunk[i];
+            chunk[i] = s;   // sum over the chunks after i
+            s += v;
+        }
+    }
+    __syncthreads();
+    double s = chunk[threadIdx.x];
+    for (int64_t b = b1 - 1; b >= b0; --b) {
+        s += blk[b];
+        blk[b] = s;
+    }
+    if (threadIdx.x == 0) blk[nb] = 0.0;
+    __syncthreads();
+}
+
+// Node range [j0, j1) of the blocks that meet the window of mu~, and the tail sum past it.
+__device__ inline void pass_window(double mu_s, double beta_s, int64_t M, const double* __restrict__ blk,
+                                   int64_t& j0, int64_t& j1, double& tail) {
+    const double a = mu_s - kSat / beta_s, b = mu_s + kSat / beta_s;
+    const double per = (double)M / 3.141592653589793;   // nodes per radian of theta
+    int64_t jhi = M - 1, jlo = 0;                       // x_j < a for j > jhi, x_j > b for j < jlo
+    if (a > -1.0) {
+        const double v = floor(acos(a) * per - 0.5) + 2.0;
+        if (v < (double)(M - 1)) jhi = v < 0.0 ? 0 : (int64_t)v;
+    }
+    if (b < 1.0) {
+        const double v = ceil(acos(b) * per - 0.5) - 2.0;
+        if (v > 0.0) jlo = v > (double)(M - 1) ? M - 1 : (int64_t)v;
+    }
+    if (jlo > jhi) jlo = jhi;
+    const int64_t bl = jlo / kQBlock, bh = jhi / kQBlock;
+    j0 = bl * kQBlock;
+    j1 = (bh + 1) * kQBlock < M ? (bh + 1) * kQBlock : M;
+    tail = blk[bh + 1];
+}
+
+// Nodes j = j0 + threadIdx.x + i NT in increasing i, below j1; the loads of U consecutive i are
+// issued together (the search is a chain of dependent passes, so load latency is what it waits
+// on).  Slots past j1 add w = 0 with an in-range x, which leaves the sum unchanged.  tail is
+// added to t once.
 template <int NT, bool SLOPE>
 __device__ __forceinline__ void trace_pass(double mu_s, const double* __restrict__ w, const double* __restrict__ x,
-                                           int64_t M, double beta_s, double* smem, double& t, double& dt) {
+                                           int64_t M, double beta_s, double* smem, double& t, double& dt,
+                                           const double* __restrict__ blk = nullptr) {
     constexpr int U = 4;
-    double acc = 0.0, accd = 0.0;
-    for (int64_t j = threadIdx.x; j < M; j += (int64_t)U * NT) {
+    int64_t j0 = 0, j1 = M;
+    double tail = 0.0;
+    if (blk) pass_window(mu_s, beta_s, M, blk, j0, j1, tail);
+    double acc = threadIdx.x == 0 ? tail : 0.0, accd = 0.0;
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += (int64_t)U * NT) {
         double xs[U], ws[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t jj = j + (int64_t)u * NT;
-            xs[u] = jj < M ? x[jj] : 0.0;
-            ws[u] = jj < M ? w[jj] : 0.0;
+            xs[u] = jj < j1 ? x[jj] : 0.0;
+            ws[u] = jj < j1 ? w[jj] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -62,10 +137,16 @@ __device__ __forceinline__ void trace_pass(double mu_s, const double* __restrict
     dt = SLOPE ? block_sum<NT>(accd, smem) / (double)M : 0.0;
 }
 
-// Writes mu_s, trace, iters, evals, learned, status, lo, hi of d (thread 0).
+// Writes mu_s, trace, iters, evals, learned, status, lo, hi of d (thread 0).  scratch: nullptr,
+// or M doubles of global memory for the tail sums (used from M >= 4 kQBlock on).
 template <int NT>
 __device__ void mu_search_one(int64_t M, const double* __restrict__ w, const double* __restrict__ x, DevScalars& d,
-                              int mode, double guess, double delta, double* smem) {
+                              int mode, double guess, double delta, double* smem, double* scratch = nullptr) {
+    const double* blk = nullptr;
+    if (scratch && M >= 4 * kQBlock) {
+        tail_sums<NT>(w, M, scratch);
+        blk = scratch;
+    }
     const double beta_s = d.beta_s, ne = d.n_elec, tol = d.tol;
     const int max_iter = d.max_iter;
     int evals = 0, learned = 0, iters = 0, status = CHEBDM_WARN_NOCONV;
@@ -76,8 +157,8 @@ __device__ void mu_search_one(int64_t M, const double* __restrict__ w, const dou
         g = fmin(fmax(g, -1.0), 1.0);
         lo = fmax(-1.0, g - delta);
         hi = fmin(1.0, g + delta);
-        trace_pass<NT, false>(lo, w, x, M, beta_s, smem, t_lo, unused);
-        trace_pass<NT, false>(hi, w, x, M, beta_s, smem, t_hi, unused);
+        trace_pass<NT, false>(lo, w, x, M, beta_s, smem, t_lo, unused, blk);
+        trace_pass<NT, false>(hi, w, x, M, beta_s, smem, t_hi, unused, blk);
         evals += 2;
         if (t_lo < ne && ne < t_hi) {
             bracketed = true;
@@ -89,8 +170,8 @@ __device__ void mu_search_one(int64_t M, const double* __restrict__ w, const dou
     if (!bracketed) {
         lo = -1.0;
         hi = 1.0;
-        trace_pass<NT, false>(lo, w, x, M, beta_s, smem, t_lo, unused);
-        trace_pass<NT, false>(hi, w, x, M, beta_s, smem, t_hi, unused);
+        trace_pass<NT, false>(lo, w, x, M, beta_s, smem, t_lo, unused, blk);
+        trace_pass<NT, false>(hi, w, x, M, beta_s, smem, t_hi, unused, blk);
         evals += 2;
         if (!(t_lo < ne && ne < t_hi)) {
             if (threadIdx.x == 0) {
@@ -109,7 +190,7 @@ __device__ void mu_search_one(int64_t M, const double* __restrict__ w, const dou
     if (mode == 0 || (mode == 2 && !learned)) {
         for (int it = 1; it <= max_iter; ++it) {
             mid = 0.5 * (lo + hi);
-            trace_pass<NT, false>(mid, w, x, M, beta_s, smem, t_mid, unused);
+            trace_pass<NT, false>(mid, w, x, M, beta_s, smem, t_mid, unused, blk);
             iters = it;
             if (fabs(t_mid - ne) < tol) {
                 status = CHEBDM_OK;
@@ -123,7 +204,7 @@ __device__ void mu_search_one(int64_t M, const double* __restrict__ w, const dou
         mid = mu0;
         for (int it = 1; it <= max_iter; ++it) {
             double dt;
-            trace_pass<NT, true>(mid, w, x, M, beta_s, smem, t_mid, dt);
+            trace_pass<NT, true>(mid, w, x, M, beta_s, smem, t_mid, dt, blk);
             iters = it;
             if (fabs(t_mid - ne) < tol) {
                 status = CHEBDM_OK;

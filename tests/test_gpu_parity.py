@@ -230,6 +230,9 @@ MU_CASES = [
     (200, "gaussmix6", 80, 20.0, 100.5, "four_chains", "bisection"),
     (257, "highdos", 99, 40.0, 128.5, "four_chains", "newton"),
     (300, "gaussmix6", 512, 80.0, 150.5, "four_chains", "bisection"),
+    # the search's node window at both extremes: beta' ~ 10 (every node inside) and ~ 10^4
+    (300, "uniform", 64, 1.0, 150.5, "composition", "bisection"),
+    (400, "highdos", 1024, 400.0, 200.5, "composition", "newton"),
 ]
 
 
