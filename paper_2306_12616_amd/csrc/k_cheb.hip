@@ -162,26 +162,38 @@ k_assemble_moments(const double* __restrict__ tr_baby, const double* __restrict_
     }
 }
 
-// w_j = sum_n (2 - delta_{n0}) tau_n cos(n theta_j); also stores x_j.
+// w_j = sum_n (2 - delta_{n0}) tau_n cos(n theta_j); also stores x_j.  kDctSplit neighbouring
+// lanes share node j, lane s summing n = s, s + kDctSplit, ...; the partial sums combine by two
+// shuffles in a fixed order.  64 nodes per work-group.
+constexpr int kDctSplit = 4;
+
 __global__ void __launch_bounds__(256)
 k_dct3(const double* __restrict__ tau, int order, int64_t M, double* __restrict__ w,
        double* __restrict__ x_tab, int damping) {
+    static_assert(kDctSplit == 4, "two shuffle steps");
     extern __shared__ double st[];
     // with damping, t(mu~) = sum_n g_n c_n(mu~) tau_n: the factors go onto the moments
     for (int i = threadIdx.x; i <= order; i += 256) st[i] = tau[i] * damping_factor(damping, i, order);
     __syncthreads();
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= M) return;
-    const int64_t mod = 4 * M, q1 = 2 * j + 1;
-    double acc = st[0];
-    int64_t q = 0;
-    for (int nn = 1; nn <= order; ++nn) {
-        q += q1;
-        if (q >= mod) q -= mod;
-        acc += 2.0 * st[nn] * node_cos(q, M);
+    const int s = threadIdx.x % kDctSplit;
+    const int64_t j = ((int64_t)blockIdx.x * 256 + threadIdx.x) / kDctSplit;
+    const bool live = j < M;   // no early exit: every lane takes part in the shuffles
+    const int64_t mod = 4 * M, q1 = 2 * j + 1, step = (kDctSplit * q1) % mod;
+    double acc = 0.0;
+    if (live) {
+        int64_t q = (s * q1) % mod;   // n q1 mod 4M for n = s
+        for (int nn = s; nn <= order; nn += kDctSplit) {
+            acc += nn == 0 ? st[0] : 2.0 * st[nn] * node_cos(q, M);
+            q += step;
+            if (q >= mod) q -= mod;
+        }
     }
-    w[j] = acc;
-    x_tab[j] = node_cos(q1, M);
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    if (live && s == 0) {
+        w[j] = acc;
+        x_tab[j] = node_cos(q1, M);
+    }
 }
 
 constexpr int kBisectThreads = 1024;
@@ -252,7 +264,8 @@ hipError_t launch_assemble_moments(const double* tr_baby, const double* gram, in
 hipError_t launch_dct3(const double* tau, int order, int M, double* w, double* x_tab,
                        hipStream_t st, int damping) {
     const size_t shmem = sizeof(double) * (size_t)(order + 1);
-    hipLaunchKernelGGL(k_dct3, dim3((unsigned)((M + 255) / 256)), dim3(256), shmem, st, tau, order,
+    const int64_t threads = (int64_t)M * kDctSplit;
+    hipLaunchKernelGGL(k_dct3, dim3((unsigned)((threads + 255) / 256)), dim3(256), shmem, st, tau, order,
                        (int64_t)M, w, x_tab, damping);
     return hipGetLastError();
 }
