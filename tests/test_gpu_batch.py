@@ -159,6 +159,35 @@ def test_batch_tuner_and_cache(cd, handle, tmp_path):
     batch2.close()
 
 
+def test_batch_schedules_agree_bitwise(cd, handle, tmp_path):
+    # the tuner's item orders (by decreasing n, input order) only move tiles between
+    # work-groups; every tile's arithmetic stays the same, so mu and D agree bit for bit
+    sizes = [96, 300, 600, 900, 130, 257] * 3
+    probs, Hs = _make(sizes, 1700)
+    betas = [30.0 + i for i in range(len(sizes))]
+    nes = [0.5 * n for n in sizes]
+    cache = str(tmp_path / "tune.txt")
+    b0 = cd.Batch(handle, sizes, 64, cd.make_opts("fp32"))
+    _say("tune: " + b0.tune(cache))
+    b0.close()
+    key = open(cache).read().split()[0]
+    out = []
+    for order in (0, 1):
+        with open(cache, "w") as f:
+            f.write(f"{key} tiles=64,64,64,64 order={order}\n")
+        b = cd.Batch(handle, sizes, 64, cd.make_opts("fp32"))
+        rep = b.tune(cache)
+        assert rep.startswith("loaded") and f"order={order}" in rep, rep
+        mu, Ds, status, *_ = b.mu_search(Hs, betas, nes)
+        assert np.all(status == 0)
+        out.append((np.array(mu), [d.cpu().numpy() for d in Ds]))
+        b.close()
+    for mu, Ds in out[1:]:
+        assert np.array_equal(mu, out[0][0])
+        for a, c in zip(Ds, out[0][1]):
+            assert np.array_equal(a, c)
+
+
 def test_batch_512_uneven_workload_sampled(cd, handle):
     # 512 problems, n uniform on {96, 128, ..., 1024}, beta on [30, 200], order 256, float32
     sizes, betas = synth.batch_problems(512, seed=3000)
