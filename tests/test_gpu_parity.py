@@ -370,6 +370,19 @@ def test_reduced_precision_ladder_schedules(cd, handle, prec):
         assert res["auto"][:2] == res["sequential"][:2]
 
 
+@pytest.mark.parametrize("order", [3, 8, 15, 24, 35])   # k = 2..6: the sequential fallback and the first chains
+def test_odd_chains_small_orders_match_oracle(cd, handle, order):
+    n = 150
+    _say(f"odd chains n={n} order={order}")
+    h, q, lam = synth.hamiltonian(n, "gaussmix6", seed=60 + order)
+    D, info = cd.chebdm_density(handle, _dev(h), 20.0, 0.05, order, cd.make_opts("fp64", baby="odd_chains"))
+    torch.cuda.synchronize()
+    ref, _ = _oracle_density(q, lam, order, 20.0, 0.05, info["emin"], info["emax"], info["n_quad"])
+    err = np.max(np.abs(D.cpu().numpy() - ref))
+    _say(f"  k={info['k']} max|D - D_oracle| = {err:.3e}")
+    assert err <= 1e-10
+
+
 @pytest.mark.parametrize("bounds", ["gershgorin", "lanczos"])
 def test_float32_baby_schedules(cd, handle, bounds):
     # float32 baby steps default to odd chains: as accurate as the sequential order (within a
