@@ -78,7 +78,7 @@ struct Plan {
     int search = CHEBDM_SEARCH_BISECTION;
     int damping = CHEBDM_DAMPING_NONE;
     int bounds = CHEBDM_BOUNDS_GERSHGORIN, lz_steps = 40;
-    int chains = 0;    // composition form: 0 library's choice, 1 or 2 chains
+    int chains = 0;    // composition form: 0 library's choice, 1, 2 or 4 chains
     int split_h = 0;   // > 0: giant steps as two Clenshaw chains joined by T_h(T_k) (extra slot k + m)
     int split_q = 0;   // > 0: each half split again at q, joined by T_q(T_k) (extra slot k + m + 1)
     double lz_margin = 0.01;
