@@ -283,6 +283,7 @@ hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
     const int64_t t64 = (n + 63) / 64;
     const int64_t w64 = t64 * (t64 + 1) / 2 * b.count;
     const bool fits48 = (n + 47) / 48 * 48 <= ld;
+    const int64_t t48 = (n + 47) / 48, w48 = t48 * (t48 + 1) / 2 * b.count;
     // With at least one full round of 64-tiles (w64 >= 1024) the unsplit 64-tile kernel with the
     // tail split wins (N = 2000, TFLOP/s, two / four / eight products: float64 48.8 / 53.1 / 55.7
     // against 46.3 / 46.6 / 51.7 for 48-tiles; float32 82.6 / 96.7 / 106.7 against 61.6 / 58.0 /
@@ -294,9 +295,20 @@ hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
                 return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st, scratch, scratch_bytes);
             return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st, scratch, scratch_bytes);
         }
-        if (fits48 && w64 < 300) return launch_cfg<P, 48, 1, 1, KU, 1, 4>(b, n, ld, st, scratch, scratch_bytes);
+        // 48-tiles while about one round of them (one wavefront per SIMD) holds the launch; past
+        // that, up to one round of 64-tiles beats two rounds of 48-tiles (N = 1000, six / seven
+        // products: 0.147 against 0.183 / 0.185 ms; N = 1500, three: 0.211 against 0.264)
+        if (fits48 && w48 <= 1200) {
+            if (w64 < 300) return launch_cfg<P, 48, 1, 1, KU, 1, 4>(b, n, ld, st, scratch, scratch_bytes);
+            return launch_cfg<P, 48, 1, 1, KU, 1, 1>(b, n, ld, st, scratch, scratch_bytes);
+        }
+        if (!fits48 && w64 < 400) return launch_cfg<P, 64, 1, 1, KU, 1, 4>(b, n, ld, st, scratch, scratch_bytes);
+        if (w64 <= 1024) {
+            if (k_split_quantises_better(w64, 1.10))
+                return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st, scratch, scratch_bytes);
+            return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st, scratch, scratch_bytes);
+        }
         if (fits48) return launch_cfg<P, 48, 1, 1, KU, 1, 1>(b, n, ld, st, scratch, scratch_bytes);
-        if (w64 < 400) return launch_cfg<P, 64, 1, 1, KU, 1, 4>(b, n, ld, st, scratch, scratch_bytes);
         return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st, scratch, scratch_bytes);
     } else if constexpr (P == P_F32) {
         if (w64 >= 1024) {
@@ -304,8 +316,13 @@ hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
                 return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st, scratch, scratch_bytes);
             return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st, scratch, scratch_bytes);
         }
-        if (fits48) return launch_cfg<P, 48, 1, 1, KU, 1, 2, 0, 16, 2>(b, n, ld, st, scratch, scratch_bytes);
-        return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st, scratch, scratch_bytes);
+        // 48-tiles split over two wavefronts while one round of them holds the launch; past that
+        // 64-tiles (N = 1000, five / six / seven products: 0.077 / 0.082 / 0.084 against 0.093 /
+        // 0.108 / 0.132 ms; N = 1500, two / three: 0.110 / 0.118 against 0.132 / 0.186), split
+        // over two wavefronts only while that still fits one round
+        if (fits48 && w48 <= 1024) return launch_cfg<P, 48, 1, 1, KU, 1, 2, 0, 16, 2>(b, n, ld, st, scratch, scratch_bytes);
+        if (w64 < 512) return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st, scratch, scratch_bytes);
+        return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st, scratch, scratch_bytes);
     } else {
         // LDS staging (each element split once per work-group, panels two K steps ahead) once
         // there are >= 100 128-tiles: three-term split at N = 4000 390 -> 563 TFLOP/s of bf16
