@@ -337,15 +337,15 @@ hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
         if constexpr (P == P_BF16X3) {
             if (w128 >= 100) return launch_lds<P, 1, 0, 2, 0, 1, 2, 0>(b, n, ld, st, sc, sv);
         } else {
-            if (w128 >= 100) return launch_lds<P, 1, 0, 2, 0, 1, 1, 0>(b, n, ld, st, sc, sv);
+            // (N = 1000, three products, 108 128-tiles: 0.068 ms against 0.058 for split 64-tiles)
+            if (w128 >= 120) return launch_lds<P, 1, 0, 2, 0, 1, 1, 0>(b, n, ld, st, sc, sv);
         }
-        // the smallest three-term launches on 48-tiles split over two wavefronts (N = 1000, one /
-        // two products: 0.022 / 0.034 ms against 0.035 / 0.048 for split 64-tiles; N = 1500, one
-        // product of 528 48-tiles: 0.067 against 0.063)
-        if constexpr (P == P_BF16X3) {
-            if (fits48 && w48 <= 500)
-                return launch_cfg<P, 48, 1, 1, KU, 1, 2, 0, 16, 2>(b, n, ld, st, scratch, scratch_bytes);
-        }
+        // the smallest launches on 48-tiles split over two wavefronts (N = 1000, one / two
+        // products: three-term 0.022 / 0.034 ms, six-term 0.029 / 0.041, against 0.035 / 0.048 and
+        // 0.045 / 0.057 for split 64-tiles; N = 1500, one product of 528 48-tiles: 0.067 and 0.082
+        // against 0.063 and 0.074)
+        if (fits48 && w48 <= 500)
+            return launch_cfg<P, 48, 1, 1, KU, 1, 2, 0, 16, 2>(b, n, ld, st, scratch, scratch_bytes);
         // below a full round of 64-tiles the K split over two wavefronts fills the chip better
         // (N = 1500, mu search + D: six-term 148 -> 192 DM/s, three-term 217 -> 223)
         if (w64 < 1024) return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st, scratch, scratch_bytes);
