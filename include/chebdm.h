@@ -300,7 +300,7 @@ int chebdm_mu_search(chebdm_handle h, const double* dH, int64_t n, int64_t ldh,
  * k + m + 2 where the giant steps go in four chains: they also keep T_q(T_k))
  * with ld = round_up(n, 128) and 8 (float64) or 4 bytes per element, plus the
  * small buffers sized for opts->n_quad quadrature nodes (2^16 when 0), plus
- * 32 MB of product scratch (partial sums of K-sliced product tiles).
+ * 64 MB of product scratch (partial sums of K-sliced product tiles).
  * Needs no device; h may be NULL.  ERR_ARG on bad sizes or options.
  */
 int chebdm_workspace_size(chebdm_handle h, int64_t n, int32_t order, const chebdm_opts* opts,

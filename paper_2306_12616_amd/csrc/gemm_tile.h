@@ -419,5 +419,38 @@ __device__ __forceinline__ void gemm_tile_fix(const GemmDesc<typename Traits<P>:
 }
 
 
+// Sum of the K pieces of tile (ti, tj) held in slots slot_of(0) .. slot_of(count - 1) of part
+// (slots of slice_accs<P, BM, 1, 1>() accumulators; a negative slot is skipped), in that order,
+// then the tile's epilogue, by one wavefront.
+template <int P, int BM, int RB, class SlotOf>
+__device__ __forceinline__ void gemm_tile_fix_slots(const GemmDesc<typename Traits<P>::T>& g, int64_t n, int64_t ld,
+                                                    int ti, int tj, const typename Traits<P>::Acc* part, int count,
+                                                    SlotOf slot_of) {
+    using Acc = typename Traits<P>::Acc;
+    constexpr int FM = BM / 16, FN = BM / 16;
+    const int lane = threadIdx.x & 63;
+    const int lr = lane & 15, lq = lane >> 4;
+    Acc acc[FM][FN];
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int q = 0; q < FN; ++q) acc[f][q] = Acc{};
+    for (int i = 0; i < count; ++i) {
+        const int64_t slot = slot_of(i);
+        if (slot < 0) continue;
+        const Acc* src = part + slot * slice_accs<P, BM, 1, 1>();
+        Acc v[FM][FN];
+#pragma unroll
+        for (int f = 0; f < FM; ++f)
+#pragma unroll
+            for (int q = 0; q < FN; ++q) v[f][q] = src[(f * FN + q) * 64 + lane];
+#pragma unroll
+        for (int f = 0; f < FM; ++f)
+#pragma unroll
+            for (int q = 0; q < FN; ++q) acc[f][q] += v[f][q];
+    }
+    tile_epilogue<P, FM, FN, (RB < FM ? RB : FM)>(g, acc, n, ld, (int64_t)ti * BM, (int64_t)tj * BM, ti == tj, lr, lq);
+}
+
 }  // namespace
 }  // namespace chebdm

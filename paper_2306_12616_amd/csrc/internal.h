@@ -118,8 +118,9 @@ hipError_t launch_gram(const T* const* lmats, int nl, const T* const* tmats, int
 
 // ---- matrix products (k_gemm.hip)
 // scratch (nullable; kGemmScratchBytes is enough): partial accumulators of the K-sliced tiles
-// of a launch's last, nearly empty round (without scratch the launch runs unsplit)
-constexpr size_t kGemmScratchBytes = (size_t)32 << 20;
+// of a launch's last, nearly empty round, or the pieces of stream-K launches (without scratch the launch
+// runs unsplit)
+constexpr size_t kGemmScratchBytes = (size_t)64 << 20;
 hipError_t launch_gemm_f64(const GemmBatch<double>& b, int64_t n, int64_t ld, hipStream_t st,
                            void* scratch = nullptr, size_t scratch_bytes = 0);
 // split: 0 float32 MFMA, 1 bf16x3, 2 bf16x6

@@ -122,6 +122,92 @@ k_gemm_fix(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, 
                                        part + (int64_t)tile * nslice * slice_accs<P, BM, WGM, WGN>(), nslice);
 }
 
+// Stream-K launches of the one-wavefront register tiles.  The launch's W tiles times U K units
+// (2 CH each) are dealt in equal contiguous ranges to G resident work-groups, so the chip runs
+// W / G rounds of tile time instead of a whole number of them.  A tile inside one range runs
+// whole with its epilogue; a tile shared by several ranges leaves each piece's raw accumulators
+// in slot 2 r (the first tile of range r) or 2 r + 1 (its last), and a fix-up launch adds the
+// pieces in range order (fixed order: deterministic) and runs the epilogue.  Ranges go to
+// work-groups in XCD order, so neighbouring tiles share an XCD's L2.
+__device__ __forceinline__ int64_t sk_range_begin(int64_t total, int64_t r, int64_t G) { return total * r / G; }
+
+template <int P, int BM, int KU, int RB>
+__global__ void __launch_bounds__(64)
+k_gemm_sk(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, int64_t kpad, int ntile, int ntri,
+          int64_t units, int64_t total, typename Traits<P>::Acc* part) {
+    constexpr int CH = 4 * KU;
+    const int64_t G = gridDim.x, r = xcd_order((int)blockIdx.x, (int)gridDim.x);
+    const int64_t a = sk_range_begin(total, r, G), b = sk_range_begin(total, r + 1, G);
+    if (a == b) return;
+    const int64_t t0 = a / units, t1 = (b - 1) / units;
+    for (int64_t t = t0; t <= t1; ++t) {
+        const int64_t u0 = (a > t * units ? a : t * units) - t * units;
+        const int64_t u1 = (b < (t + 1) * units ? b : (t + 1) * units) - t * units;
+        int z, ti, tj;
+        lin_tile((int)t, ntri, ntile, z, ti, tj);
+        if (u0 == 0 && u1 == units) {
+            gemm_tile<P, BM, 1, 1, KU, 1, RB>(batch.d[z], n, ld, kpad, ti, tj);
+        } else {
+            const int64_t slot = 2 * r + (t == t0 ? 0 : 1);
+            gemm_tile<P, BM, 1, 1, KU, 1, RB>(batch.d[z], n, ld, kpad, ti, tj, u0 * 2 * CH, u1 * 2 * CH,
+                                              part + slot * slice_accs<P, BM, 1, 1>());
+        }
+    }
+}
+
+// One work-group per tile; tiles inside one range were finished by k_gemm_sk.
+template <int P, int BM, int RB>
+__global__ void __launch_bounds__(64)
+k_gemm_sk_fix(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, int ntile, int ntri, int64_t units,
+              int64_t total, int64_t G, const typename Traits<P>::Acc* part) {
+    const int64_t t = blockIdx.x;
+    // range holding iteration i: the largest r with total r / G <= i
+    const int64_t ra = ((t * units + 1) * G + total - 1) / total - 1;
+    const int64_t rb = (((t + 1) * units) * G + total - 1) / total - 1;
+    if (ra == rb) return;
+    int z, ti, tj;
+    lin_tile((int)t, ntri, ntile, z, ti, tj);
+    gemm_tile_fix_slots<P, BM, RB>(batch.d[z], n, ld, ti, tj, part, (int)(rb - ra + 1), [&](int i) -> int64_t {
+        const int64_t r = ra + i;
+        const int64_t a = sk_range_begin(total, r, G), b = sk_range_begin(total, r + 1, G);
+        if (a == b) return -1;
+        return 2 * r + (t == a / units ? 0 : 1);
+    });
+}
+
+// Stream-K launch over G = 1024 work-groups (one wavefront per SIMD).  sk_fits: the shapes fit,
+// the scratch holds 2 G pieces, and every range has at least four K units.
+constexpr int64_t kSkGroups = 1024;
+
+template <int P, int BM, int KU>
+bool sk_fits(int64_t n, int64_t ld, int count, size_t scratch_bytes) {
+    constexpr int CH = 4 * KU;
+    const int64_t kpad = (n + 2 * CH - 1) / (2 * CH) * (2 * CH);
+    if (kpad > ld || (n + BM - 1) / BM * BM > ld) return false;
+    const int64_t ntile = (n + BM - 1) / BM, W = ntile * (ntile + 1) / 2 * count;
+    const int64_t need = 2 * kSkGroups * slice_accs<P, BM, 1, 1>() * (int64_t)sizeof(typename Traits<P>::Acc);
+    return W * (kpad / (2 * CH)) >= 4 * kSkGroups && need <= (int64_t)scratch_bytes;
+}
+
+template <int P, int BM, int KU, int RB = 16>
+hipError_t launch_sk(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int64_t ld, hipStream_t st, void* scratch,
+                     size_t scratch_bytes) {
+    using Acc = typename Traits<P>::Acc;
+    constexpr int CH = 4 * KU;
+    constexpr int64_t G = kSkGroups;
+    if (!scratch || !sk_fits<P, BM, KU>(n, ld, b.count, scratch_bytes)) return hipErrorInvalidValue;
+    const int64_t kpad = (n + 2 * CH - 1) / (2 * CH) * (2 * CH);
+    const int ntile = (int)((n + BM - 1) / BM);
+    const int ntri = ntile * (ntile + 1) / 2;
+    const int64_t W = (int64_t)ntri * b.count, units = kpad / (2 * CH), total = W * units;
+    Acc* part = static_cast<Acc*>(scratch);
+    hipLaunchKernelGGL((k_gemm_sk<P, BM, KU, RB>), dim3((unsigned)G), dim3(64), 0, st, b, n, ld, kpad, ntile, ntri,
+                       units, total, part);
+    hipLaunchKernelGGL((k_gemm_sk_fix<P, BM, RB>), dim3((unsigned)W), dim3(64), 0, st, b, n, ld, ntile, ntri, units,
+                       total, G, (const Acc*)part);
+    return hipGetLastError();
+}
+
 // OCC: wavefronts per SIMD the kernel holds (from its register use); the chip's 1024 SIMDs then
 // keep 1024 OCC / (WGM WGN SK) work-groups resident.
 template <int P, int BM, int WGM, int WGN, int KU, int XCD, int SK = 1, int GB = 0, int RB = 16, int OCC = 1>
@@ -289,6 +375,16 @@ hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
     // against 46.3 / 46.6 / 51.7 for 48-tiles; float32 82.6 / 96.7 / 106.7 against 61.6 / 58.0 /
     // 60.9); below it the smaller 48-tiles fill the chip better (float64 N = 2000 single: 40.0
     // against 38.4 for split 64-tiles; N = 1000: 48-tiles, K split 4 ways up to 300 64-tiles).
+    // Stream-K from N = 1500 (K long enough for pieces) while the 64-tiles fill less than three
+    // rounds and leave the last one under 80 % full: one product at N = 1500 / 2000, float64
+    // 0.094 / 0.186 ms against 0.126 / 0.196, float32 0.067 / 0.111 against 0.088 / 0.135;
+    // three products at N = 2000, float32 0.257 against 0.294; no gain from three full rounds
+    // on (N = 2000, eight products) or with a nearly full last round (N = 4000, one product).
+    if constexpr (P == P_F64 || P == P_F32) {
+        if (n >= 1500 && scratch && w64 < 3 * 1024 && w64 % 1024 < 820 &&
+            sk_fits<P, 64, KU>(n, ld, b.count, scratch_bytes))
+            return launch_sk<P, 64, KU>(b, n, ld, st, scratch, scratch_bytes);
+    }
     if constexpr (P == P_F64) {
         if (w64 >= 1024 && n >= 1500) {
             if (k_split_quantises_better(w64, 1.10))

@@ -405,6 +405,25 @@ def test_float32_baby_schedules(cd, handle, bounds):
     assert res["auto"][0] <= 2.0 * res["sequential"][0]
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_stream_k_products_match_oracle(cd, handle, prec, tol):
+    # n = 1530: 300 64-tiles per product with a ragged edge (1530 = 23 * 64 + 58), so launches of
+    # one to nine products run as stream-K (K pieces shared between work-groups, summed by the
+    # fix-up launch); the whole D is held to the precision's bound against the oracle
+    n, order, beta = 1530, 120, 60.0
+    _say(f"stream-K products n={n} order={order} {prec}")
+    h, q, lam = synth.hamiltonian(n, "gaussmix6", seed=1530)
+    mu, D, info = cd.chebdm_mu_search(handle, _dev(h), beta, n / 2 + 0.5, order, cd.make_opts(prec))
+    torch.cuda.synchronize()
+    assert info["status"] == 0
+    ref, _ = _oracle_density(q, lam, order, beta, mu, info["emin"], info["emax"], info["n_quad"])
+    err = float(np.max(np.abs(D.cpu().numpy() - ref)))
+    _say(f"  mu={mu:.12f} max|D - D_oracle| = {err:.3e}")
+    assert err <= tol
+    Dn = D.cpu().numpy()
+    assert np.array_equal(Dn, Dn.T)
+
+
 def test_profile_counts_products(cd, handle):
     h, q, lam = synth.hamiltonian(300, "uniform", seed=31)
     H = _dev(h)
