@@ -327,18 +327,26 @@ k_batch_dct3(const double* __restrict__ tau, int order, const int64_t* __restric
     for (int i = threadIdx.x; i <= order; i += 256)
         st[i] = tau[(int64_t)p * (order + 1) + i] * damping_factor(damping, i, order);
     __syncthreads();
-    const int64_t M = mq[p], j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= M) return;
-    const int64_t mod = 4 * M, q1 = 2 * j + 1;
-    double acc = st[0];
-    int64_t q = 0;
-    for (int nn = 1; nn <= order; ++nn) {
-        q += q1;
-        if (q >= mod) q -= mod;
-        acc += 2.0 * st[nn] * node_cos(q, M);
+    // four neighbouring lanes share node j, lane s summing n = s, s + 4, ... (as k_dct3)
+    const int s = threadIdx.x & 3;
+    const int64_t M = mq[p], j = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 2;
+    const bool live = j < M;   // no early exit: every lane takes part in the shuffles
+    const int64_t mod = 4 * M, q1 = 2 * j + 1, step = (4 * q1) % mod;
+    double acc = 0.0;
+    if (live) {
+        int64_t q = (s * q1) % mod;
+        for (int nn = s; nn <= order; nn += 4) {
+            acc += nn == 0 ? st[0] : 2.0 * st[nn] * node_cos(q, M);
+            q += step;
+            if (q >= mod) q -= mod;
+        }
     }
-    w[p * mcap + j] = acc;
-    x[p * mcap + j] = node_cos(q1, M);
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    if (live && s == 0) {
+        w[p * mcap + j] = acc;
+        x[p * mcap + j] = node_cos(q1, M);
+    }
 }
 
 constexpr int kBisect = 512;
@@ -644,7 +652,7 @@ hipError_t launch_batch_moments(const BatchDims& d, const BatchGeom* geo, const 
 hipError_t launch_batch_search(const BatchDims& d, const double* tau, const int64_t* mq, double* w, double* x,
                                DevScalars* s, int mode, const float* mu_hat, double delta, double* scratch,
                                hipStream_t st) {
-    hipLaunchKernelGGL(k_batch_dct3, dim3((unsigned)((d.mcap + 255) / 256), (unsigned)d.count), dim3(256),
+    hipLaunchKernelGGL(k_batch_dct3, dim3((unsigned)((4 * d.mcap + 255) / 256), (unsigned)d.count), dim3(256),
                        sizeof(double) * (size_t)(d.order + 1), st, tau, d.order, mq, d.mcap, w, x, d.damping);
     hipLaunchKernelGGL(k_batch_search, dim3((unsigned)d.count), dim3(kBisect), 0, st, mq, d.mcap, (const double*)w,
                        (const double*)x, s, mode, mu_hat, delta, scratch);
