@@ -232,5 +232,41 @@ __device__ __forceinline__ void gemm_tile_lds_fix(const GemmDesc<float>& g, int6
                               lq);
 }
 
+// As gemm_tile_lds_fix, with the K pieces of the tile in slots slot_of(0) .. slot_of(count - 1)
+// of part (one 128 x 128 tile's partials, kSlicePart-sized, per slot; a negative slot is
+// skipped), added in that order.
+template <int P, class SlotOf>
+__device__ __forceinline__ void gemm_tile_lds_fix_slots(const GemmDesc<float>& g, int64_t n, int64_t ld, int ti,
+                                                        int tj, const f32x4* part, int count, SlotOf slot_of,
+                                                        int wave) {
+    constexpr int BM = 128;
+    const int lane = threadIdx.x & 63;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lr = lane & 15, lq = lane >> 4;
+    const bool diag_tile = ti == tj;
+    if (diag_tile && wm > wn) return;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[f][q] = f32x4{};
+    for (int i = 0; i < count; ++i) {
+        const int64_t slot = slot_of(i);
+        if (slot < 0) continue;
+        const f32x4* src = part + (slot * 4 + wave) * 16 * 64;
+        f32x4 v[4][4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[f][q] = src[(f * 4 + q) * 64 + lane];
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[f][q] += v[f][q];
+    }
+    tile_epilogue<P, 4, 4, 1>(g, acc, n, ld, (int64_t)ti * BM + wm * 64, (int64_t)tj * BM + wn * 64, diag_tile, lr,
+                              lq);
+}
+
 }  // namespace
 }  // namespace chebdm

@@ -298,6 +298,53 @@ k_gemm_lds_fix(const GemmBatch<float> batch, int64_t n, int64_t ld, int ntile, i
     gemm_tile_lds_fix<P>(batch.d[z], n, ld, ti, tj, part + (int64_t)tile * nslice * kSlicePart, nslice, wave);
 }
 
+// Stream-K launches of the LDS kernel (the scheme of k_gemm_sk): kLdsSlots resident work-groups
+// share the launch's tiles x K-step pairs in equal contiguous ranges; pieces of shared tiles
+// leave their partials (one tile's kSlicePart per slot) in slot 2 r or 2 r + 1 of range r, and
+// k_gemm_lds_sk_fix adds them in range order, one 64-thread work-group per wave tile.
+template <int P, int DEPTH, int PAD, int SWZ, int LDB, int IGLP>
+__global__ void __launch_bounds__(256)
+k_gemm_lds_sk(const GemmBatch<float> batch, int64_t n, int64_t ld, int64_t kpad, int ntile, int ntri, int64_t units,
+              int64_t total, f32x4* part) {
+    const int64_t G = gridDim.x, r = xcd_order((int)blockIdx.x, (int)gridDim.x);
+    const int64_t a = sk_range_begin(total, r, G), b = sk_range_begin(total, r + 1, G);
+    if (a == b) return;
+    const int64_t t0 = a / units, t1 = (b - 1) / units;
+    for (int64_t t = t0; t <= t1; ++t) {
+        const int64_t u0 = (a > t * units ? a : t * units) - t * units;
+        const int64_t u1 = (b < (t + 1) * units ? b : (t + 1) * units) - t * units;
+        int z, ti, tj;
+        lin_tile((int)t, ntri, ntile, z, ti, tj);
+        if (u0 == 0 && u1 == units) {
+            gemm_tile_lds<P, DEPTH, PAD, SWZ, LDB, IGLP>(batch.d[z], n, ld, kpad, ti, tj);
+        } else {
+            const int64_t slot = 2 * r + (t == t0 ? 0 : 1);
+            gemm_tile_lds<P, DEPTH, PAD, SWZ, LDB, IGLP>(batch.d[z], n, ld, kpad, ti, tj, 2 * u0, 2 * u1,
+                                                         part + slot * kSlicePart);
+        }
+        __syncthreads();   // the next tile's panels go into the same LDS stages
+    }
+}
+
+template <int P>
+__global__ void __launch_bounds__(64)
+k_gemm_lds_sk_fix(const GemmBatch<float> batch, int64_t n, int64_t ld, int ntile, int ntri, int64_t units,
+                  int64_t total, int64_t G, const f32x4* part) {
+    const int64_t t = (int64_t)blockIdx.x >> 2;
+    const int wave = (int)blockIdx.x & 3;
+    const int64_t ra = ((t * units + 1) * G + total - 1) / total - 1;
+    const int64_t rb = (((t + 1) * units) * G + total - 1) / total - 1;
+    if (ra == rb) return;
+    int z, ti, tj;
+    lin_tile((int)t, ntri, ntile, z, ti, tj);
+    gemm_tile_lds_fix_slots<P>(batch.d[z], n, ld, ti, tj, part, (int)(rb - ra + 1), [&](int i) -> int64_t {
+        const int64_t r = ra + i;
+        const int64_t a = sk_range_begin(total, r, G), b = sk_range_begin(total, r + 1, G);
+        if (a == b) return -1;
+        return 2 * r + (t == a / units ? 0 : 1);
+    }, wave);
+}
+
 // LDS layout: unpadded 64-byte rows with the 16-byte chunks of row r XOR-swizzled by
 // (r >> 1) & 3 (measured: 522 -> 570 TFLOP/s of bf16 work at N = 4000 against 8-element padding)
 // Rounds of tile work a launch of W tiles takes on S slots: full rounds, plus a small tail when
@@ -346,6 +393,29 @@ hipError_t launch_lds(const GemmBatch<float>& b, int64_t n, int64_t ld, hipStrea
                        0, st, b, n, ld, kpad, ntile, ntri, nmain, nslice, scratch);
     hipLaunchKernelGGL((k_gemm_lds_fix<P>), dim3((unsigned)(rest * 4)), dim3(64), 0, st, b, n, ld, ntile, ntri, nmain,
                        nslice, (const f32x4*)scratch);
+    return hipGetLastError();
+}
+
+// Stream-K over kLdsSlots work-groups: the shapes fit, the scratch holds 2 kLdsSlots tile
+// partials, and every range has at least four K-step pairs.
+inline bool lds_sk_fits(int64_t n, int64_t ld, int count, int64_t scratch_vec) {
+    const int64_t kpad = (n + 63) / 64 * 64, ntile = (n + 127) / 128;
+    if (kpad > ld || ntile * 128 > ld) return false;
+    const int64_t W = ntile * (ntile + 1) / 2 * count;
+    return W * (kpad / 64) >= 4 * (int64_t)kLdsSlots && 2 * (int64_t)kLdsSlots * kSlicePart <= scratch_vec;
+}
+
+template <int P, int DEPTH, int PAD, int SWZ, int LDB, int IGLP>
+hipError_t launch_lds_sk(const GemmBatch<float>& b, int64_t n, int64_t ld, hipStream_t st, f32x4* scratch,
+                         int64_t scratch_vec) {
+    if (!scratch || !lds_sk_fits(n, ld, b.count, scratch_vec)) return hipErrorInvalidValue;
+    const int64_t kpad = (n + 63) / 64 * 64;
+    const int ntile = (int)((n + 127) / 128), ntri = ntile * (ntile + 1) / 2;
+    const int64_t W = (int64_t)ntri * b.count, units = kpad / 64, total = W * units, G = kLdsSlots;
+    hipLaunchKernelGGL((k_gemm_lds_sk<P, DEPTH, PAD, SWZ, LDB, IGLP>), dim3((unsigned)G), dim3(256), 0, st, b, n, ld,
+                       kpad, ntile, ntri, units, total, scratch);
+    hipLaunchKernelGGL((k_gemm_lds_sk_fix<P>), dim3((unsigned)(W * 4)), dim3(64), 0, st, b, n, ld, ntile, ntri, units,
+                       total, G, (const f32x4*)scratch);
     return hipGetLastError();
 }
 
@@ -430,9 +500,16 @@ hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
         const int64_t t128 = (n + 127) / 128, w128 = t128 * (t128 + 1) / 2 * b.count;
         f32x4* sc = static_cast<f32x4*>(scratch);
         const int64_t sv = (int64_t)(scratch_bytes / sizeof(f32x4));
+        // stream-K on the LDS kernel from N = 1500 while the 128-tiles fill under 80 % of one round
+        // of kLdsSlots (mu search + D at N = 2000: three-term 194 -> 223 DM/s, six-term 130 ->
+        // 150); past one round the tail split is better (N = 4000, one product of 528 tiles,
+        // as stream-K: mu search + D 54 -> 41 DM/s)
+        const bool lds_sk = n >= 1500 && w128 < 410 && sc && lds_sk_fits(n, ld, b.count, sv);
         if constexpr (P == P_BF16X3) {
+            if (w128 >= 100 && lds_sk) return launch_lds_sk<P, 2, 0, 1, 2, 0>(b, n, ld, st, sc, sv);
             if (w128 >= 100) return launch_lds<P, 1, 0, 2, 0, 1, 2, 0>(b, n, ld, st, sc, sv);
         } else {
+            if (w128 >= 120 && lds_sk) return launch_lds_sk<P, 2, 0, 1, 1, 0>(b, n, ld, st, sc, sv);
             // (N = 1000, three products, 108 128-tiles: 0.068 ms against 0.058 for split 64-tiles)
             if (w128 >= 120) return launch_lds<P, 1, 0, 2, 0, 1, 1, 0>(b, n, ld, st, sc, sv);
         }
