@@ -422,7 +422,7 @@ def main():
         cases = [(1000, "fp64", "bisection"), (1000, "fp64", "newton"), (1000, "fp32", "bisection"),
                  (2000, "fp64", "bisection"), (2000, "fp32", "bisection"), (4000, "fp32", "bisection"),
                  (4000, "bf16x3", "bisection"), (4000, "bf16x6", "bisection"), (1000, "bf16x3", "bisection"),
-                 (4000, "fp64", "newton")]
+                 (2000, "bf16x3", "bisection"), (2000, "bf16x6", "bisection"), (4000, "fp64", "newton")]
         if args.prec != "fp64" or n != 4000:
             cases.append((4000, "fp64", "bisection"))
         seeds = {1000: 2000, 2000: 2001, 4000: 2002}
