@@ -27,17 +27,54 @@ if ROOT not in sys.path:
 METRIC = "density matrices/s and % MFMA peak at N=1000/4000 vs plain FP64 path"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}   # dense MFMA peaks of MI355X
 PEAK_HBM_GBS = 8000.0
+SEEDS = {1000: 2000, 2000: 2001, 4000: 2002}   # gaussmix6 workloads at order 512
+ALL_SECTIONS = ("breakdown", "fixed", "config", "lanczos", "accuracy", "diag", "batch", "learned")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def make_h(n, law, seed):
-    import synth
+class Inputs:
+    """Seeded Hamiltonians, drawn once per (n, law, seed): the host copy with the generator's
+    eigenpairs (kept for the oracle check after the timed work) and a resident device copy."""
 
-    h, q, lam = synth.hamiltonian(n, law, seed=seed)
-    return h
+    def __init__(self):
+        self.host = {}
+        self.dev = {}
+
+    def get(self, n, law, seed):
+        import torch
+
+        import synth
+
+        key = (int(n), law, int(seed))
+        if key not in self.dev:
+            log(f"generating H: n={n} law={law} seed={seed}")
+            self.host[key] = synth.hamiltonian(int(n), law, seed=int(seed))
+            self.dev[key] = torch.from_numpy(self.host[key][0]).to("cuda:0")
+        return self.dev[key]
+
+    def drop_device(self):
+        self.dev.clear()
+
+
+def band_rows(n, band=64):
+    """One row per 64-row band (tile row of the product grid), plus the first and last rows."""
+    rows = {0, n - 1}
+    for b, start in enumerate(range(0, n, band)):
+        stop = min(start + band, n)
+        rows.add(start + (b % 3) * (stop - 1 - start) // 2)
+    return sorted(rows)
+
+
+def check_record(row, key, order, beta, n_elec, mu, info, D):
+    """What the oracle check after the timed region needs: the sampled rows of D (host), mu and
+    the library's bounds; the error fields are written into `row` by attach_oracle_errors."""
+    rows = band_rows(key[0])
+    d_rows = D[rows].cpu().numpy() if D is not None else None
+    return {"row": row, "key": key, "order": order, "beta": beta, "n_elec": n_elec, "mu": mu,
+            "rows": rows, "d_rows": d_rows, "emin": info["emin"], "emax": info["emax"], "n_quad": info["n_quad"]}
 
 
 def timed(call, steps, warmup, cd=None, handle=None):
@@ -70,14 +107,30 @@ def timed(call, steps, warmup, cd=None, handle=None):
     return dt, prof, out
 
 
-def run_steps(cd, handle, H, beta, n_elec, order, opts, steps, warmup, want_density=True):
+def run_steps(cd, handle, H, beta, n_elec, order, opts, steps, warmup, want_density=True, with_out=False):
     import torch
 
     D = torch.empty_like(H) if want_density else None
     dt, prof, out = timed(lambda: cd.chebdm_mu_search(handle, H, beta, n_elec, order, opts,
                                                       want_density=want_density, D=D),
                           steps, warmup, cd, handle)
+    if with_out:
+        return dt, prof, out[2], out[0], D
     return dt, prof, out[2]
+
+
+def mu_search_row(cd, handle, inputs, key, beta, order, prec, search="bisection", steps=5, warmup=2):
+    """Timed mu search + density on one resident workload: the row and its oracle-check record."""
+    n = key[0]
+    H = inputs.get(*key)
+    dt, prof, info, mu, D = run_steps(cd, handle, H, beta, n / 2.0, order, cd.make_opts(prec, search=search),
+                                      steps, warmup, with_out=True)
+    r = roofline_of(prof, prec)
+    row = {"dm_per_s": round(steps / dt, 3), "ms_per_step": round(1e3 * dt / steps, 3),
+           "gemm_frac_of_peak": r["frac"] if r else None, "gemm_tflops": r["achieved"] if r else None,
+           "search_ms": round(prof["search_ms"] / steps, 3), "search_evals": info["iters"],
+           "products": info["n_gemm"], "status": info["status"]}
+    return row, check_record(row, key, order, beta, n / 2.0, mu, info, D)
 
 
 GEMM_SOURCES = ("paper_2306_12616_amd/csrc/gemm_tile.h", "paper_2306_12616_amd/csrc/k_gemm.hip")
@@ -142,7 +195,11 @@ def hbm_of(ms, nbytes):
     return round(nbytes / (ms * 1e-3) / 1e9, 1)
 
 
-def cpu_baseline(h_np, beta, n_elec, order, budget_s=10.0, max_reps=50):
+def cpu_baseline(h_np, beta, n_elec, order, reps=5, budget_s=30.0):
+    """The oracle's whole path on the host cores: one untimed warm-up, then the median of `reps`
+    timed runs (fewer if they would exceed the budget)."""
+    import statistics
+
     from oracle import chebyshev as ch
 
     try:
@@ -151,17 +208,124 @@ def cpu_baseline(h_np, beta, n_elec, order, budget_s=10.0, max_reps=50):
         cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:
         cores = os.cpu_count() or 1
-    reps, t0 = 0, time.perf_counter()
-    max_reps = max(max_reps, 1)
-    while reps < max_reps:
+    t0 = time.perf_counter()
+    ch.mu_search_density(h_np, beta, n_elec, order)
+    t_warm = time.perf_counter() - t0
+    times = []
+    while len(times) < reps and (not times or t_warm + sum(times) + times[-1] <= budget_s):
+        t1 = time.perf_counter()
         ch.mu_search_density(h_np, beta, n_elec, order)
-        reps += 1
-        if time.perf_counter() - t0 > budget_s:
+        times.append(time.perf_counter() - t1)
+    med = statistics.median(times)
+    return {"value": round(1.0 / med, 4), "unit": "density matrices/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"median of {len(times)} runs after 1 warm-up: full mu search + density at "
+                      f"N={h_np.shape[0]}, order {order} (oracle route: LAPACK eigh of H, moments, bisection, "
+                      f"Q p(lam) Q^T); runs {', '.join(f'{t:.2f}' for t in times)} s"}
+
+
+def attach_oracle_errors(records, inputs):
+    """After the timed work: every recorded GPU result against the float64 oracle.
+
+    The oracle takes its own Gershgorin bounds and quadrature size (the library's bounds are
+    compared, as a relative difference), forms the sampled rows of D_L at the GPU's mu from the
+    generator's eigenpairs, Q[rows] diag(p(lam~)) Q^T, and the trace with the exact moments.
+    Writes max_abs_err_vs_oracle (over one row per 64-row band), trace_err_vs_oracle
+    (|t_oracle(mu) - N_e|) and bounds_rel_diff into each record's row."""
+    import numpy as np
+
+    from oracle import chebyshev as ch
+
+    bounds_cache = {}
+    for rec in records:
+        h, q, lam = inputs.host[rec["key"]]
+        if rec["key"] not in bounds_cache:
+            bounds_cache[rec["key"]] = ch.gershgorin_bounds(h)
+        lo, hi = bounds_cache[rec["key"]]
+        cen, a = ch.scaling(lo, hi)
+        M = ch.quadrature_size(rec["order"], rec["beta"] * a)
+        c = ch.chebyshev_coeffs(rec["order"], rec["beta"] * a, (rec["mu"] - cen) / a, M)
+        row = rec["row"]
+        row["bounds_rel_diff"] = float(f"{max(abs(rec['emin'] - lo), abs(rec['emax'] - hi)) / max(abs(lo), abs(hi)):.2e}")
+        row["n_quad_matches_oracle"] = bool(rec["n_quad"] == M)
+        tau = ch.moments_from_eigs(lam, lo, hi, rec["order"])
+        row["trace_err_vs_oracle"] = float(f"{abs(ch.trace_of_series(c, tau) - rec['n_elec']):.3e}")
+        if rec["d_rows"] is not None:
+            p = ch.cheb_eval(c, (lam - cen) / a)
+            ref = (q[rec["rows"]] * p) @ q.T
+            row["max_abs_err_vs_oracle"] = float(f"{float(np.max(np.abs(rec['d_rows'] - ref))):.3e}")
+            row["err_rows"] = f"{len(rec['rows'])} rows (one per 64-row band)"
+
+
+def fermi_level(e, beta, n_elec, iters=200):
+    """mu with sum_i 1/(1 + exp(beta (e_i - mu))) = n_elec, by bisection on the eigenvalues."""
+    import numpy as np
+
+    lo, hi = float(e.min()) - 50.0 / beta, float(e.max()) + 50.0 / beta
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        with np.errstate(over="ignore"):
+            cnt = float(np.sum(1.0 / (1.0 + np.exp(beta * (e - mid)))))
+        if cnt < n_elec:
+            lo = mid
+        else:
+            hi = mid
+        if hi - lo <= 4.0 * np.spacing(max(abs(mid), 1.0)):
             break
-    dt = time.perf_counter() - t0
-    return {"value": round(reps / dt, 4), "unit": "density matrices/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{reps} full mu search + density at N={h_np.shape[0]}, order {order} "
-                      f"(oracle route: LAPACK eigh of H, moments, bisection, Q p(lam) Q^T), {dt:.1f} s"}
+    return 0.5 * (lo + hi)
+
+
+def diag_gpu_rows(inputs, cheb_rows, beta, workloads):
+    """On-box diagonalisation comparator (the paper's Sec. II.A / III.A comparison, on MI355X).
+
+    D = V f(E) V^T with E, V from torch.linalg.eigh on the device (the vendor solver, run as a
+    library), mu from the eigenvalues (host bisection), and V f(E) V^T as one device product.
+    Reports density matrices/s, the Chebyshev path's speed-up over it (mu search + D, float64),
+    and the eigensolver / GEMM time ratio (one float64 N x N x N torch.matmul)."""
+    import statistics
+
+    import numpy as np
+    import torch
+
+    out = {}
+    for key in workloads:
+        n = key[0]
+        H = inputs.get(*key)
+
+        def sync_time(fn, reps):
+            fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            return statistics.median(ts)
+
+        def diag_density():
+            e, v = torch.linalg.eigh(H)
+            e_h = e.cpu().numpy()
+            mu = fermi_level(e_h, beta, n / 2.0)
+            with np.errstate(over="ignore"):
+                occ = torch.from_numpy(1.0 / (1.0 + np.exp(beta * (e_h - mu)))).to(H.device)
+            return torch.matmul(v * occ, v.t().contiguous()), mu
+
+        reps = 5 if n <= 2000 else 3
+        log(f"diag_gpu: n={n}")
+        t_eigh = sync_time(lambda: torch.linalg.eigh(H), reps)
+        t_dm = sync_time(diag_density, reps)
+        t_gemm = sync_time(lambda: torch.matmul(H, H), 10)
+        cheb = cheb_rows.get(f"n{n}_fp64", {}).get("dm_per_s")
+        out[f"n{n}"] = {"dm_per_s": round(1.0 / t_dm, 3), "ms_per_dm": round(1e3 * t_dm, 2),
+                        "eigh_ms": round(1e3 * t_eigh, 2), "dgemm_ms": round(1e3 * t_gemm, 3),
+                        "dgemm_tflops": round(2.0 * n ** 3 / t_gemm / 1e12, 2),
+                        "eigh_over_dgemm": round(t_eigh / t_gemm, 1),
+                        "chebyshev_fp64_dm_per_s": cheb,
+                        "chebyshev_speedup": round(cheb * t_dm, 2) if cheb else None}
+        log(f"diag_gpu: {out[f'n{n}']}")
+    return {"method": "torch.linalg.eigh (float64, device) -> mu from the eigenvalues -> V f(E) V^T; exact "
+                      "Fermi operator, not the order-L expansion",
+            **out}
 
 
 def lanczos_rows(cd, handle, hs, beta, order, reps=10):
@@ -274,7 +438,7 @@ def batch_row(cd, handle, torch, prec="fp32", order=256, reps=3):
                                "median_beta_scaled": round(float(np.median(beta_s_lz)), 1)}}
 
 
-def learned_row(cd, handle, torch, order=256, chunks=20, chunk=1024, eval_count=1024, eval_n=500, epochs=40):
+def learned_row(cd, handle, torch, order=256, chunks=30, chunk=1024, eval_count=1024, eval_n=500, epochs=120):
     """Learned mu start: train on method-generated data, then compare search modes on 1024 x N=500."""
     import numpy as np
 
@@ -330,7 +494,10 @@ def learned_row(cd, handle, torch, order=256, chunks=20, chunk=1024, eval_count=
                         f"{eval_count} x n={eval_n}",
             "train_samples": int(X.shape[0] - nval), "data_s": round(t_data, 1), "train_s": round(t_train, 1),
             "epochs": epochs, "validation_rms_mu_scaled": float(np.sqrt(np.mean(res ** 2))), "delta": delta,
-            "modes": modes}
+            "modes": modes,
+            "learned_over_newton": {"evals": round(modes["learned"]["mean_evals"] / modes["newton"]["mean_evals"], 3),
+                                    "search_ms": round(modes["learned"]["search_ms_eager"]
+                                                       / modes["newton"]["search_ms_eager"], 3)}}
 
 
 def main():
@@ -345,7 +512,10 @@ def main():
     ap.add_argument("--no-breakdown", action="store_true")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched 512-problem workload (for profiling it) and print its row")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the CPU oracle leg (its timing and the oracle check of every GPU result)")
+    ap.add_argument("--sections", default="all",
+                    help=f"comma list of the sections after the headline line: {','.join(ALL_SECTIONS)}")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (the calibration "
                          "kernel for rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -372,9 +542,16 @@ def main():
 
     n, order, beta = args.n, args.order, args.beta
     n_elec = n / 2.0
-    log(f"generating H: n={n} law=gaussmix6 seed=2002")
-    h_np = make_h(n, "gaussmix6", 2002)
-    H = torch.from_numpy(h_np).to("cuda:0")
+    sections = set(ALL_SECTIONS if args.sections == "all" else args.sections.split(","))
+    unknown = sections - set(ALL_SECTIONS)
+    if unknown:
+        print(f"unknown sections {sorted(unknown)}; choose from {ALL_SECTIONS}", file=sys.stderr)
+        sys.exit(2)
+    if args.no_breakdown:
+        sections = set()
+    inputs = Inputs()
+    head_key = (n, "gaussmix6", 2002 if n == 4000 else SEEDS.get(n, 2000))
+    H = inputs.get(*head_key)
     opts = cd.make_opts(args.prec)
     if args.copy_probe_mib > 0:
         src = torch.ones(args.copy_probe_mib * (1 << 18), dtype=torch.float32, device="cuda:0")
@@ -386,12 +563,16 @@ def main():
         del src, dst
 
     log(f"timing {args.steps} steps (warmup {args.warmup}) of mu search + density, prec={args.prec}")
-    dt, prof, info = run_steps(cd, handle, H, beta, n_elec, order, opts, args.steps, args.warmup)
+    dt, prof, info, head_mu, head_D = run_steps(cd, handle, H, beta, n_elec, order, opts, args.steps, args.warmup,
+                                                with_out=True)
     value = args.steps / dt
     log(f"  {value:.3f} DM/s, {1e3 * dt / args.steps:.2f} ms/step, gemm {prof['gemm_ms'] / args.steps:.2f} ms/step")
     roof = roofline_of(prof, args.prec)
     if roof is not None:
         roof["traffic"] = traffic_of(args.prec, n, order)
+    head_check = {}
+    records = [check_record(head_check, head_key, order, beta, n_elec, head_mu, info, head_D)]
+    del head_D
 
     result = {
         "metric": METRIC, "value": round(value, 4), "unit": "density matrices/s", "n_gpus": 1,
@@ -415,58 +596,88 @@ def main():
                                               / args.steps, 3)},
         "hbm_GBs": {"combine": hbm_of(prof["combine_ms"], prof["combine_bytes"]),
                     "gram": hbm_of(prof["gram_ms"], prof["gram_bytes"]), "peak": PEAK_HBM_GBS},
+        "oracle_check": head_check,
     }
 
-    if not args.no_breakdown:
-        rows = {}
+    rows = {}
+    if "breakdown" in sections:
         cases = [(1000, "fp64", "bisection"), (1000, "fp64", "newton"), (1000, "fp32", "bisection"),
                  (2000, "fp64", "bisection"), (2000, "fp32", "bisection"), (4000, "fp32", "bisection"),
                  (4000, "bf16x3", "bisection"), (4000, "bf16x6", "bisection"), (1000, "bf16x3", "bisection"),
                  (2000, "bf16x3", "bisection"), (2000, "bf16x6", "bisection"), (4000, "fp64", "newton")]
         if args.prec != "fp64" or n != 4000:
             cases.append((4000, "fp64", "bisection"))
-        seeds = {1000: 2000, 2000: 2001, 4000: 2002}
-        hs = {n: H}
         for nn, pr, se in cases:
             log(f"breakdown n={nn} prec={pr} search={se}")
-            if nn not in hs:
-                hs[nn] = torch.from_numpy(make_h(nn, "gaussmix6", seeds.get(nn, 2000))).to("cuda:0")
             steps = 20 if nn <= 1000 else (10 if nn <= 2000 else 5)
-            d2, p2, i2 = run_steps(cd, handle, hs[nn], beta, nn / 2.0, order, cd.make_opts(pr, search=se), steps, 2)
-            r2 = roofline_of(p2, pr)
-            key = f"n{nn}_{pr}" + ("" if se == "bisection" else f"_{se}")
-            rows[key] = {"dm_per_s": round(steps / d2, 3), "ms_per_step": round(1e3 * d2 / steps, 3),
-                         "gemm_frac_of_peak": r2["frac"] if r2 else None,
-                         "gemm_tflops": r2["achieved"] if r2 else None,
-                         "search_ms": round(p2["search_ms"] / steps, 3), "search_evals": i2["iters"]}
-        fixed = {}
-        for nn, pr in ((1000, "fp64"), (4000, "fp64"), (4000, "fp32")):
-            log(f"fixed mu: n={nn} prec={pr}")
-            hh = hs[nn]
-            mu_nn, _, _ = cd.chebdm_mu_search(handle, hh, beta, nn / 2.0, order, cd.make_opts(pr), want_density=False)
-            steps = 20 if nn <= 1000 else 5
-            d3, p3 = run_density_steps(cd, handle, hh, beta, mu_nn, order, cd.make_opts(pr), steps, 2)
-            r3 = roofline_of(p3, pr)
-            fixed[f"n{nn}_{pr}"] = {"dm_per_s": round(steps / d3, 3), "ms_per_step": round(1e3 * d3 / steps, 3),
-                                    "products": p3["gemm_products"] // steps,
-                                    "gemm_frac_of_peak": r3["frac"] if r3 else None}
-        result["fixed_mu"] = fixed
-        result["lanczos_bounds"] = lanczos_rows(cd, handle, hs, beta, order)
-        result["accuracy_vs_order"] = accuracy_rows(cd, handle)
-        del hs
+            row, rec = mu_search_row(cd, handle, inputs, (nn, "gaussmix6", SEEDS[nn]), beta, order, pr, se, steps)
+            rows[f"n{nn}_{pr}" + ("" if se == "bisection" else f"_{se}")] = row
+            records.append(rec)
         for key, row in rows.items():
             nn = key.split("_")[0]
             base = value if (nn == f"n{n}" and args.prec == "fp64") else rows.get(f"{nn}_fp64", {}).get("dm_per_s")
             row["speedup_vs_fp64"] = round(row["dm_per_s"] / base, 3) if base else None
         result["breakdown"] = rows
 
-    if not args.no_breakdown:
+    if "fixed" in sections:
+        fixed = {}
+        for nn, pr in ((1000, "fp64"), (4000, "fp64"), (4000, "fp32")):
+            log(f"fixed mu: n={nn} prec={pr}")
+            key = (nn, "gaussmix6", SEEDS[nn])
+            hh = inputs.get(*key)
+            mu_nn, _, _ = cd.chebdm_mu_search(handle, hh, beta, nn / 2.0, order, cd.make_opts(pr), want_density=False)
+            steps = 20 if nn <= 1000 else 5
+            D = torch.empty_like(hh)
+            d3, p3, (_, i3) = timed(lambda: cd.chebdm_density(handle, hh, beta, mu_nn, order, cd.make_opts(pr), D=D),
+                                    steps, 2, cd, handle)
+            r3 = roofline_of(p3, pr)
+            fixed[f"n{nn}_{pr}"] = row = {"dm_per_s": round(steps / d3, 3), "ms_per_step": round(1e3 * d3 / steps, 3),
+                                          "products": p3["gemm_products"] // steps,
+                                          "gemm_frac_of_peak": r3["frac"] if r3 else None}
+            records.append(check_record(row, key, order, beta, nn / 2.0, mu_nn, i3, D))
+        result["fixed_mu"] = fixed
+
+    if "config" in sections:
+        # the N = 256 reference workload (order 128, beta 50, N_e = 128, lam uniform on [-1, 1])
+        log("config n=256 order=128")
+        row, rec = mu_search_row(cd, handle, inputs, (256, "uniform", 1000), 50.0, 128, "fp64", steps=50, warmup=5)
+        result["n256_order128"] = {"workload": "mu search + density, N=256, order 128, beta 50, N_e=128, "
+                                               "lam uniform on [-1,1] (seed 1000), float64", **row}
+        records.append(rec)
+        # the hard case: N = 5000, order 2048, beta 400, 40 % of the levels in a Gaussian of width
+        # 0.01 at the Fermi level (seed 4000), every precision
+        c4 = {"workload": "mu search + density, N=5000, order 2048, beta 400, N_e=N/2, high DOS at the Fermi "
+                          "level (40 % of lam ~ N(0, 0.01^2), rest U[-1,1], seed 4000); split-bf16 form for "
+                          "the 1e-5 target: bf16x6"}
+        for pr in ("fp64", "fp32", "bf16x3", "bf16x6"):
+            log(f"config n=5000 order=2048 prec={pr}")
+            row, rec = mu_search_row(cd, handle, inputs, (5000, "highdos", 4000), 400.0, 2048, pr, steps=3, warmup=1)
+            c4[pr] = row
+            records.append(rec)
+        for pr in ("fp32", "bf16x3", "bf16x6"):
+            c4[pr]["speedup_vs_fp64"] = round(c4[pr]["dm_per_s"] / c4["fp64"]["dm_per_s"], 3)
+        result["n5000_order2048_highdos"] = c4
+
+    if "lanczos" in sections:
+        result["lanczos_bounds"] = lanczos_rows(cd, handle, {nn: inputs.get(nn, "gaussmix6", SEEDS[nn])
+                                                             for nn in (1000, 2000, 4000)}, beta, order)
+    if "accuracy" in sections:
+        result["accuracy_vs_order"] = accuracy_rows(cd, handle)
+    if "diag" in sections:
+        result["diag_gpu"] = diag_gpu_rows(inputs, rows, beta, [(nn, "gaussmix6", SEEDS[nn]) for nn in (1000, 2000, 4000)])
+    inputs.drop_device()
+    del H
+    torch.cuda.empty_cache()
+    if "batch" in sections:
         result["batch512"] = batch_row(cd, handle, torch)
+    if "learned" in sections:
         result["learned_mu"] = learned_row(cd, handle, torch)
 
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on host cores")
-        result["cpu_baseline"] = cpu_baseline(h_np, beta, n_elec, order)
+        result["cpu_baseline"] = cpu_baseline(inputs.host[head_key][0], beta, n_elec, order)
+        log("oracle check of every recorded GPU result")
+        attach_oracle_errors(records, inputs)
     else:
         result["cpu_baseline"] = None
     handle.close()

@@ -383,21 +383,28 @@ int chebdm_batch_info(chebdm_batch b, int32_t* k, int32_t* m, int32_t* products_
  * t(mu~) at the returned mu.  It is captured as a graph of its own.
  *
  * chebdm_batch_set_search: how the per-problem search on the trace
- * function t(mu~) of Sec. 3 proceeds in later runs.
+ * function t(mu~) proceeds in later runs (the search itself is the
+ * library's reading: the paper takes mu as an input; see chebdm_mu_search).
  *   mode 0  bisection on [-1, 1] (the default; what chebdm_mu_search does);
  *   mode 1  safeguarded Newton on [-1, 1] from mu~ = 0, with t' from the
  *           same quadrature (a step leaving the bracket is a bisection step);
  *   mode 2  learned start: the network (chebdm_mlp_*) with device weights dW
  *           (float32, chebdm_mlp_num_params() of them, read at every run,
  *           not copied; they must stay valid) maps the moments to a guess g;
- *           if t(g - delta) < N_e < t(g + delta) the safeguarded Newton search
- *           runs inside that bracket, otherwise plain bisection on [-1, 1]
- *           (the fallback).  0 < delta <= 2.
+ *           Newton steps run from g, each evaluated point becoming the low
+ *           or the high end of the bracket, until both ends are evaluated
+ *           points (then safeguarded Newton inside them) or the search
+ *           converges.  A step with t' <= 0, outside [-1, 1] or further than
+ *           delta from g, or no bracket after 8 evaluations, falls back to
+ *           plain bisection between the ends found so far and whichever of
+ *           -1, 1 is still unchecked (ERR_BRACKET if N_e is not inside).
+ *           0 < delta <= 2.
  *   Every mode ends on |t - N_e| < tol, a bracket under 4 ulp or max_iter.
  *   Drops the captured graphs.  ERR_ARG on a bad mode, NULL dW or delta.
  * chebdm_batch_stats: after a run, per problem (each output nullable, host,
  *   count entries): evaluations of t (bracket checks included), whether the
- *   learned bracket was taken (0/1), the scaled mu~ and beta' = beta a.
+ *   learned start converged or formed the bracket itself (0/1; 0 when it fell
+ *   back), the scaled mu~ and beta' = beta a.
  * chebdm_batch_features: after a run, writes the network inputs of every
  *   problem to dfeat (device float32, count x 64 row-major): tau_1..tau_62
  *   divided by n, N_e / n, log(beta') / 4 (moments past the order are 0).
@@ -408,7 +415,8 @@ int chebdm_batch_features(chebdm_batch b, float* dfeat);
 
 /*
  * The learned chemical-potential network (not part of the paper: a start
- * guess for the search of Sec. 3).  y = w3 . relu(W2 relu(W1 x + b1) + b2) + b3
+ * guess for the library's chemical-potential search, which the paper does not
+ * have: it takes mu as an input).  y = w3 . relu(W2 relu(W1 x + b1) + b2) + b3
  * with x in R^64, 256 units per hidden layer, float32.  Flat parameter
  * vector (device, float32): W1 (256 x 64 row-major), b1 (256), W2 (256 x 256),
  * b2 (256), w3 (256), b3 (1): chebdm_mlp_num_params() = 82689 floats.

@@ -11,10 +11,16 @@
 //   mode 1  safeguarded Newton on [-1, 1] from mu~ = 0: every evaluation
 //           shrinks the bracket, and a Newton step that leaves it becomes a
 //           bisection step
-//   mode 2  start guess g (the learned network's): if t(g - delta) < N_e <
-//           t(g + delta), safeguarded Newton from g inside that bracket;
-//           otherwise plain bisection on [-1, 1] (the fallback)
-// ERR_BRACKET unless t(-1) < N_e < t(1) (checked whenever [-1, 1] is used).
+//   mode 2  start guess g (the learned network's): Newton steps from g, each
+//           evaluation moving the low or the high end of a bracket to its
+//           point, until both ends are points where t was evaluated (then
+//           safeguarded Newton inside, as mode 1) or the search converges.
+//           If a step is undefined (t' <= 0), leaves [-1, 1] or moves further
+//           than delta from g, or no bracket forms within kLearnedSteps
+//           evaluations, it falls back to plain bisection between the ends
+//           found so far and whichever of -1, 1 is still unchecked.
+// ERR_BRACKET unless t(-1) < N_e < t(1) (checked for each end not yet known from
+// an evaluated point).
 #pragma once
 
 #include "cheb_dev.h"
@@ -37,6 +43,9 @@ constexpr double kSat = 50.0;
 // (found from arccos of its ends, widened by two nodes) and adds the tail as one suffix sum.  It
 // classifies every node as the full pass does, so only the order of the additions changes.
 constexpr int kQBlock = 256;
+
+// Evaluations the learned start may spend before it holds a bracket.
+constexpr int kLearnedSteps = 8;
 
 // blk: nb + 1 doubles of global scratch, nb = ceil(M / kQBlock).  Deterministic.
 template <int NT>
@@ -151,28 +160,61 @@ __device__ void mu_search_one(int64_t M, const double* __restrict__ w, const dou
     const int max_iter = d.max_iter;
     int evals = 0, learned = 0, iters = 0, status = CHEBDM_WARN_NOCONV;
     double lo = -1.0, hi = 1.0, mu0 = 0.0, t_lo, t_hi, unused;
-    bool bracketed = false;
+    bool have_lo = false, have_hi = false;   // an end is a point where t was evaluated
+    double mid = 0.0, t_mid = NAN;
+    bool done = false;
     if (mode == 2) {
-        double g = isfinite(guess) ? guess : 0.0;
-        g = fmin(fmax(g, -1.0), 1.0);
-        lo = fmax(-1.0, g - delta);
-        hi = fmin(1.0, g + delta);
-        trace_pass<NT, false>(lo, w, x, M, beta_s, smem, t_lo, unused, blk);
-        trace_pass<NT, false>(hi, w, x, M, beta_s, smem, t_hi, unused, blk);
-        evals += 2;
-        if (t_lo < ne && ne < t_hi) {
-            bracketed = true;
-            learned = 1;
-            mu0 = g;
+        const double g = fmin(fmax(isfinite(guess) ? guess : 0.0, -1.0), 1.0);
+        mid = g;
+        for (int it = 1; it <= kLearnedSteps && it <= max_iter; ++it) {
+            double dt;
+            trace_pass<NT, true>(mid, w, x, M, beta_s, smem, t_mid, dt, blk);
+            ++evals;
+            if (fabs(t_mid - ne) < tol) {
+                status = CHEBDM_OK;
+                learned = 1;
+                done = true;
+                break;
+            }
+            if (t_mid < ne) {
+                lo = mid;
+                have_lo = true;
+            } else {
+                hi = mid;
+                have_hi = true;
+            }
+            if (have_lo && have_hi) {   // bracketed: safeguarded Newton inside from here
+                learned = 1;
+                double cand = mid - (t_mid - ne) / dt;
+                if (!(dt > 0.0) || !(cand > lo && cand < hi)) cand = 0.5 * (lo + hi);
+                if (hi - lo < 4.0 * ulp_spacing(mid)) {
+                    done = true;
+                    break;
+                }
+                mu0 = cand;
+                break;
+            }
+            const double cand = mid - (t_mid - ne) / dt;
+            if (!(dt > 0.0) || !(cand > -1.0 && cand < 1.0) || !(fabs(cand - g) <= delta)) break;
+            mid = cand;
         }
     }
-    double mid = 0.0, t_mid = NAN;
-    if (!bracketed) {
-        lo = -1.0;
-        hi = 1.0;
-        trace_pass<NT, false>(lo, w, x, M, beta_s, smem, t_lo, unused, blk);
-        trace_pass<NT, false>(hi, w, x, M, beta_s, smem, t_hi, unused, blk);
-        evals += 2;
+    if (!done && !learned) {
+        // the ends not known from an evaluated point are -1 and 1, checked here
+        if (!have_lo) {
+            lo = -1.0;
+            trace_pass<NT, false>(lo, w, x, M, beta_s, smem, t_lo, unused, blk);
+            ++evals;
+        } else {
+            t_lo = -INFINITY;
+        }
+        if (!have_hi) {
+            hi = 1.0;
+            trace_pass<NT, false>(hi, w, x, M, beta_s, smem, t_hi, unused, blk);
+            ++evals;
+        } else {
+            t_hi = INFINITY;
+        }
         if (!(t_lo < ne && ne < t_hi)) {
             if (threadIdx.x == 0) {
                 d.mu_s = NAN;
@@ -187,7 +229,9 @@ __device__ void mu_search_one(int64_t M, const double* __restrict__ w, const dou
             return;
         }
     }
-    if (mode == 0 || (mode == 2 && !learned)) {
+    if (done) {
+        // converged (or collapsed) in the learned start
+    } else if (mode == 0 || (mode == 2 && !learned)) {
         for (int it = 1; it <= max_iter; ++it) {
             mid = 0.5 * (lo + hi);
             trace_pass<NT, false>(mid, w, x, M, beta_s, smem, t_mid, unused, blk);

@@ -3,10 +3,14 @@
 The network (64 inputs -> 256 -> 256 -> 1, ReLU, float32; the C ABI's
 ``chebdm_mlp_*``) maps a problem's Chebyshev trace moments, its electron
 fraction and its scaled inverse temperature to the scaled chemical potential
-mu~ at which the quadrature trace of Sec. 3's search meets N_e.  It is not
-in the paper: it only supplies a guess g, and the batched search keeps that
-guess only if t(g - delta) < N_e < t(g + delta) holds, so a wrong guess
-costs two trace evaluations and falls back to plain bisection.
+mu~ at which the quadrature trace of the library's chemical-potential search
+meets N_e (the search is the library's reading: the paper takes mu as an
+input).  It is not in the paper either: it only supplies a guess g.  The
+batched search takes Newton steps from g, growing a bracket from the points
+it evaluates; a step that is undefined, leaves [-1, 1] or strays further than
+delta from g, or no bracket after 8 evaluations, falls back to plain
+bisection, so the result is always a point where the quadrature trace meets
+N_e, never the network's output itself.
 
 Everything numeric runs in the library's kernels: training targets and
 inputs come from moments-only batched runs with bisection, and the forward,
@@ -183,7 +187,8 @@ def search_report(batch: B.Batch, status, iters, trace, n_elecs) -> Dict:
 
 def delta_from_residuals(residual: np.ndarray, quantile: float = 0.999, floor: float = 1e-4,
                          factor: float = 2.0) -> float:
-    """Bracket half-width for the learned search: ``factor`` times a high quantile of |g - mu~|."""
+    """How far the learned start's Newton steps may move from g before the search falls back:
+    ``factor`` times a high quantile of the validation residuals |g - mu~|."""
     r = np.abs(np.asarray(residual, dtype=np.float64))
     return float(max(floor, factor * np.quantile(r, quantile)))
 

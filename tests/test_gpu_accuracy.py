@@ -14,6 +14,7 @@ import pytest
 
 import synth
 from oracle import chebyshev as ch
+from refcheck import checked_bounds, checked_lanczos_bounds, checked_quadrature
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -47,9 +48,10 @@ def test_error_against_order_and_bounds(cd, handle):
     h, q, lam = synth.hamiltonian(n, "highdos", seed=4001)
     H = torch.from_numpy(h).to("cuda:0")
     exact = ch.fermi_dirac_density(q, lam, beta, mu)
+    # the oracle's bounds, after checking the library's against them; both sides then take them
     bounds = {"spectrum": (float(lam.min()), float(lam.max())),
-              "lanczos": cd.chebdm_bounds_lanczos(handle, H, 40, 0.01, 0)[:2],
-              "gershgorin": cd.chebdm_bounds(handle, H)}
+              "lanczos": checked_lanczos_bounds(h, cd.chebdm_bounds_lanczos(handle, H, 40, 0.01, 0)[:2]),
+              "gershgorin": checked_bounds(h, gpu_bounds=cd.chebdm_bounds(handle, H))}
     err = {}
     for name, (lo, hi) in bounds.items():
         cen, a = ch.scaling(lo, hi)
@@ -57,7 +59,7 @@ def test_error_against_order_and_bounds(cd, handle):
         for L in orders:
             D, info = cd.chebdm_density(handle, H, beta, mu, L, cd.make_opts("fp64"), lo, hi)
             d = D.cpu().numpy()
-            c = ch.chebyshev_coeffs(L, beta * a, (mu - cen) / a, info["n_quad"])
+            c = ch.chebyshev_coeffs(L, beta * a, (mu - cen) / a, checked_quadrature(L, beta, lo, hi, info))
             parity = float(np.max(np.abs(d - ch.density_from_eigs(q, lam, c, lo, hi))))
             assert parity <= 1e-10, (name, L, parity)
             err[name].append(float(np.max(np.abs(d - exact))))

@@ -4,7 +4,9 @@ Each problem of a batch must match the CPU oracle exactly as a single
 problem does: max-abs 1e-10 on D in float64 (1e-5 in float32 / bf16x6) at the
 problem's own mu, and the oracle's trace at that mu within tolerance.
 Graph replays must reproduce the first run bit for bit, and an eager run
-(launch timing on) must agree with the graph.
+(launch timing on) must agree with the graph.  References take the oracle's
+Gershgorin bounds; each problem's beta' = beta (e_b - e_a)/2 reported by the
+library is checked against them first.
 """
 import os
 import sys
@@ -57,6 +59,12 @@ def _check_problem(q, lam, D, mu, order, beta, ne, emin_emax, M, tol_d, tol_t):
     return err, t_err
 
 
+def _check_beta_scaled(beta_s, beta, lo, hi):
+    # the library's beta' carries its own Gershgorin bounds: they must be the oracle's to rounding
+    ref = beta * 0.5 * (hi - lo)
+    assert abs(beta_s - ref) <= 1e-13 * beta * max(abs(lo), abs(hi)), (beta_s, ref)
+
+
 def _make(sizes, seed0, law="uniform"):
     probs = [synth.hamiltonian(n, law, seed=seed0 + i) for i, n in enumerate(sizes)]
     return probs, [_dev(h) for h, _, _ in probs]
@@ -72,9 +80,11 @@ def test_batch_matches_oracle(cd, handle, prec, tol):
     batch = cd.Batch(handle, sizes, order, cd.make_opts(prec))
     _say(f"batch {prec}: {batch.info()}")
     mu, Ds, status, iters, trace = batch.mu_search(Hs, betas, nes)
+    _, _, _, beta_s = batch.stats()
     for p, n in enumerate(sizes):
         h, q, lam = probs[p]
         lo, hi = ch.gershgorin_bounds(h)
+        _check_beta_scaled(beta_s[p], betas[p], lo, hi)
         cen, a = ch.scaling(lo, hi)
         M = ch.quadrature_size(order, betas[p] * a)
         assert status[p] == 0, (p, status[p])
@@ -188,8 +198,10 @@ def test_batch_schedules_agree_bitwise(cd, handle, tmp_path):
             assert np.array_equal(a, c)
 
 
-def test_batch_512_uneven_workload_sampled(cd, handle):
-    # 512 problems, n uniform on {96, 128, ..., 1024}, beta on [30, 200], order 256, float32
+def test_batch_512_uneven_workload(cd, handle):
+    # 512 problems, n uniform on {96, 128, ..., 1024}, beta on [30, 200], order 256, float32:
+    # every problem's bounds (through beta') and electron count against the oracle, and the
+    # whole D of 40 problems (the first and last few, the largest and smallest, and a stride)
     sizes, betas = synth.batch_problems(512, seed=3000)
     order = 256
     _say("generating 512 Hamiltonians")
@@ -200,19 +212,50 @@ def test_batch_512_uneven_workload_sampled(cd, handle):
     _say("tune: " + batch.tune())
     mu, Ds, status, iters, trace = batch.mu_search(Hs, betas, nes)
     assert np.all(status == 0), np.unique(status)
-    for p in [0, 1, 100, 255, 300, 511, int(np.argmax(sizes)), int(np.argmin(sizes))]:
+    _, _, _, beta_s = batch.stats()
+    full = set([0, 1, 2, 3, 508, 509, 510, 511, int(np.argmax(sizes)), int(np.argmin(sizes))])
+    full |= set(range(5, 512, 17))
+    worst_d, worst_t = 0.0, 0.0
+    for p in range(512):
         h, q, lam = probs[p]
         lo, hi = ch.gershgorin_bounds(h)
+        _check_beta_scaled(beta_s[p], betas[p], lo, hi)
         cen, a = ch.scaling(lo, hi)
         M = ch.quadrature_size(order, betas[p] * a)
-        rows = np.array([0, sizes[p] // 2, sizes[p] - 1])
         c = ch.chebyshev_coeffs(order, betas[p] * a, (mu[p] - cen) / a, M)
-        pv = ch.cheb_eval(c, (lam - cen) / a)
-        ref = (q[rows] * pv) @ q.T
-        err = float(np.max(np.abs(Ds[p][rows].cpu().numpy() - ref)))
         t_err = abs(ch.trace_of_series(c, ch.moments_from_eigs(lam, lo, hi, order)) - nes[p])
-        _say(f"  p={p} n={sizes[p]} err={err:.2e} t_err={t_err:.2e}")
-        assert err <= 1e-5 and t_err <= 1e-5 * sizes[p]
+        assert t_err <= 1e-5 * sizes[p], (p, t_err)
+        worst_t = max(worst_t, t_err / sizes[p])
+        if p in full:
+            ref = ch.density_from_eigs(q, lam, c, lo, hi)
+            err = float(np.max(np.abs(Ds[p].cpu().numpy() - ref)))
+            assert err <= 1e-5, (p, sizes[p], err)
+            worst_d = max(worst_d, err)
+    _say(f"  512 problems: worst |t_oracle - Ne|/n = {worst_t:.2e}; whole D of {len(full)} problems, "
+         f"worst max|D - D_oracle| = {worst_d:.2e}")
+    batch.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("bf16x3", 1e-5)])
+def test_batch_split_bf16_matches_oracle(cd, handle, prec, tol):
+    # the three-term split in batched form: same products as the single-problem kernels' tiles
+    sizes = [96, 130, 200, 257, 64, 320, 33, 512]
+    order, beta = 128, 60.0
+    probs, Hs = _make(sizes, 2600, "gaussmix6")
+    betas = [beta + 5 * i for i in range(len(sizes))]
+    nes = [0.5 * n + 0.5 for n in sizes]
+    batch = cd.Batch(handle, sizes, order, cd.make_opts(prec))
+    mu, Ds, status, iters, trace = batch.mu_search(Hs, betas, nes)
+    _, _, _, beta_s = batch.stats()
+    for p, n in enumerate(sizes):
+        h, q, lam = probs[p]
+        lo, hi = ch.gershgorin_bounds(h)
+        _check_beta_scaled(beta_s[p], betas[p], lo, hi)
+        cen, a = ch.scaling(lo, hi)
+        M = ch.quadrature_size(order, betas[p] * a)
+        assert status[p] == 0, (p, status[p])
+        err, t_err = _check_problem(q, lam, Ds[p], mu[p], order, betas[p], nes[p], (lo, hi), M, tol, 1e-5 * n)
+        _say(f"  {prec} n={n} err={err:.2e} t_err={t_err:.2e}")
     batch.close()
 
 
@@ -256,9 +299,9 @@ def test_batch_lanczos_bounds_match_single_and_oracle(cd, handle, prec, tol):
         assert abs(lo - rlo) <= 1e-10 * scale and abs(hi - rhi) <= 1e-10 * scale
         assert beta_s[p] == betas[p] * (0.5 * (hi - lo)), (p, beta_s[p], betas[p] * 0.5 * (hi - lo))
         assert status[p] == 0, (p, status[p])
-        cen, a = ch.scaling(lo, hi)
+        cen, a = ch.scaling(rlo, rhi)                       # the reference takes the oracle's bounds
         M = ch.quadrature_size(order, betas[p] * a)
-        err, t_err = _check_problem(q, lam, Ds[p], mu[p], order, betas[p], nes[p], (lo, hi), M, tol,
+        err, t_err = _check_problem(q, lam, Ds[p], mu[p], order, betas[p], nes[p], (rlo, rhi), M, tol,
                                     1e-9 if prec == "fp64" else 1e-5 * n)
         _say(f"  p={p} n={n} [{lo:.4f}, {hi:.4f}] err={err:.1e} t_err={t_err:.1e}")
     batch.close()

@@ -7,8 +7,10 @@ chemical potential, so it isolates the products; the target is a max-abs
 error of 1e-5 for both forms.
 
 Full size: the benchmark shapes (N = 1000/2000/4000, order 512; N = 5000,
-order 2048) are compared on sampled rows, which the oracle computes one by
-one from the generator's eigenpairs: D[rows] = Q[rows] diag(p(lam~)) Q^T.
+order 2048) are compared on the whole D, which the oracle forms from the
+generator's eigenpairs as Q diag(p(lam~)) Q^T.  Every reference uses the
+oracle's own Gershgorin bounds and quadrature size, after asserting that the
+GPU's agree with them.
 """
 import sys
 
@@ -17,6 +19,7 @@ import pytest
 
 import synth
 from oracle import chebyshev as ch
+from refcheck import checked_bounds, checked_quadrature, density, trace_error
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -48,13 +51,6 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 
 
-def _oracle_rows(q, lam, rows, order, beta, mu, emin, emax, M):
-    cen, a = ch.scaling(emin, emax)
-    c = ch.chebyshev_coeffs(order, beta * a, (mu - cen) / a, M)
-    p = ch.cheb_eval(c, (lam - cen) / a)
-    return (q[rows] * p) @ q.T
-
-
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
 @pytest.mark.parametrize("n,law,order,beta", [(256, "uniform", 128, 50.0), (520, "gaussmix6", 255, 60.0),
                                               (700, "highdos", 512, 100.0)])
@@ -64,8 +60,9 @@ def test_reduced_precision_density(cd, handle, prec, n, law, order, beta):
     mu = 0.05
     D, info = cd.chebdm_density(handle, _dev(h), beta, mu, order, cd.make_opts(prec))
     torch.cuda.synchronize()
-    rows = np.arange(n)
-    ref = _oracle_rows(q, lam, rows, order, beta, mu, info["emin"], info["emax"], info["n_quad"])
+    lo, hi = checked_bounds(h, info)
+    M = checked_quadrature(order, beta, lo, hi, info)
+    ref, _ = density(q, lam, order, beta, mu, lo, hi, M)
     err = float(np.max(np.abs(D.cpu().numpy() - ref)))
     _say(f"  max|D_{prec} - D_oracle| = {err:.3e}")
     assert err <= 1e-5
@@ -78,16 +75,21 @@ def test_reduced_precision_mu_search(cd, handle, prec):
     h, q, lam = synth.hamiltonian(n, "gaussmix6", seed=77)
     mu, D, info = cd.chebdm_mu_search(handle, _dev(h), beta, ne, order, cd.make_opts(prec))
     torch.cuda.synchronize()
-    emin, emax = info["emin"], info["emax"]
-    cen, a = ch.scaling(emin, emax)
-    c = ch.chebyshev_coeffs(order, beta * a, (mu - cen) / a, info["n_quad"])
-    tau = ch.moments_from_eigs(lam, emin, emax, order)
-    t_err = abs(ch.trace_of_series(c, tau) - ne)
-    _say(f"  |t_oracle(mu_{prec}) - Ne| = {t_err:.3e}  iters={info['iters']}")
+    lo, hi = checked_bounds(h, info)
+    M = checked_quadrature(order, beta, lo, hi, info)
+    ref, c = density(q, lam, order, beta, mu, lo, hi, M)
+    t_err = trace_error(lam, c, lo, hi, order, ne)
+    err = float(np.max(np.abs(D.cpu().numpy() - ref)))
+    _say(f"  |t_oracle(mu_{prec}) - Ne| = {t_err:.3e}  iters={info['iters']}  max|D - D_oracle| = {err:.3e}")
+    assert err <= 1e-5
     # moments from reduced-precision matrices: electron count within 1e-5 * N
     assert t_err <= 1e-5 * n
     assert abs(info["trace"] - ne) <= 1e-5 * n
 
+
+BF16X3_CONFIG4 = ("the three-term split (hi*hi + hi*lo + lo*hi) carries about 16 bits per product; over the "
+                  "132 products of order 2048 at beta' ~ 1e4 it ends near 5e-5, above the 1e-5 target: the "
+                  "six-term split (bf16x6) is the split-bf16 form for this shape")
 
 FULL = [
     # n, law, order, beta, prec, seed
@@ -95,44 +97,48 @@ FULL = [
     (2000, "gaussmix6", 512, 100.0, "fp64", 2001),
     (4000, "gaussmix6", 512, 100.0, "fp64", 2002),
     (1000, "gaussmix6", 512, 100.0, "fp32", 2000),
-    (4000, "gaussmix6", 512, 100.0, "fp32", 2002),
-    (4000, "gaussmix6", 512, 100.0, "bf16x3", 2002),
-    (1800, "uniform", 512, 100.0, "bf16x3", 2003),     # LDS-staged split products, ragged 128-tiles
     (2000, "gaussmix6", 512, 100.0, "fp32", 2001),
-    (5000, "highdos", 2048, 400.0, "bf16x6", 4000),
-    (5000, "highdos", 2048, 400.0, "bf16x3", 4000),
+    (4000, "gaussmix6", 512, 100.0, "fp32", 2002),
+    (1000, "gaussmix6", 512, 100.0, "bf16x3", 2000),
+    (2000, "gaussmix6", 512, 100.0, "bf16x3", 2001),
+    (4000, "gaussmix6", 512, 100.0, "bf16x3", 2002),
+    (4000, "gaussmix6", 512, 100.0, "bf16x6", 2002),
+    (1800, "uniform", 512, 100.0, "bf16x3", 2003),     # LDS-staged split products, ragged 128-tiles
+    (5000, "highdos", 2048, 400.0, "fp64", 4000),
     (5000, "highdos", 2048, 400.0, "fp32", 4000),
+    (5000, "highdos", 2048, 400.0, "bf16x6", 4000),
+    pytest.param((5000, "highdos", 2048, 400.0, "bf16x3", 4000), id="n5000-L2048-bf16x3",
+                 marks=pytest.mark.xfail(strict=True, reason=BF16X3_CONFIG4)),
 ]
 
-# The three-product split carries ~2^-16 relative error per product; over the
-# 89 products of order 2048 it ends near 5e-5, so at that shape it is held to
-# 1e-4 and the six-product split carries the 1e-5 target.
-LOOSE = {("bf16x3", 2048): 1e-4}
+
+def _case_id(c):
+    return f"n{c[0]}-L{c[2]}-{c[4]}"
 
 
-@pytest.mark.parametrize("case", FULL, ids=[f"n{c[0]}-L{c[2]}-{c[4]}" for c in FULL])
-def test_full_size_mu_search_sampled_rows(cd, handle, case):
+@pytest.mark.parametrize("case", FULL, ids=_case_id)
+def test_full_size_mu_search_whole_density(cd, handle, case):
+    # the whole D against the oracle's Q diag(p) Q^T: every tile of every launch shape the
+    # library picks at these sizes (full rounds, tail-split slices, stream-K pieces, LDS tiles)
     n, law, order, beta, prec, seed = case
     _say(f"full-size mu_search {case}")
     h, q, lam = synth.hamiltonian(n, law, seed=seed)
     mu, D, info = cd.chebdm_mu_search(handle, _dev(h), beta, n / 2, order, cd.make_opts(prec))
     torch.cuda.synchronize()
-    rng = np.random.default_rng(seed)
-    rows = np.sort(rng.choice(n, size=6, replace=False))
-    rows[0] = 0
-    rows[-1] = n - 1
-    ref = _oracle_rows(q, lam, rows, order, beta, mu, info["emin"], info["emax"], info["n_quad"])
-    err = float(np.max(np.abs(D[rows].cpu().numpy() - ref)))
-    emin, emax = info["emin"], info["emax"]
-    cen, a = ch.scaling(emin, emax)
-    c = ch.chebyshev_coeffs(order, beta * a, (mu - cen) / a, info["n_quad"])
-    t_err = abs(ch.trace_of_series(c, ch.moments_from_eigs(lam, emin, emax, order)) - n / 2)
-    _say(f"  status={info['status']} iters={info['iters']} max|D-D_oracle|(rows)={err:.3e} "
+    lo, hi = checked_bounds(h, info)
+    M = checked_quadrature(order, beta, lo, hi, info)
+    ref, c = density(q, lam, order, beta, mu, lo, hi, M)
+    d = D.cpu().numpy()
+    del D
+    err = float(np.max(np.abs(d - ref)))
+    t_err = trace_error(lam, c, lo, hi, order, n / 2)
+    _say(f"  status={info['status']} iters={info['iters']} max|D-D_oracle|={err:.3e} "
          f"|t_oracle(mu)-Ne|={t_err:.3e} |trD-Ne|={abs(info['trace'] - n / 2):.3e}")
+    assert np.array_equal(d, d.T)
     if prec == "fp64":
         assert info["status"] == 0 and err <= 1e-10 and t_err <= 1e-8
     else:
-        assert err <= LOOSE.get((prec, order), 1e-5) and t_err <= 1e-5 * n
+        assert err <= 1e-5 and t_err <= 1e-5 * n
 
 
 def test_six_term_split_grouped_stage_launches(cd, handle):
@@ -142,9 +148,10 @@ def test_six_term_split_grouped_stage_launches(cd, handle):
     h, q, lam = synth.hamiltonian(n, "gaussmix6", seed=seed)
     mu, D, info = cd.chebdm_mu_search(handle, _dev(h), beta, n / 2, order, cd.make_opts("bf16x6", baby="stages"))
     torch.cuda.synchronize()
-    rows = np.array([0, 1, 127, 128, 900, n - 9, n - 1])
-    ref = _oracle_rows(q, lam, rows, order, beta, mu, info["emin"], info["emax"], info["n_quad"])
-    err = float(np.max(np.abs(D[rows].cpu().numpy() - ref)))
-    _say(f"  bf16x6 stages n={n}: max|D-D_oracle|(rows)={err:.3e} status={info['status']}")
+    lo, hi = checked_bounds(h, info)
+    M = checked_quadrature(order, beta, lo, hi, info)
+    ref, _ = density(q, lam, order, beta, mu, lo, hi, M)
+    err = float(np.max(np.abs(D.cpu().numpy() - ref)))
+    _say(f"  bf16x6 stages n={n}: max|D-D_oracle|={err:.3e} status={info['status']}")
     assert err <= 1e-5
     assert abs(info["trace"] - n / 2) <= 1e-5 * n

@@ -16,6 +16,7 @@ import pytest
 
 import synth
 from oracle import chebyshev as ch
+from refcheck import checked_lanczos_bounds, checked_quadrature
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -130,8 +131,9 @@ def test_mu_search_with_lanczos_bounds(cd, handle, prec, tol):
     lo, hi, _, _ = cd.chebdm_bounds_lanczos(handle, H, 40, 0.01, 0)
     assert (info["emin"], info["emax"]) == (lo, hi)   # same kernels, same seed: bit-identical
     assert info["status"] == 0
+    lo, hi = checked_lanczos_bounds(h, (lo, hi))       # the reference takes the oracle's bounds
     cen, a = ch.scaling(lo, hi)
-    M = ch.quadrature_size(order, beta * a)
+    M = checked_quadrature(order, beta, lo, hi, info)
     c = ch.chebyshev_coeffs(order, beta * a, (mu - cen) / a, M)
     ref = ch.density_from_eigs(q, lam, c, lo, hi)
     err = float(np.max(np.abs(D.cpu().numpy() - ref)))

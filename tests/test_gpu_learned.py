@@ -154,8 +154,10 @@ def test_newton_and_fallback_agree_with_bisection(cd, handle):
     mu2, st2, it2, t2 = batch.mu_only(Hs, betas, nes)
     ev2, learned2, *_ = batch.stats()
     assert np.all(st0 == 0) and np.all(st1 == 0) and np.all(st2 == 0)
+    # the guess clamps to mu~ = 1, where the Newton step is undefined or leaves [-1, 1]: the
+    # fallback bisects on [-1, 1] with t(1) already evaluated, i.e. exactly the plain bisection
     assert not learned2.any()
-    assert np.array_equal(mu2, mu0) and np.array_equal(ev2, ev0 + 2)
+    assert np.array_equal(mu2, mu0) and np.array_equal(ev2, ev0)
     for mu, t in ((mu0, t0), (mu1, t1), (mu2, t2)):
         assert np.max(np.abs(t - np.array(nes))) <= 1e-8
     _say(f"  evals bisection {ev0.mean():.1f} newton {ev1.mean():.1f} fallback {ev2.mean():.1f}")
@@ -173,12 +175,12 @@ def test_newton_and_fallback_agree_with_bisection(cd, handle):
     batch.close()
 
 
-def test_learned_start_beats_bisection(cd, handle, tmp_path):
+def test_learned_start_beats_newton(cd, handle, tmp_path):
     # training set: method-generated (bisection) targets, N in 64..512, N_e / N in [0.3, 0.7], order 256
     from paper_2306_12616_amd.learned_mu import MuNet, collect_samples, delta_from_residuals, search_report
 
     t_start = time.time()
-    order, chunk, chunks = 256, 1024, 8
+    order, chunk, chunks = 256, 1024, 16
     sizes0 = synth.mu_training_sizes(chunk)
     plan = cd.Batch(handle, sizes0, order)
 
@@ -190,7 +192,7 @@ def test_learned_start_beats_bisection(cd, handle, tmp_path):
     plan.close()
     nval = 1024
     net = MuNet(handle, seed=0)
-    net.train(X[nval:], T[nval:], epochs=40, batch=256, lr=1e-3, log=_say)
+    net.train(X[nval:], T[nval:], epochs=120, batch=256, lr=1e-3)
     res = (net.predict(X[:nval]) - T[:nval]).cpu().numpy()
     delta = delta_from_residuals(res)
     _say(f"  validation rms {np.sqrt(np.mean(res ** 2)):.2e}, delta {delta:.2e}, {time.time() - t_start:.1f} s")
@@ -206,13 +208,21 @@ def test_learned_start_beats_bisection(cd, handle, tmp_path):
             ev.set_search(mode, net.W, delta)
         else:
             ev.set_search(mode)
-        mu, status, iters, t = ev.mu_only(Hs, betas, nes, allow_errors=True)
+        ev.mu_only(Hs, betas, nes, allow_errors=True)                   # captures the graph
+        cd.chebdm_profile_enable(handle, True)
+        mu, status, iters, t = ev.mu_only(Hs, betas, nes, allow_errors=True)   # eager, launch-timed
+        prof = cd.chebdm_profile_read(handle)
+        cd.chebdm_profile_enable(handle, False)
         rep[mode] = search_report(ev, status, iters, t, nes)
+        rep[mode]["search_ms"] = round(prof["search_ms"], 3)
         mus[mode] = mu
         _say(f"  {mode}: {rep[mode]}")
         assert rep[mode]["converged"] == count
         assert rep[mode]["max_count_err"] <= 1e-8
-    assert rep["learned"]["mean_evals"] < 0.5 * rep["bisection"]["mean_evals"]
+    # the gain is measured against the best search without the network (safeguarded Newton
+    # from mu~ = 0 after the bracket check at -1 and 1), not only against bisection
+    assert rep["learned"]["mean_evals"] <= 0.6 * rep["newton"]["mean_evals"]
+    assert rep["learned"]["search_ms"] < rep["newton"]["search_ms"]
     assert rep["learned"]["learned_share"] >= 0.9
     assert np.max(np.abs(mus["learned"] - mus["bisection"])) <= 1e-6
     ev.close()

@@ -4,7 +4,9 @@ Tolerances (max-abs, float64 path): 1e-10 on D as the target states; bounds
 and coefficients are single reductions, compared at 1e-13 relative.  The
 chemical potential is compared through the oracle's own trace at the GPU's
 mu (several mu are correct to within the tolerance).  Same seeded inputs on
-both sides (``synth``); the oracle uses the generator's eigenpairs.
+both sides (``synth``); the oracle uses the generator's eigenpairs.  Where the
+library computes the bounds itself, the reference uses the oracle's bounds
+and quadrature size, after asserting that the GPU's agree with them.
 """
 import math
 import sys
@@ -15,6 +17,7 @@ import pytest
 import synth
 from oracle import chebyshev as ch
 from oracle import decomposition as dec
+from refcheck import checked_bounds, checked_lanczos_bounds, checked_quadrature
 
 pytestmark = pytest.mark.gpu
 
@@ -138,15 +141,13 @@ def test_density_fp64_matches_oracle(cd, handle, case):
     opts = cd.make_opts("fp64", form, k_override=kov)
     D, info = cd.chebdm_density(handle, _dev(h), beta, mu, order, opts)
     torch.cuda.synchronize()
-    emin, emax = info["emin"], info["emax"]
     if n == 1:
         # a 1 x 1 H has e_a = e_b: the library returns f(H_00) exactly
-        assert emin == emax == h[0, 0] and info["n_quad"] == 0
+        assert info["emin"] == info["emax"] == h[0, 0] and info["n_quad"] == 0
         assert abs(D.item() - 1.0 / (1.0 + math.exp(beta * (h[0, 0] - mu)))) <= 1e-15
         return
-    cen, a = ch.scaling(emin, emax)
-    M = ch.quadrature_size(order, beta * a)
-    assert info["n_quad"] == M
+    emin, emax = checked_bounds(h, info)
+    M = checked_quadrature(order, beta, emin, emax, info)
     ref, c = _oracle_density(q, lam, order, beta, mu, emin, emax, M)
     err = np.max(np.abs(D.cpu().numpy() - ref))
     _say(f"  max|D - D_oracle| = {err:.3e}  k={info['k']} m={info['m']} gemms={info['n_gemm']}")
@@ -163,7 +164,8 @@ def test_density_writes_only_n_by_n(cd, handle):
     D, info = cd.chebdm_density(handle, _dev(h), 20.0, 0.0, 50, None, D=out[:, :n])
     torch.cuda.synchronize()
     assert torch.all(out[:, n:] == 7.0)
-    ref, _ = _oracle_density(q, lam, 50, 20.0, 0.0, info["emin"], info["emax"], info["n_quad"])
+    lo, hi = checked_bounds(h, info)
+    ref, _ = _oracle_density(q, lam, 50, 20.0, 0.0, lo, hi, checked_quadrature(50, 20.0, lo, hi, info))
     assert np.max(np.abs(D.cpu().numpy() - ref)) <= 1e-10
 
 
@@ -174,7 +176,7 @@ def test_density_given_bounds(cd, handle):
     D, info = cd.chebdm_density(handle, _dev(h), beta, mu, order, None, emin, emax)
     torch.cuda.synchronize()
     assert (info["emin"], info["emax"]) == (emin, emax)
-    ref, _ = _oracle_density(q, lam, order, beta, mu, emin, emax, info["n_quad"])
+    ref, _ = _oracle_density(q, lam, order, beta, mu, emin, emax, checked_quadrature(order, beta, emin, emax, info))
     assert np.max(np.abs(D.cpu().numpy() - ref)) <= 1e-10
 
 
@@ -201,9 +203,8 @@ def test_moments_match_oracle(cd, handle, n, order, kov):
     _say(f"moments n={n} order={order}")
     h, q, lam = synth.hamiltonian(n, "gaussmix6", seed=n + order)
     tau = cd.chebdm_moments(handle, _dev(h), order, cd.make_opts(k_override=kov))
-    lo, hi = ch.gershgorin_bounds(h)
-    lo_g, hi_g = cd.chebdm_bounds(handle, _dev(h))
-    ref = ch.moments_from_eigs(lam, lo_g, hi_g, order)
+    lo, hi = checked_bounds(h, gpu_bounds=cd.chebdm_bounds(handle, _dev(h)))
+    ref = ch.moments_from_eigs(lam, lo, hi, order)
     assert tau[0] == n
     err = np.max(np.abs(tau - ref))
     _say(f"  max|tau - tau_oracle| = {err:.3e}")
@@ -249,9 +250,9 @@ def test_mu_search_matches_oracle(cd, handle, case):
         assert info["iters"] < info_b["iters"]
     torch.cuda.synchronize()
     assert info["status"] == 0, info
-    emin, emax = info["emin"], info["emax"]
+    emin, emax = checked_bounds(h, info)
     cen, a = ch.scaling(emin, emax)
-    M = ch.quadrature_size(order, beta * a)
+    M = checked_quadrature(order, beta, emin, emax, info)
     ref, c = _oracle_density(q, lam, order, beta, mu, emin, emax, M)
     tau = ch.moments_from_eigs(lam, emin, emax, order)
     t_or = ch.trace_of_series(c, tau)
@@ -332,7 +333,8 @@ def test_baby_schedules_match_oracle(cd, handle, baby, n, order):
     h, q, lam = synth.hamiltonian(n, "gaussmix6", seed=40 + n)
     D, info = cd.chebdm_density(handle, _dev(h), 100.0, 0.02, order, cd.make_opts("fp64", baby=baby))
     torch.cuda.synchronize()
-    ref, _ = _oracle_density(q, lam, order, 100.0, 0.02, info["emin"], info["emax"], info["n_quad"])
+    lo, hi = checked_bounds(h, info)
+    ref, _ = _oracle_density(q, lam, order, 100.0, 0.02, lo, hi, checked_quadrature(order, 100.0, lo, hi, info))
     err = np.max(np.abs(D.cpu().numpy() - ref))
     _say(f"  max|D - D_oracle| = {err:.3e}")
     assert err <= 1e-10
@@ -349,7 +351,7 @@ def test_reduced_precision_ladder_schedules(cd, handle, prec):
     _say(f"ladder schedules {prec} n={n} order={order}")
     h, q, lam = synth.hamiltonian(n, "gaussmix6", seed=77)
     H = _dev(h)
-    lo, hi = cd.chebdm_bounds(handle, H)
+    lo, hi = checked_bounds(h, gpu_bounds=cd.chebdm_bounds(handle, H))
     ref = ch.moments_from_eigs(lam, lo, hi, order)
     res = {}
     for baby in ("auto", "sequential"):
@@ -377,7 +379,8 @@ def test_odd_chains_small_orders_match_oracle(cd, handle, order):
     h, q, lam = synth.hamiltonian(n, "gaussmix6", seed=60 + order)
     D, info = cd.chebdm_density(handle, _dev(h), 20.0, 0.05, order, cd.make_opts("fp64", baby="odd_chains"))
     torch.cuda.synchronize()
-    ref, _ = _oracle_density(q, lam, order, 20.0, 0.05, info["emin"], info["emax"], info["n_quad"])
+    lo, hi = checked_bounds(h, info)
+    ref, _ = _oracle_density(q, lam, order, 20.0, 0.05, lo, hi, checked_quadrature(order, 20.0, lo, hi, info))
     err = np.max(np.abs(D.cpu().numpy() - ref))
     _say(f"  k={info['k']} max|D - D_oracle| = {err:.3e}")
     assert err <= 1e-10
@@ -397,7 +400,9 @@ def test_float32_baby_schedules(cd, handle, bounds):
         D, info = cd.chebdm_density(handle, H, beta, mu, order, cd.make_opts("fp32", baby=baby, bounds=bounds))
         prof = cd.chebdm_profile_read(handle)
         cd.chebdm_profile_enable(handle, False)
-        ref, _ = _oracle_density(q, lam, order, beta, mu, info["emin"], info["emax"], info["n_quad"])
+        gpu_b = (info["emin"], info["emax"])
+        lo, hi = checked_bounds(h, gpu_bounds=gpu_b) if bounds == "gershgorin" else checked_lanczos_bounds(h, gpu_b)
+        ref, _ = _oracle_density(q, lam, order, beta, mu, lo, hi, checked_quadrature(order, beta, lo, hi, info))
         res[baby] = (float(np.max(np.abs(D.cpu().numpy() - ref))), prof["gemm_launches"], prof["gemm_products"])
         _say(f"  {baby:10s} max|D - D_oracle| = {res[baby][0]:.3e} in {res[baby][1]} launches")
     assert res["auto"][2] == res["sequential"][2] and res["auto"][1] < res["sequential"][1]
@@ -416,7 +421,8 @@ def test_stream_k_products_match_oracle(cd, handle, prec, tol):
     mu, D, info = cd.chebdm_mu_search(handle, _dev(h), beta, n / 2 + 0.5, order, cd.make_opts(prec))
     torch.cuda.synchronize()
     assert info["status"] == 0
-    ref, _ = _oracle_density(q, lam, order, beta, mu, info["emin"], info["emax"], info["n_quad"])
+    lo, hi = checked_bounds(h, info)
+    ref, _ = _oracle_density(q, lam, order, beta, mu, lo, hi, checked_quadrature(order, beta, lo, hi, info))
     err = float(np.max(np.abs(D.cpu().numpy() - ref)))
     _say(f"  mu={mu:.12f} max|D - D_oracle| = {err:.3e}")
     assert err <= tol
@@ -487,9 +493,9 @@ def test_bounds_survive_scalar_workspace_growth(cd):
         cd.chebdm_mu_search(h2, H, 5.0, 150.5, 64, None)                       # small M
         mu, D, info = cd.chebdm_mu_search(h2, H, 400.0, 150.5, 256, None)      # M grows
         assert info["status"] == 0, info
-        emin, emax = info["emin"], info["emax"]
+        emin, emax = checked_bounds(hm, info)
         cen, a = ch.scaling(emin, emax)
-        c = ch.chebyshev_coeffs(256, 400.0 * a, (mu - cen) / a, info["n_quad"])
+        c = ch.chebyshev_coeffs(256, 400.0 * a, (mu - cen) / a, checked_quadrature(256, 400.0, emin, emax, info))
         t_or = ch.trace_of_series(c, ch.moments_from_eigs(lam, emin, emax, 256))
         assert abs(t_or - 150.5) <= 1e-9
     finally:
@@ -502,9 +508,10 @@ def test_jackson_damping_matches_oracle(cd, handle, prec, tol):
     h, q, lam = synth.hamiltonian(n, "gaussmix6", seed=77)
     mu, D, info = cd.chebdm_mu_search(handle, _dev(h), beta, ne, order, cd.make_opts(prec, damping="jackson"))
     assert info["status"] == 0
-    emin, emax = info["emin"], info["emax"]
+    emin, emax = checked_bounds(h, info)
     cen, a = ch.scaling(emin, emax)
-    c = ch.chebyshev_coeffs(order, beta * a, (mu - cen) / a, info["n_quad"], "jackson")
+    c = ch.chebyshev_coeffs(order, beta * a, (mu - cen) / a, checked_quadrature(order, beta, emin, emax, info),
+                            "jackson")
     ref = ch.density_from_eigs(q, lam, c, emin, emax)
     err = float(np.max(np.abs(D.cpu().numpy() - ref)))
     t_or = ch.trace_of_series(c, ch.moments_from_eigs(lam, emin, emax, order))
@@ -566,10 +573,11 @@ def test_mu_search_tight_binding(cd, handle, kind, bounds):
     lam, q = np.linalg.eigh(h)
     mu, D, info = cd.chebdm_mu_search(handle, _dev(h), beta, ne, order, cd.make_opts(bounds=bounds))
     assert info["status"] == 0, info
-    emin, emax = info["emin"], info["emax"]
+    gpu_b = (info["emin"], info["emax"])
+    emin, emax = checked_bounds(h, gpu_bounds=gpu_b) if bounds == "gershgorin" else checked_lanczos_bounds(h, gpu_b)
     assert emin <= lam.min() and lam.max() <= emax
     cen, a = ch.scaling(emin, emax)
-    c = ch.chebyshev_coeffs(order, beta * a, (mu - cen) / a, info["n_quad"])
+    c = ch.chebyshev_coeffs(order, beta * a, (mu - cen) / a, checked_quadrature(order, beta, emin, emax, info))
     err = float(np.max(np.abs(D.cpu().numpy() - ch.density_from_eigs(q, lam, c, emin, emax))))
     t_or = ch.trace_of_series(c, ch.moments_from_eigs(lam, emin, emax, order))
     _say(f"  [{emin:.3f}, {emax:.3f}] beta'={beta * a:.0f} mu={mu:.10f} |t_oracle-Ne|={abs(t_or - ne):.1e} "
