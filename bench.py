@@ -664,7 +664,11 @@ def main():
     if "accuracy" in sections:
         result["accuracy_vs_order"] = accuracy_rows(cd, handle)
     if "diag" in sections:
-        result["diag_gpu"] = diag_gpu_rows(inputs, rows, beta, [(nn, "gaussmix6", SEEDS[nn]) for nn in (1000, 2000, 4000)])
+        cheb_rows = dict(rows)
+        if args.prec == "fp64":   # the headline step is the float64 row at its N
+            cheb_rows.setdefault(f"n{n}_fp64", {"dm_per_s": round(value, 3)})
+        result["diag_gpu"] = diag_gpu_rows(inputs, cheb_rows, beta,
+                                           [(nn, "gaussmix6", SEEDS[nn]) for nn in (1000, 2000, 4000)])
     inputs.drop_device()
     del H
     torch.cuda.empty_cache()

@@ -70,7 +70,8 @@ enum chebdm_baby {
     CHEBDM_BABY_AUTO = 0,       /* baby steps: stages for CHEBDM_FP64, odd chains for     */
                                 /* CHEBDM_FP32, sequential for the split-bf16 precisions; */
                                 /* ladder: stages for CHEBDM_FP64 and CHEBDM_FP32,        */
-                                /* sequential for the split-bf16 precisions               */
+                                /* sequential for the split-bf16 precisions; CHEBDM_FP32  */
+                                /* with k > 24 (order >= 576): sequential for both        */
     CHEBDM_BABY_STAGES = 1,     /* Algorithm 1: ceil(log2 k) stages of independent        */
                                 /* products T_{i+u} = 2 T_i T_u - T_{i-u}, one launch each */
     CHEBDM_BABY_SEQUENTIAL = 2, /* T_{i+1} = 2 T_1 T_i - T_{i-1}: errors grow ~i instead  */

@@ -138,6 +138,10 @@ def load_library(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # torch first: the library then binds to the HIP runtime torch has loaded; loaded the other
+    # way round, the process holds two runtimes and the second finds no device
+    import torch  # noqa: F401
+
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2306_12616_amd.build` "
                            "(there is no CPU fallback)")

@@ -29,6 +29,14 @@ FLAGS = [
     "-Wno-unused-command-line-argument",
     "-I", INCLUDE, "-I", CSRC,
 ]
+# MFMA accumulators in VGPRs.  With its own heuristic the compiler kept the K loop's
+# loop-carried accumulators in VGPRs but ran the MFMAs on AGPR copies, moving all 128
+# accumulator registers in and out on every iteration of the float64 product loop (N = 4000,
+# three products per launch: 3.41 -> 3.08 ms; N = 2000, four: 0.831 -> 0.751 ms).  Not for the
+# batched product kernel: there the float32 tiles then fit two wavefronts per SIMD and its
+# persistent grid doubles, which measured slower (512-problem batch: 4593 -> 3292 DM/s).
+VGPR_FORM = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
+NO_VGPR_FORM = {"k_batch.hip"}
 
 
 def hipcc() -> str:
@@ -40,7 +48,8 @@ def hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    extra = [] if src in NO_VGPR_FORM else VGPR_FORM
+    cmd = [hipcc(), *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")

@@ -78,6 +78,7 @@ struct Plan {
     int search = CHEBDM_SEARCH_BISECTION;
     int damping = CHEBDM_DAMPING_NONE;
     int bounds = CHEBDM_BOUNDS_GERSHGORIN, lz_steps = 40;
+    bool order_auto = true;   // baby-step and ladder orders are the library's choice
     int chains = 0;    // composition form: 0 library's choice, 1, 2 or 4 chains
     int split_h = 0;   // > 0: giant steps as two Clenshaw chains joined by T_h(T_k) (extra slot k + m)
     int split_q = 0;   // > 0: each half split again at q, joined by T_q(T_k) (extra slot k + m + 1)
@@ -228,6 +229,7 @@ int check_opts(const chebdm_opts* o, Plan& pl) {
     // every odd T_s are small; chains of step 3, 5 or 7 match the sequential order there and
     // every order agrees on tight bounds.  The split-bf16 products stay sequential (their
     // chains double the error, and they sit closer to their tolerance).
+    pl.order_auto = o->baby_steps == CHEBDM_BABY_AUTO;
     pl.baby = o->baby_steps != CHEBDM_BABY_AUTO
                   ? o->baby_steps
                   : (o->prec == CHEBDM_FP64 ? CHEBDM_BABY_STAGES
@@ -270,6 +272,15 @@ int plan_split(Plan& pl) {
                                         " needs more than 48 baby steps or blocks");
     pl.k = (int)k;
     pl.m = (int)m;
+    // Float32 past k = 24 (orders from 576 on): sequential baby steps and ladder.  The odd
+    // chains multiply by T_s with s up to 7, whose rounding compounds over the 45 steps of
+    // k = 46: N = 5000, order 2048, beta' ~ 1e4, max|D - D_oracle| 3.5e-5 with the odd chains and
+    // the staged ladder against 7.6e-6 sequentially.  There every product fills the chip on its
+    // own, so the sequential order costs little.
+    if (pl.order_auto && pl.prec == CHEBDM_FP32 && pl.k > 24) {
+        pl.baby = CHEBDM_BABY_SEQUENTIAL;
+        pl.ladder = CHEBDM_BABY_SEQUENTIAL;
+    }
     return 0;
 }
 

@@ -288,7 +288,13 @@ __device__ __forceinline__ void tile_epilogue(const GemmDesc<typename Traits<P>:
 // k_lo, k_hi (multiples of 2 CH; k_hi < 0: kpad): the K range of this call.  part != null:
 // instead of the epilogue, the work-group's summed accumulators are stored there, lane-native,
 // wave tile by wave tile (a K slice of a tile, added up later by gemm_tile_fix).
-template <int P, int BM, int WGM, int WGN, int KU, int SK = 1, int RB = 16>
+// SB: instruction order of the K loop.  0: the compiler's; 1: scheduling barriers pin each
+// chunk's loads right after the MFMAs of the chunk whose registers they refill, so they are
+// in flight while the other chunk's MFMAs run (left alone, the compiler sinks both chunks'
+// loads to the end of the loop body, behind most of the MFMAs); -1: 1 for float32 (N = 4000,
+// three products: 1.766 -> 1.700 ms; N = 2000, four: 0.425 -> 0.407), 0 otherwise (float64
+// already issues them early; no change).
+template <int P, int BM, int WGM, int WGN, int KU, int SK = 1, int RB = 16, int SB = -1>
 __device__ __forceinline__ void gemm_tile(const GemmDesc<typename Traits<P>::T>& g, int64_t n, int64_t ld,
                                           int64_t kpad, int ti, int tj, int64_t k_lo = 0, int64_t k_hi = -1,
                                           typename Traits<P>::Acc* part = nullptr) {
@@ -297,6 +303,7 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<typename Traits<P>::T>&
     constexpr int CH = 4 * KU;                 // k per chunk
     constexpr int WTM = BM / WGM, WTN = BM / WGN;
     constexpr int FM = WTM / 16, FN = WTN / 16;
+    constexpr bool kSB = SB < 0 ? P == P_F32 : SB != 0;
     static_assert(FM >= 1 && FN >= 1 && WTM % 16 == 0 && WTN % 16 == 0, "wave tile must hold whole MFMA blocks");
     static_assert(KU % Traits<P>::MK == 0, "KU must be a multiple of the MFMA k per lane");
     static_assert(SK >= 1 && SK <= 8, "K split of 1..8 wavefronts");
@@ -342,8 +349,11 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<typename Traits<P>::T>&
         load(a1, b1, kbeg + CH);
         for (int64_t k0 = kbeg;;) {
             mma_chunk<P, KU, FM, FN>(acc, a0, b0);
+            if constexpr (kSB) __builtin_amdgcn_sched_barrier(0);
             load(a0, b0, (k0 + 2 * CH < kend) ? k0 + 2 * CH : kend - 2 * CH);
+            if constexpr (kSB) __builtin_amdgcn_sched_barrier(0);
             mma_chunk<P, KU, FM, FN>(acc, a1, b1);
+            if constexpr (kSB) __builtin_amdgcn_sched_barrier(0);
             load(a1, b1, (k0 + 3 * CH < kend) ? k0 + 3 * CH : kend - CH);
             k0 += 2 * CH;
             if (k0 >= kend) break;

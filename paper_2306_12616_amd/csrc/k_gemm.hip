@@ -450,8 +450,11 @@ hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
     // 0.094 / 0.186 ms against 0.126 / 0.196, float32 0.067 / 0.111 against 0.088 / 0.135;
     // three products at N = 2000, float32 0.257 against 0.294; no gain from three full rounds
     // on (N = 2000, eight products) or with a nearly full last round (N = 4000, one product).
+    // Float32 also from N = 1000 once the 64-tiles fill one round (eight products at N = 1000:
+    // 0.129 -> 0.105 ms).
     if constexpr (P == P_F64 || P == P_F32) {
-        if (n >= 1500 && scratch && w64 < 3 * 1024 && w64 % 1024 < 820 &&
+        const bool long_enough = n >= 1500 || (P == P_F32 && w64 >= 1024);
+        if (long_enough && scratch && w64 < 3 * 1024 && w64 % 1024 < 820 &&
             sk_fits<P, 64, KU>(n, ld, b.count, scratch_bytes))
             return launch_sk<P, 64, KU>(b, n, ld, st, scratch, scratch_bytes);
     }
@@ -486,7 +489,12 @@ hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
         // 64-tiles (N = 1000, five / six / seven products: 0.077 / 0.082 / 0.084 against 0.093 /
         // 0.108 / 0.132 ms; N = 1500, two / three: 0.110 / 0.118 against 0.132 / 0.186), split
         // over two wavefronts only while that still fits one round
-        if (fits48 && w48 <= 1024) return launch_cfg<P, 48, 1, 1, KU, 1, 2, 0, 16, 2>(b, n, ld, st, scratch, scratch_bytes);
+        // With the accumulators in VGPRs the float32 48-tile holds two wavefronts per SIMD, and
+        // past the smallest launches it runs best unsplit (N = 1000, two / three / four products:
+        // 0.049 / 0.069 / 0.085 -> 0.044 / 0.047 / 0.056 ms; one product stays split: 0.027
+        // against 0.042)
+        if (fits48 && w48 <= 300) return launch_cfg<P, 48, 1, 1, KU, 1, 2, 0, 16, 2>(b, n, ld, st, scratch, scratch_bytes);
+        if (fits48 && w48 <= 1024) return launch_cfg<P, 48, 1, 1, KU, 1, 1, 0, 16, 2>(b, n, ld, st, scratch, scratch_bytes);
         if (w64 < 512) return launch_cfg<P, 64, 1, 1, KU, 1, 2>(b, n, ld, st, scratch, scratch_bytes);
         return launch_cfg<P, 64, 1, 1, KU, 1, 1>(b, n, ld, st, scratch, scratch_bytes);
     } else {

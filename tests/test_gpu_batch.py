@@ -236,10 +236,21 @@ def test_batch_512_uneven_workload(cd, handle):
     batch.close()
 
 
-@pytest.mark.parametrize("prec,tol", [("bf16x3", 1e-5)])
-def test_batch_split_bf16_matches_oracle(cd, handle, prec, tol):
-    # the three-term split in batched form: same products as the single-problem kernels' tiles
-    sizes = [96, 130, 200, 257, 64, 320, 33, 512]
+BF16X3_N512 = ("the three-term split (hi*hi + hi*lo + lo*hi) carries about 16 bits per product; at n = 512, "
+               "order 128 (gaussmix6 spectrum) the batched density ends at 1.02e-5, just above the 1e-5 target; "
+               "the six-term split meets it there")
+
+SPLIT_SIZES = [96, 130, 200, 257, 64, 320, 33]
+
+
+@pytest.mark.parametrize("prec,tol,sizes", [
+    ("bf16x3", 1e-5, SPLIT_SIZES),
+    ("bf16x6", 1e-5, SPLIT_SIZES + [512]),
+    pytest.param("bf16x3", 1e-5, SPLIT_SIZES + [512], id="bf16x3-n512",
+                 marks=pytest.mark.xfail(strict=True, reason=BF16X3_N512)),
+], ids=["bf16x3", "bf16x6", "bf16x3-n512"])
+def test_batch_split_bf16_matches_oracle(cd, handle, prec, tol, sizes):
+    # the split forms in batched form: same products as the single-problem kernels' tiles
     order, beta = 128, 60.0
     probs, Hs = _make(sizes, 2600, "gaussmix6")
     betas = [beta + 5 * i for i in range(len(sizes))]
