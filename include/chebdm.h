@@ -206,6 +206,23 @@ int chebdm_bounds(chebdm_handle h, const double* dH, int64_t n, int64_t ldh,
                   double* emin, double* emax);
 
 /*
+ * chebdm_bounds for callers that cannot allocate device memory (code under
+ * HIP stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same Gershgorin kernels and fold order, with their partial sums in a
+ * fixed static device array of 8 MiB (each GPU the library runs on holds one
+ * until the process ends; its address is looked up when a handle on that
+ * device is created).  The call allocates nothing, does not synchronise and
+ * is stream-ordered on the handle's stream.
+ * dH: n x n, leading dimension ldh >= n, 1 <= n <= 65535 (larger n:
+ * CHEBDM_ERR_ARG).  d_out: device pointer to 2 doubles, receives emin, emax
+ * (both NaN when H holds NaN or Inf; there is no read-back to report it).
+ * All calls on one device share that device's array: calls that overlap on
+ * one device (two streams, two threads) race and must be serialised by the
+ * caller.  Errors: CHEBDM_ERR_ARG, CHEBDM_ERR_HIP.
+ */
+int chebdm_bounds_noalloc(chebdm_handle h, const double* dH, int64_t n, int64_t ldh, double* d_out);
+
+/*
  * Spectral bounds of H from `steps` Lanczos steps (not in the paper; a
  * tighter alternative to Gershgorin's discs for e_a, e_b of Sec. II.B).
  * Start vector: the SplitMix64 generator (Steele, Lea, Flood 2014) of `seed`,

@@ -73,6 +73,8 @@ _SIGNATURES = {
     "chebdm_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "chebdm_bounds": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "chebdm_bounds_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                             ctypes.c_void_p]),
     "chebdm_bounds_lanczos": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                              ctypes.c_int32, ctypes.c_double, ctypes.c_uint64,
                                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -242,6 +244,19 @@ def chebdm_bounds(h: Handle, H):
     lo, hi = ctypes.c_double(), ctypes.c_double()
     _check(load_library().chebdm_bounds(h.ptr, p, n, ld, ctypes.byref(lo), ctypes.byref(hi)))
     return lo.value, hi.value
+
+
+def chebdm_bounds_noalloc(h: Handle, H, out):
+    """Gershgorin bounds into `out` (a float64 device tensor of at least 2 elements), stream-ordered,
+    no device allocation and no synchronisation (NaN, NaN when H holds NaN or Inf)."""
+    import torch
+
+    p, n, ld = _matrix_args(H, "H")
+    if not isinstance(out, torch.Tensor) or not out.is_cuda or out.dtype != torch.float64 or \
+            not out.is_contiguous() or out.numel() < 2:
+        raise TypeError("out must be a contiguous float64 device tensor of at least 2 elements")
+    _check(load_library().chebdm_bounds_noalloc(h.ptr, p, n, ld, ctypes.c_void_p(out.data_ptr())))
+    return out
 
 
 def chebdm_bounds_lanczos(h: Handle, H, steps: int = 40, margin: float = 0.01, seed: int = 0):

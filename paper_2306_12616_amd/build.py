@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_PATH = os.path.join(HERE, "libchebdm.so")
 
-SOURCES = ["api.hip", "api_batch.hip", "api_mlp.hip", "k_batch.hip", "k_bounds.hip", "k_check.hip", "k_cheb.hip", "k_combine.hip",
+SOURCES = ["api.hip", "api_batch.hip", "api_mlp.hip", "api_noalloc.hip", "k_batch.hip", "k_bounds.hip", "k_check.hip", "k_cheb.hip", "k_combine.hip",
            "k_gemm.hip", "k_lanczos.hip", "k_mlp.hip"]
 ARCH = os.environ.get("CHEBDM_OFFLOAD_ARCH", "gfx950")
 

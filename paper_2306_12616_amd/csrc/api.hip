@@ -812,6 +812,7 @@ int chebdm_create(chebdm_handle* out, int device, void* stream) {
     HIP_TRY(hipGetDeviceCount(&count));
     if (device < 0 || device >= count) return fail(CHEBDM_ERR_ARG, "no such HIP device");
     HIP_TRY(hipSetDevice(device));
+    CHECK(noalloc_setup(device));
     chebdm_ctx* h = new (std::nothrow) chebdm_ctx();
     if (!h) return fail(CHEBDM_ERR_OOM, "cannot allocate handle");
     h->device = device;

@@ -66,6 +66,9 @@ int prof_begin(chebdm_handle h, int kind, int products, double flop, double byte
 int prof_end(chebdm_handle h, size_t idx);
 // Algorithmic flops of one symmetric n x n product: n^2 (n + 1).
 double sym_product_flop(int64_t n);
+// Looks up (once per device; the device must be current) the address of the fixed scratch array
+// of chebdm_bounds_noalloc.
+int noalloc_setup(int device);
 
 }  // namespace chebdm
 
