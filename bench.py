@@ -133,7 +133,9 @@ def mu_search_row(cd, handle, inputs, key, beta, order, prec, search="bisection"
     return row, check_record(row, key, order, beta, n / 2.0, mu, info, D)
 
 
-GEMM_SOURCES = ("paper_2306_12616_amd/csrc/gemm_tile.h", "paper_2306_12616_amd/csrc/k_gemm.hip")
+# what the product kernels are built from (their code and the compile flags)
+GEMM_SOURCES = ("paper_2306_12616_amd/csrc/gemm_tile.h", "paper_2306_12616_amd/csrc/gemm_lds.h",
+                "paper_2306_12616_amd/csrc/k_gemm.hip", "paper_2306_12616_amd/build.py")
 
 
 def gemm_sources_sha256():

@@ -451,10 +451,16 @@ hipError_t launch_any(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int6
     // three products at N = 2000, float32 0.257 against 0.294; no gain from three full rounds
     // on (N = 2000, eight products) or with a nearly full last round (N = 4000, one product).
     // Float32 also from N = 1000 once the 64-tiles fill one round (eight products at N = 1000:
-    // 0.129 -> 0.105 ms).
+    // 0.129 -> 0.105 ms).  Past one round, a last round under a quarter full goes to the tail
+    // split instead, for float64 from N = 1500 (N = 2000, two / four products: 0.345 / 0.631 ->
+    // 0.333 / 0.596 ms; N = 3000, one / two: 0.556 / 0.995 -> 0.510 / 0.929) and for float32 from
+    // N = 2500 (N = 3000, one / two: 0.296 / 0.536 -> 0.278 / 0.504; at N = 2000, two products,
+    // stream-K stays ahead, 0.184 against 0.195, and at N = 1000 the K slices are too short).
     if constexpr (P == P_F64 || P == P_F32) {
         const bool long_enough = n >= 1500 || (P == P_F32 && w64 >= 1024);
-        if (long_enough && scratch && w64 < 3 * 1024 && w64 % 1024 < 820 &&
+        const bool tail_split_fits =
+            n >= (P == P_F64 ? 1500 : 2500) && w64 >= 1024 && (w64 % 1024) * 4 <= 1024;
+        if (long_enough && !tail_split_fits && scratch && w64 < 3 * 1024 && w64 % 1024 < 820 &&
             sk_fits<P, 64, KU>(n, ld, b.count, scratch_bytes))
             return launch_sk<P, 64, KU>(b, n, ld, st, scratch, scratch_bytes);
     }
