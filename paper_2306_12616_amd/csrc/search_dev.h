@@ -47,6 +47,10 @@ constexpr int kQBlock = 256;
 // Evaluations the learned start may spend before it holds a bracket.
 constexpr int kLearnedSteps = 8;
 
+// Node count of a trace window above which a multi-point bisection pass (one wavefront per
+// point) would be slower than a single point on the whole work-group.
+constexpr int64_t kWideWindow = 2048;
+
 // blk: nb + 1 doubles of global scratch, nb = ceil(M / kQBlock).  Deterministic.
 template <int NT>
 __device__ void tail_sums(const double* __restrict__ w, int64_t M, double* __restrict__ blk) {
@@ -146,11 +150,144 @@ __device__ __forceinline__ void trace_pass(double mu_s, const double* __restrict
     dt = SLOPE ? block_sum<NT>(accd, smem) / (double)M : 0.0;
 }
 
+// t at P points in one pass: point p by the G = NT / (64 P) wavefronts p G .. p G + G - 1 (any
+// left over idle); thread (g, lane) of a point's group adds the nodes j0 + 64 g + lane + k 64 G,
+// k = 0, 1, ..., in order (loads of U consecutive k issued together), the group's lane 0 of
+// wavefront 0 also its saturated tail, and the group's wavefront sums are added in order.  With
+// P = 1 that is exactly trace_pass<NT, false>; with more points the passes run side by side
+// instead of one after another, which is what the chain of dependent evaluations waits on.
+// Thread p < P brings point p in mu_mine.  Shared: win (4 P doubles: each point's node range,
+// tail sum and mu~), part (NT / 64 doubles), tout (P doubles, the results, valid on return).
+template <int NT, int P>
+__device__ __forceinline__ void trace_pass_groups(double mu_mine, const double* __restrict__ w,
+                                                  const double* __restrict__ x, int64_t M, double beta_s,
+                                                  double* part, double* win, double* tout,
+                                                  const double* __restrict__ blk) {
+    constexpr int U = 4, NW = NT / 64, G = NW / P;
+    static_assert(G >= 1, "at least one wavefront per point");
+    if (threadIdx.x < P) {
+        int64_t j0 = 0, j1 = M;
+        double tail = 0.0;
+        if (blk) pass_window(mu_mine, beta_s, M, blk, j0, j1, tail);
+        win[4 * threadIdx.x] = (double)j0;
+        win[4 * threadIdx.x + 1] = (double)j1;
+        win[4 * threadIdx.x + 2] = tail;
+        win[4 * threadIdx.x + 3] = mu_mine;
+    }
+    __syncthreads();
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int p = wid / G, g = wid % G;
+    double a = 0.0;
+    if (p < P) {
+        const int64_t j0 = (int64_t)win[4 * p], j1 = (int64_t)win[4 * p + 1];
+        const double mu_s = win[4 * p + 3];
+        constexpr int64_t S = 64 * G;
+        if (g == 0 && lane == 0) a = win[4 * p + 2];
+        for (int64_t j = j0 + 64 * g + lane; j < j1; j += U * S) {
+            double xs[U], ws[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t jj = j + u * S;
+                xs[u] = jj < j1 ? x[jj] : 0.0;
+                ws[u] = jj < j1 ? w[jj] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const double z = beta_s * (xs[u] - mu_s);
+                if (z < -kSat) {
+                    a += ws[u];
+                } else if (z <= kSat) {
+                    const double f = 1.0 / (1.0 + exp(z));
+                    a += f * ws[u];
+                }
+            }
+        }
+    }
+    a = wave_sum(a);
+    if (lane == 0) part[wid] = a;
+    __syncthreads();
+    if (threadIdx.x < P) {
+        double r = 0.0;
+#pragma unroll
+        for (int gg = 0; gg < G; ++gg) r += part[threadIdx.x * G + gg];
+        tout[threadIdx.x] = r / (double)M;
+    }
+    __syncthreads();
+}
+
+// Bisection LV steps per pass: the 2^LV - 1 midpoints that the next LV steps can visit (the
+// same 0.5 (lo + hi) of the same ends: node q of the heap-ordered tree is reached by halving
+// [lo, hi] along the path of q's index, children 2q + 1 for t >= N_e, the left half, and
+// 2q + 2) are evaluated side by side (trace_pass_groups), then the steps are taken from those
+// values with the stopping rule checked after each, so the sequence of brackets, the step count
+// and the stopping point are those of one-at-a-time bisection on the same trace values.  A pass
+// whose first window holds more than kWideWindow nodes (small beta', or a coarse bracket near
+// the ends) takes one step on all wavefronts instead.  Shared: part, win, tout as for
+// trace_pass_groups with P = 2^LV - 1.
+template <int NT, int LV>
+__device__ void bisect_levels(int64_t M, const double* __restrict__ w, const double* __restrict__ x, double beta_s,
+                              double ne, double tol, int max_iter, double* part, double* win, double* tout,
+                              const double* __restrict__ blk, double& lo, double& hi, double& mid, double& t_mid,
+                              int& iters, int& status) {
+    constexpr int NP = (1 << LV) - 1;
+    int it = 1;
+    bool stop = max_iter < 1;
+    while (!stop) {
+        const double root = 0.5 * (lo + hi);
+        int64_t j0 = 0, j1 = M;
+        double tail;
+        if (blk) pass_window(root, beta_s, M, blk, j0, j1, tail);
+        int levels = LV;
+        if (j1 - j0 > kWideWindow) {
+            trace_pass_groups<NT, 1>(root, w, x, M, beta_s, part, win, tout, blk);
+            levels = 1;
+        } else {
+            double mine = root;
+            if (threadIdx.x < NP) {   // walk down to node threadIdx.x
+                const int q1 = (int)threadIdx.x + 1;
+                const int depth = 31 - __clz(q1);
+                double l = lo, h = hi;
+                for (int b = depth - 1; b >= 0; --b) {
+                    const double m = 0.5 * (l + h);
+                    if ((q1 >> b) & 1) l = m;   // right child: [m, h]
+                    else h = m;
+                }
+                mine = 0.5 * (l + h);
+            }
+            trace_pass_groups<NT, NP>(mine, w, x, M, beta_s, part, win, tout, blk);
+        }
+        int k = 0;
+        for (int lev = 0; lev < levels; ++lev) {
+            mid = win[4 * k + 3];
+            t_mid = tout[k];
+            iters = it;
+            if (fabs(t_mid - ne) < tol) {
+                status = CHEBDM_OK;
+                stop = true;
+                break;
+            }
+            const bool below = t_mid < ne;
+            if (below) lo = mid;
+            else hi = mid;
+            if (hi - lo < 4.0 * ulp_spacing(mid) || ++it > max_iter) {
+                stop = true;
+                break;
+            }
+            k = 2 * k + (below ? 2 : 1);
+        }
+        __syncthreads();   // win and tout are rewritten by the next pass
+    }
+}
+
 // Writes mu_s, trace, iters, evals, learned, status, lo, hi of d (thread 0).  scratch: nullptr,
-// or M doubles of global memory for the tail sums (used from M >= 4 kQBlock on).
-template <int NT>
+// or M doubles of global memory for the tail sums (used from M >= 4 kQBlock on).  LV > 0 (with
+// shared part of NT / 64 doubles, win of 4 (2^LV - 1) and tout of 2^LV - 1): the bisection of
+// mode 0 takes up to LV steps per pass (bisect_levels) and the bracket check evaluates both ends
+// side by side.
+template <int NT, int LV = 0>
 __device__ void mu_search_one(int64_t M, const double* __restrict__ w, const double* __restrict__ x, DevScalars& d,
-                              int mode, double guess, double delta, double* smem, double* scratch = nullptr) {
+                              int mode, double guess, double delta, double* smem, double* scratch = nullptr,
+                              double* part = nullptr, double* win = nullptr, double* tout = nullptr) {
     const double* blk = nullptr;
     if (scratch && M >= 4 * kQBlock) {
         tail_sums<NT>(w, M, scratch);
@@ -199,6 +336,30 @@ __device__ void mu_search_one(int64_t M, const double* __restrict__ w, const dou
             mid = cand;
         }
     }
+    if constexpr (LV > 0) {
+        if (!done && !learned && !have_lo && !have_hi) {
+            trace_pass_groups<NT, 2>(threadIdx.x == 0 ? -1.0 : 1.0, w, x, M, beta_s, part, win, tout, blk);
+            evals += 2;
+            lo = -1.0;
+            hi = 1.0;
+            t_lo = tout[0];
+            t_hi = tout[1];
+            have_lo = have_hi = true;   // both ends checked here; the block below only tests them
+            if (!(t_lo < ne && ne < t_hi)) {
+                if (threadIdx.x == 0) {
+                    d.mu_s = NAN;
+                    d.trace = NAN;
+                    d.iters = 0;
+                    d.evals = evals;
+                    d.learned = 0;
+                    d.status = CHEBDM_ERR_BRACKET;
+                    d.lo = lo;
+                    d.hi = hi;
+                }
+                return;
+            }
+        }
+    }
     if (!done && !learned) {
         // the ends not known from an evaluated point are -1 and 1, checked here
         if (!have_lo) {
@@ -231,6 +392,10 @@ __device__ void mu_search_one(int64_t M, const double* __restrict__ w, const dou
     }
     if (done) {
         // converged (or collapsed) in the learned start
+    } else if (LV > 0 && mode == 0) {
+        if constexpr (LV > 0)
+            bisect_levels<NT, LV>(M, w, x, beta_s, ne, tol, max_iter, part, win, tout, blk, lo, hi, mid, t_mid,
+                                  iters, status);
     } else if (mode == 0 || (mode == 2 && !learned)) {
         for (int it = 1; it <= max_iter; ++it) {
             mid = 0.5 * (lo + hi);
