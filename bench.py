@@ -537,6 +537,14 @@ def main():
         sys.exit(1)
     cd.load_library()
     handle = cd.Handle(0)
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib * (1 << 18), dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
+        del src, dst
     if args.batch_only:
         print(json.dumps({"batch512": batch_row(cd, handle, torch)}), flush=True)
         handle.close()
@@ -555,15 +563,6 @@ def main():
     head_key = (n, "gaussmix6", 2002 if n == 4000 else SEEDS.get(n, 2000))
     H = inputs.get(*head_key)
     opts = cd.make_opts(args.prec)
-    if args.copy_probe_mib > 0:
-        src = torch.ones(args.copy_probe_mib * (1 << 18), dtype=torch.float32, device="cuda:0")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
-        del src, dst
-
     log(f"timing {args.steps} steps (warmup {args.warmup}) of mu search + density, prec={args.prec}")
     dt, prof, info, head_mu, head_D = run_steps(cd, handle, H, beta, n_elec, order, opts, args.steps, args.warmup,
                                                 with_out=True)
