@@ -33,8 +33,9 @@ FLAGS = [
 # loop-carried accumulators in VGPRs but ran the MFMAs on AGPR copies, moving all 128
 # accumulator registers in and out on every iteration of the float64 product loop (N = 4000,
 # three products per launch: 3.41 -> 3.08 ms; N = 2000, four: 0.831 -> 0.751 ms).  Not for the
-# batched product kernel: there the float32 tiles then fit two wavefronts per SIMD and its
-# persistent grid doubles, which measured slower (512-problem batch: 4593 -> 3292 DM/s).
+# batched product kernel: it gains nothing there at one wavefront per SIMD (512-problem batch:
+# 4588 -> 4573 DM/s), and where its float32 tiles fit two wavefronts per SIMD the persistent
+# grid doubles, which measured slower (4593 -> 3292 DM/s).
 VGPR_FORM = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
 NO_VGPR_FORM = {"k_batch.hip"}
 

@@ -113,7 +113,9 @@ int upload_schedule(chebdm_batch_ctx* b) {
         acc += b->n[p];
     }
     for (int p = 0; p < count; ++p) {
-        const int tile = b->tile_of_bucket[bucket_of(b->n[p])];
+        int tile = b->tile_of_bucket[bucket_of(b->n[p])];
+        // a 48-tile grid must stay inside the workspace matrix (ld = round_up(n, 128))
+        if (tile == 48 && (b->n[p] + 47) / 48 * 48 > b->ld[p]) tile = 64;
         geo[p] = BatchGeom{b->n[p], b->ld[p], b->off[p], colsum_off[p], tile, (int32_t)((b->n[p] + tile - 1) / tile)};
     }
     std::vector<int> order(count);
@@ -293,7 +295,7 @@ bool parse_value(const std::string& v, int tiles[kBuckets], int* order) {
     int t0, t1, t2, t3, o;
     if (std::sscanf(v.c_str(), "tiles=%d,%d,%d,%d order=%d", &t0, &t1, &t2, &t3, &o) != 5) return false;
     for (int t : {t0, t1, t2, t3})
-        if (t != 32 && t != 64) return false;
+        if (t != 32 && t != 48 && t != 64) return false;
     if (o != 0 && o != 1) return false;
     tiles[0] = t0, tiles[1] = t1, tiles[2] = t2, tiles[3] = t3;
     *order = o;
@@ -516,12 +518,18 @@ int chebdm_batch_tune(chebdm_batch b, const char* cache_path, char* report, int3
         rep << "base tiles=64 order=0: " << best << " ms;";
         for (int bk = 0; bk < kBuckets; ++bk) {
             if (!present[bk]) continue;
-            b->tile_of_bucket[bk] = 32;
-            float t = 0.0f;
-            CHECK(time_step0(b, &t));
-            rep << " bucket" << bk << " tile32: " << t << " ms;";
-            if (t < 0.98f * best) best = t;
-            else b->tile_of_bucket[bk] = 64;
+            int keep = 64;
+            for (int cand : {48, 32}) {
+                b->tile_of_bucket[bk] = cand;
+                float t = 0.0f;
+                CHECK(time_step0(b, &t));
+                rep << " bucket" << bk << " tile" << cand << ": " << t << " ms;";
+                if (t < 0.98f * best) {
+                    best = t;
+                    keep = cand;
+                }
+            }
+            b->tile_of_bucket[bk] = keep;
         }
         b->order_mode = 1;
         float t = 0.0f;

@@ -145,7 +145,7 @@ struct BatchGeom {         // fixed for a plan
     int64_t n, ld;         // size and leading dimension (multiple of 128) of the workspace matrices
     int64_t off;           // element offset of the problem's slot 0 in the batch workspace
     int64_t col_off;       // offset of the problem's column sums in the bounds scratch
-    int32_t tile;          // product tile edge: 64 or 32 (chosen by the tuner)
+    int32_t tile;          // product tile edge: 64, 48 or 32 (chosen by the tuner per size bucket)
     int32_t ntile;         // ceil(n / tile)
 };
 

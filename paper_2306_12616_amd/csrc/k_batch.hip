@@ -23,7 +23,7 @@ namespace {
 
 typedef double f64x2b __attribute__((ext_vector_type(2)));
 
-template <int P> struct BatchKU;   // k per lane per chunk for the 64- and 32-edge tiles
+template <int P> struct BatchKU;   // k per lane per chunk for the 64-, 48- and 32-edge tiles
 template <> struct BatchKU<P_F64> { static constexpr int K64 = 4, K32 = 4; };
 template <> struct BatchKU<P_F32> { static constexpr int K64 = 8, K32 = 8; };
 template <> struct BatchKU<P_BF16X3> { static constexpr int K64 = 16, K32 = 16; };
@@ -47,6 +47,9 @@ k_batch_gemm(const GemmDesc<typename Traits<P>::T>* __restrict__ descs, const Ba
         if (gm.tile == 64) {
             const int64_t kpad = (gm.n + 8 * KU64 - 1) / (8 * KU64) * (8 * KU64);
             gemm_tile<P, 64, 1, 1, KU64>(g, gm.n, gm.ld, kpad, ti, tj);
+        } else if (gm.tile == 48) {   // only where ceil(n / 48) * 48 <= ld (the host checks)
+            const int64_t kpad = (gm.n + 8 * KU64 - 1) / (8 * KU64) * (8 * KU64);
+            gemm_tile<P, 48, 1, 1, KU64>(g, gm.n, gm.ld, kpad, ti, tj);
         } else {
             const int64_t kpad = (gm.n + 8 * KU32 - 1) / (8 * KU32) * (8 * KU32);
             gemm_tile<P, 32, 1, 1, KU32>(g, gm.n, gm.ld, kpad, ti, tj);

@@ -171,8 +171,11 @@ def test_batch_tuner_and_cache(cd, handle, tmp_path):
 
 def test_batch_schedules_agree_bitwise(cd, handle, tmp_path):
     # the tuner's item orders (by decreasing n, input order) only move tiles between
-    # work-groups; every tile's arithmetic stays the same, so mu and D agree bit for bit
-    sizes = [96, 300, 600, 900, 130, 257] * 3
+    # work-groups, and its tile edges (64, 48, 32 per size bucket) only regroup the output
+    # elements: every element is still summed over K in the same order, so mu and D agree bit
+    # for bit.  n = 1020 has no 48-tile grid inside its workspace (ceil(1020/48)*48 > 1024) and
+    # keeps 64-tiles; 1000 and 900 take 48-tiles.
+    sizes = [96, 300, 600, 900, 130, 257, 1000, 1020] * 2
     probs, Hs = _make(sizes, 1700)
     betas = [30.0 + i for i in range(len(sizes))]
     nes = [0.5 * n for n in sizes]
@@ -182,12 +185,13 @@ def test_batch_schedules_agree_bitwise(cd, handle, tmp_path):
     b0.close()
     key = open(cache).read().split()[0]
     out = []
-    for order in (0, 1):
+    for tiles, order in (("64,64,64,64", 0), ("64,64,64,64", 1), ("48,48,48,48", 0), ("32,32,32,32", 0),
+                         ("48,32,64,48", 1)):
         with open(cache, "w") as f:
-            f.write(f"{key} tiles=64,64,64,64 order={order}\n")
+            f.write(f"{key} tiles={tiles} order={order}\n")
         b = cd.Batch(handle, sizes, 64, cd.make_opts("fp32"))
         rep = b.tune(cache)
-        assert rep.startswith("loaded") and f"order={order}" in rep, rep
+        assert rep.startswith("loaded") and f"tiles={tiles} order={order}" in rep, rep
         mu, Ds, status, *_ = b.mu_search(Hs, betas, nes)
         assert np.all(status == 0)
         out.append((np.array(mu), [d.cpu().numpy() for d in Ds]))
