@@ -133,18 +133,26 @@ def mu_search_row(cd, handle, inputs, key, beta, order, prec, search="bisection"
     return row, check_record(row, key, order, beta, n / 2.0, mu, info, D)
 
 
-# what the product kernels are built from (their code and the compile flags)
+# what the product kernels are built from: their code, and the compile flags build.py gives
+# k_gemm.hip (without the include paths, which name the checkout)
 GEMM_SOURCES = ("paper_2306_12616_amd/csrc/gemm_tile.h", "paper_2306_12616_amd/csrc/gemm_lds.h",
-                "paper_2306_12616_amd/csrc/k_gemm.hip", "paper_2306_12616_amd/build.py")
+                "paper_2306_12616_amd/csrc/k_gemm.hip")
 
 
 def gemm_sources_sha256():
     import hashlib
 
+    from paper_2306_12616_amd import build as pkg_build
+
     h = hashlib.sha256()
     for rel in GEMM_SOURCES:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
+    flags = [f for i, f in enumerate(pkg_build.FLAGS)
+             if f != "-I" and not (i > 0 and pkg_build.FLAGS[i - 1] == "-I")]
+    if "k_gemm.hip" not in pkg_build.NO_VGPR_FORM:
+        flags += list(pkg_build.VGPR_FORM)
+    h.update(" ".join(flags).encode())
     return h.hexdigest()
 
 
