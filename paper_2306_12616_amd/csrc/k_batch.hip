@@ -141,12 +141,17 @@ k_batch_shift(const BatchProblem* __restrict__ tab, const BatchGeom* __restrict_
               const DevScalars* __restrict__ s, T* __restrict__ mats) {
     const int p = blockIdx.z;
     const int64_t n = geo[p].n, ld = geo[p].ld;
-    const int64_t i = blockIdx.y, j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n || j >= n) return;
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
     const double cen = s[p].cen, half = s[p].half;
-    const double h = tab[p].H[i * tab[p].ldh + j];
-    const double v = half > 0.0 ? (i == j ? h - cen : h) / half : 0.0;
-    mats[geo[p].off + i * ld + j] = (T)v;
+    const double* __restrict__ H = tab[p].H;
+    const int64_t ldh = tab[p].ldh;
+    T* __restrict__ out = mats + geo[p].off;
+    for (int64_t i = blockIdx.y; i < n; i += gridDim.y) {   // rows i, i + gridDim.y, ...
+        const double h = H[i * ldh + j];
+        const double v = half > 0.0 ? (i == j ? h - cen : h) / half : 0.0;
+        out[i * ld + j] = (T)v;
+    }
 }
 
 // the last giant step writes the caller's D
@@ -446,37 +451,38 @@ k_batch_combine(const BatchGeom* __restrict__ geo, const double* __restrict__ co
     constexpr int W = BVec<T>::W;
     const int p = blockIdx.z;
     const int64_t n = geo[p].n, ld = geo[p].ld, stride = ld * ld;
-    const int64_t row = blockIdx.y;
     const int64_t col = ((int64_t)blockIdx.x * 256 + threadIdx.x) * W;
-    if (row >= n || col >= ld) return;
+    if (col >= ld) return;
     const T* tb = mats + geo[p].off;
     T* rb = mats + geo[p].off + (int64_t)k * stride;
     const double* cf = coef + (int64_t)p * k * m;
     const int lcount = (m - l0) < MB ? (m - l0) : MB;
-    const int64_t off = row * ld + col;
-    double acc[MB][W];
-#pragma unroll
-    for (int l = 0; l < MB; ++l) {
-        const double c0 = l < lcount ? cf[(int64_t)(l0 + l) * k] : 0.0;
-#pragma unroll
-        for (int w = 0; w < W; ++w) acc[l][w] = (col + w == row) ? c0 : 0.0;
-    }
-    for (int i = 1; i < k; ++i) {
-        const V t = *reinterpret_cast<const V*>(tb + (int64_t)(i - 1) * stride + off);
+    for (int64_t row = blockIdx.y; row < n; row += gridDim.y) {   // rows row, row + gridDim.y, ...
+        const int64_t off = row * ld + col;
+        double acc[MB][W];
 #pragma unroll
         for (int l = 0; l < MB; ++l) {
-            const double c = l < lcount ? cf[(int64_t)(l0 + l) * k + i] : 0.0;
+            const double c0 = l < lcount ? cf[(int64_t)(l0 + l) * k] : 0.0;
 #pragma unroll
-            for (int w = 0; w < W; ++w) acc[l][w] += c * (double)t[w];
+            for (int w = 0; w < W; ++w) acc[l][w] = (col + w == row) ? c0 : 0.0;
         }
-    }
+        for (int i = 1; i < k; ++i) {
+            const V t = *reinterpret_cast<const V*>(tb + (int64_t)(i - 1) * stride + off);
 #pragma unroll
-    for (int l = 0; l < MB; ++l) {
-        if (l < lcount) {
-            V o;
+            for (int l = 0; l < MB; ++l) {
+                const double c = l < lcount ? cf[(int64_t)(l0 + l) * k + i] : 0.0;
 #pragma unroll
-            for (int w = 0; w < W; ++w) o[w] = (T)acc[l][w];
-            *reinterpret_cast<V*>(rb + (int64_t)(l0 + l) * stride + off) = o;
+                for (int w = 0; w < W; ++w) acc[l][w] += c * (double)t[w];
+            }
+        }
+#pragma unroll
+        for (int l = 0; l < MB; ++l) {
+            if (l < lcount) {
+                V o;
+#pragma unroll
+                for (int w = 0; w < W; ++w) o[w] = (T)acc[l][w];
+                *reinterpret_cast<V*>(rb + (int64_t)(l0 + l) * stride + off) = o;
+            }
         }
     }
 }
@@ -487,9 +493,10 @@ k_batch_scalar_fill(const BatchProblem* __restrict__ tab, const BatchGeom* __res
                     const DevScalars* __restrict__ s) {
     const int p = blockIdx.z;
     if (s[p].status != 2) return;
-    const int64_t n = geo[p].n, i = blockIdx.y, j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n || j >= n) return;
-    tab[p].D[i * tab[p].ldd + j] = (i == j) ? tab[p].n_elec / (double)n : 0.0;
+    const int64_t n = geo[p].n, j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    for (int64_t i = blockIdx.y; i < n; i += gridDim.y)
+        tab[p].D[i * tab[p].ldd + j] = (i == j) ? tab[p].n_elec / (double)n : 0.0;
 }
 
 __global__ void __launch_bounds__(256)
@@ -521,10 +528,16 @@ k_batch_finish(const BatchProblem* __restrict__ tab, const BatchGeom* __restrict
     }
 }
 
+// Row groups of the per-row kernels (shift, combine, scalar fill): work-group y takes rows
+// y, y + G, ... of its problem, so a problem smaller than the largest launches no idle
+// work-groups (one work-group per row of the largest problem cost 0.9 ms per 512-problem
+// batch in the fill alone, which has work only for a scalar H).
+inline int batch_row_groups(int64_t nmax) { return nmax < 64 ? (int)nmax : 64; }
+
 template <typename T>
 hipError_t combine_all(const BatchDims& d, const BatchGeom* geo, const double* coef, T* mats, hipStream_t st) {
     const int64_t per = 256 * BVec<T>::W;
-    dim3 grid((unsigned)((d.ldmax + per - 1) / per), (unsigned)d.nmax, (unsigned)d.count);
+    dim3 grid((unsigned)((d.ldmax + per - 1) / per), (unsigned)batch_row_groups(d.nmax), (unsigned)d.count);
     for (int l0 = 0; l0 < d.m; l0 += 24) {
         const int cnt = (d.m - l0) < 24 ? (d.m - l0) : 24;
         if (cnt <= 8)
@@ -627,7 +640,7 @@ hipError_t launch_batch_setup(const BatchDims& d, const BatchProblem* tab, const
 
 hipError_t launch_batch_shift(const BatchDims& d, const BatchProblem* tab, const BatchGeom* geo, const DevScalars* s,
                               void* mats, hipStream_t st) {
-    dim3 grid((unsigned)((d.nmax + 255) / 256), (unsigned)d.nmax, (unsigned)d.count);
+    dim3 grid((unsigned)((d.nmax + 255) / 256), (unsigned)batch_row_groups(d.nmax), (unsigned)d.count);
     if (d.prec == CHEBDM_FP64)
         hipLaunchKernelGGL(k_batch_shift<double>, grid, dim3(256), 0, st, tab, geo, s, (double*)mats);
     else
@@ -688,8 +701,8 @@ hipError_t launch_batch_combine(const BatchDims& d, const BatchGeom* geo, const 
 hipError_t launch_batch_finish(const BatchDims& d, const BatchProblem* tab, const BatchGeom* geo, DevScalars* s,
                                double* mu, double* trD, int with_density, hipStream_t st) {
     if (with_density)
-        hipLaunchKernelGGL(k_batch_scalar_fill, dim3((unsigned)((d.nmax + 255) / 256), (unsigned)d.nmax,
-                                                     (unsigned)d.count),
+        hipLaunchKernelGGL(k_batch_scalar_fill, dim3((unsigned)((d.nmax + 255) / 256),
+                                                     (unsigned)batch_row_groups(d.nmax), (unsigned)d.count),
                            dim3(256), 0, st, tab, geo, (const DevScalars*)s);
     hipLaunchKernelGGL(k_batch_finish, dim3((unsigned)d.count), dim3(256), 0, st, tab, geo, s, mu, trD, with_density);
     return hipGetLastError();
