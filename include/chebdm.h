@@ -367,9 +367,11 @@ int chebdm_block_coeffs(chebdm_handle h, const double* c, int32_t order, int32_t
  *   rule asks for more reports CHEBDM_ERR_ARG in its status).  Allocates
  *   sum_p (k+m) ld_p^2 workspace elements (ld_p = round_up(n_p, 128)).
  * chebdm_batch_tune: the autotuner.  Times one product step for each
- *   candidate schedule on the plan's workspace (tile edge 64 or 32 per size
- *   bucket n <= 256 / 512 / 768 / larger; problems ordered by decreasing n or
- *   as given) and keeps the fastest.  cache_path (nullable): a text file of
+ *   candidate schedule on the plan's workspace (tile edge 64, 48 or 32 per
+ *   size bucket n <= 256 / 512 / 768 / larger, a problem whose 48-tile grid
+ *   would leave its workspace keeping 64; problems ordered by decreasing n or
+ *   as given) and keeps the fastest.  Every candidate gives the same result
+ *   bit for bit.  cache_path (nullable): a text file of
  *   "key value" lines; a matching key is applied without timing, a new result
  *   is appended.  report (nullable) receives a one-line summary.
  * chebdm_batch_mu_search: host arrays of count entries: dH[p], dD[p] (device
