@@ -332,6 +332,9 @@ k_batch_dct3(const double* __restrict__ tau, int order, const int64_t* __restric
              double* __restrict__ w, double* __restrict__ x, int damping) {
     extern __shared__ double st[];
     const int p = blockIdx.y;
+    // the grid spans the largest quadrature the plan allows; work-groups past this problem's
+    // M nodes (64 per work-group) leave at once, before staging the moments
+    if ((int64_t)blockIdx.x * 64 >= mq[p]) return;
     for (int i = threadIdx.x; i <= order; i += 256)
         st[i] = tau[(int64_t)p * (order + 1) + i] * damping_factor(damping, i, order);
     __syncthreads();
