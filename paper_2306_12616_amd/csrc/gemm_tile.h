@@ -61,24 +61,43 @@ __device__ __forceinline__ void load_frag(Frag<T, KU>& f, const T* p) {
     }
 }
 
+// Two floats to a pair of bf16 (round to nearest even, one packed conversion) and those two
+// bf16 values back to float, read straight from the packed bits (exact).
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ bf16x2 to_bf16x2(float a, float b, float& ra, float& rb) {
+    const bf16x2 h = __builtin_convertvector((f32x2){a, b}, bf16x2);
+    const uint32_t u = __builtin_bit_cast(uint32_t, h);
+    ra = __builtin_bit_cast(float, u << 16);
+    rb = __builtin_bit_cast(float, u & 0xffff0000u);
+    return h;
+}
+
+// x = hi + lo (+ rounding), hi = bf16(x), lo = bf16(x - hi); pairs of elements share each
+// conversion (three VALU operations per element instead of four).
 __device__ __forceinline__ void split_bf16(const float* x, bf16x8& hi, bf16x8& lo) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const __bf16 h = (__bf16)x[t];
-        hi[t] = h;
-        lo[t] = (__bf16)(x[t] - (float)h);
+    for (int t = 0; t < 8; t += 2) {
+        float h0, h1, u0, u1;
+        const bf16x2 h = to_bf16x2(x[t], x[t + 1], h0, h1);
+        const bf16x2 l = to_bf16x2(x[t] - h0, x[t + 1] - h1, u0, u1);
+        hi[t] = h[0], hi[t + 1] = h[1];
+        lo[t] = l[0], lo[t + 1] = l[1];
     }
 }
 
+// x = hi + mid + lo (+ rounding): hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi - mid).
 __device__ __forceinline__ void split3_bf16(const float* x, bf16x8& hi, bf16x8& mid, bf16x8& lo) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const __bf16 h = (__bf16)x[t];
-        const float r = x[t] - (float)h;
-        const __bf16 m = (__bf16)r;
-        hi[t] = h;
-        mid[t] = m;
-        lo[t] = (__bf16)(r - (float)m);
+    for (int t = 0; t < 8; t += 2) {
+        float h0, h1, m0, m1, u0, u1;
+        const bf16x2 h = to_bf16x2(x[t], x[t + 1], h0, h1);
+        const float r0 = x[t] - h0, r1 = x[t + 1] - h1;
+        const bf16x2 m = to_bf16x2(r0, r1, m0, m1);
+        const bf16x2 l = to_bf16x2(r0 - m0, r1 - m1, u0, u1);
+        hi[t] = h[0], hi[t + 1] = h[1];
+        mid[t] = m[0], mid[t + 1] = m[1];
+        lo[t] = l[0], lo[t + 1] = l[1];
     }
 }
 
