@@ -4,8 +4,9 @@
 // and can be formed together): all m blocks R_l = sum_{i<k} coef[l][i] T_i
 // in one pass over T_1..T_{k-1}, i.e. the skinny product (m x k) (k x N^2).
 // The pass is HBM-bound (about 2.9 flop per byte in float64), so each thread
-// streams 16-byte vectors of one row of every T_i once and keeps up to 24
-// block accumulators in registers; T_0 = I adds coef[l][0] on the diagonal.
+// streams two elements of one row of every T_i once and keeps up to 24 float64
+// block accumulators per element in registers (four wavefronts per SIMD in
+// both precisions); T_0 = I adds coef[l][0] on the diagonal.
 // Full padded rows are processed: the zero padding of T_i yields zero
 // padding in R_l, so no column predicate is needed.
 //
@@ -24,11 +25,10 @@ namespace {
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-template <typename T> struct Vec16;
-template <> struct Vec16<double> { using V = f64x2; static constexpr int W = 2; };
-template <> struct Vec16<float> { using V = f32x4; static constexpr int W = 4; };
+template <typename T> struct Vec;
+template <> struct Vec<double> { using V = f64x2; static constexpr int W = 2; };
+template <> struct Vec<float> { using V = f32x2; static constexpr int W = 2; };
 
 constexpr int kCombineThreads = 256;
 
@@ -36,29 +36,56 @@ template <typename T, int MB>
 __global__ void __launch_bounds__(kCombineThreads)
 k_combine(const T* __restrict__ tbase, int64_t stride, int k, int l0, int lcount,
           const double* __restrict__ coef, T* __restrict__ rbase, int64_t n, int64_t ld) {
-    using V = typename Vec16<T>::V;
-    constexpr int W = Vec16<T>::W;
+    using V = typename Vec<T>::V;
+    constexpr int W = Vec<T>::W;
+    // float32 stages its coefficients in LDS (cs[i][l] = coef[l0 + l][i], zero past lcount) and
+    // keeps the next T_i in flight: its loop then reads uniform LDS words instead of one guarded
+    // scalar load per block and term (combine bandwidth at n = 1000 / 2000 / 4000: 2.9 / 3.1 /
+    // 3.5 -> 4.4 / 3.6 / 4.0 TB/s).  float64 keeps the scalar loads, which measured as fast at
+    // n = 4000 and 8 % faster at n = 2000.
+    constexpr bool kStage = sizeof(T) == 4;
     const int64_t row = blockIdx.y;
     const int64_t col = ((int64_t)blockIdx.x * kCombineThreads + threadIdx.x) * W;
-    if (col >= ld) return;
-    const int64_t off = row * ld + col;
+    const bool live = col < ld;
+    const int64_t off = row * ld + (live ? col : 0);
+    auto tload = [&](int j) { return *reinterpret_cast<const V*>(tbase + (int64_t)j * stride + off); };
+    V t{};
+    __shared__ double cs[kStage ? kMaxBlocks : 1][MB];
+    if constexpr (kStage) {
+        if (k > 1) t = tload(0);   // T_1, in flight while the coefficients are staged
+        for (int idx = threadIdx.x; idx < lcount * k; idx += kCombineThreads) {
+            const int l = idx / k, i = idx % k;
+            cs[i][l] = coef[(int64_t)(l0 + l) * k + i];
+        }
+        for (int idx = threadIdx.x; idx < (MB - lcount) * k; idx += kCombineThreads)
+            cs[idx % k][lcount + idx / k] = 0.0;
+        __syncthreads();
+    }
+    if (!live) return;
+    auto coef_at = [&](int i, int l) -> double {
+        if constexpr (kStage) return cs[i][l];
+        else return l < lcount ? coef[(int64_t)(l0 + l) * k + i] : 0.0;
+    };
 
     double acc[MB][W];
     // T_0 = I: coef[l][0] on the diagonal
 #pragma unroll
     for (int l = 0; l < MB; ++l) {
-        const double c0 = (l < lcount) ? coef[(int64_t)(l0 + l) * k] : 0.0;
+        const double c0 = coef_at(0, l);
 #pragma unroll
         for (int w = 0; w < W; ++w) acc[l][w] = (col + w == row) ? c0 : 0.0;
     }
     for (int i = 1; i < k; ++i) {
-        const V t = *reinterpret_cast<const V*>(tbase + (int64_t)(i - 1) * stride + off);
+        V tn{};
+        if constexpr (kStage) tn = tload(i < k - 1 ? i : i - 1);   // T_{i+1} (the last step re-reads T_i)
+        else t = tload(i - 1);
 #pragma unroll
         for (int l = 0; l < MB; ++l) {
-            const double c = (l < lcount) ? coef[(int64_t)(l0 + l) * k + i] : 0.0;
+            const double c = coef_at(i, l);
 #pragma unroll
             for (int w = 0; w < W; ++w) acc[l][w] += c * (double)t[w];
         }
+        if constexpr (kStage) t = tn;
     }
 #pragma unroll
     for (int l = 0; l < MB; ++l) {
@@ -231,8 +258,8 @@ void launch_gram_fm(int fn, const PtrList<T>& L, int nl, const PtrList<T>& Tm, i
 template <typename T>
 hipError_t launch_combine(const T* tbase, int64_t stride, int k, int m, const double* coef, T* rbase,
                           int64_t n, int64_t ld, hipStream_t st) {
-    constexpr int W = Vec16<T>::W;
-    if (ld % (W * 2) != 0) return hipErrorInvalidValue;
+    constexpr int W = Vec<T>::W;
+    if (ld % (W * 2) != 0 || k < 1 || k > kMaxBlocks) return hipErrorInvalidValue;
     const int64_t per_block = (int64_t)kCombineThreads * W;
     dim3 grid((unsigned)((ld + per_block - 1) / per_block), (unsigned)n);
     for (int l0 = 0; l0 < m; l0 += 24) {
