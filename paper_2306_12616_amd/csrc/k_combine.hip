@@ -106,31 +106,11 @@ struct PtrList {
 constexpr int kGramThreads = 256;
 constexpr int kGramMax = 48;   // rows / columns of G handled (3 MFMA blocks of 16)
 
-// VW consecutive elements of one matrix per lane (32 bytes: 4 float64 or 8 float32), widened
-// to float64, loaded as 16-byte vectors
-template <int VW>
-struct Lane {
-    double v[VW];
-};
-template <int VW>
-__device__ __forceinline__ Lane<VW> loadv(const double* p) {   // one 32-byte vector load
-    static_assert(VW == 4, "float64 lanes hold four elements");
-    const f64x4 x = *reinterpret_cast<const f64x4*>(p);
-    Lane<VW> out;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) out.v[t] = x[t];
-    return out;
-}
-template <int VW>
-__device__ __forceinline__ Lane<VW> loadv(const float* p) {    // one 32-byte vector load
-    static_assert(VW == 8, "float32 lanes hold eight elements");
-    typedef float f32x8v __attribute__((ext_vector_type(8)));
-    const f32x8v x = *reinterpret_cast<const f32x8v*>(p);
-    Lane<VW> out;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) out.v[t] = (double)x[t];
-    return out;
-}
+// VW consecutive elements of one matrix per lane, one 32-byte vector load (4 float64 or 8
+// float32), widened to float64 only where the MFMA takes them
+template <typename T> struct Raw;
+template <> struct Raw<double> { typedef double V __attribute__((ext_vector_type(4))); };
+template <> struct Raw<float> { typedef float V __attribute__((ext_vector_type(8))); };
 
 // Chunks of CH = 4 VW consecutive elements: lane group lq holds elements lq VW .. lq VW + VW-1
 // of each of its matrices, so every (matrix, chunk) is one whole 128-byte line.
@@ -138,7 +118,7 @@ template <typename T, int FM, int FN, int VW = 32 / (int)sizeof(T)>
 __global__ void __launch_bounds__(kGramThreads)
 k_gram_partial(const PtrList<T> lm, int nl, const PtrList<T> tm, int nt, int64_t nchunk,
                double* __restrict__ partial) {
-    using V = Lane<VW>;
+    using R = typename Raw<T>::V;
     constexpr int CH = 4 * VW;
     __shared__ double red[FM * 16][FN * 16 + 1];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -165,42 +145,35 @@ k_gram_partial(const PtrList<T> lm, int nl, const PtrList<T> tm, int nt, int64_t
 #pragma unroll
         for (int g = 0; g < FN; ++g) acc[f][g] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-    // U chunks per iteration (64 bytes per lane and matrix): all loads issue before the first MFMA
-    constexpr int U = 2;
-    int64_t c = c_begin;
-    for (; c + U <= c_end; c += U) {
-        V a[U][FM], b[U][FN];
+    auto load = [&](R (&a)[FM], R (&b)[FN], int64_t c) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+        for (int f = 0; f < FM; ++f) a[f] = *reinterpret_cast<const R*>(pa[f] + c * CH);
 #pragma unroll
-            for (int f = 0; f < FM; ++f) a[u][f] = loadv<VW>(pa[f] + (c + u) * CH);
-#pragma unroll
-            for (int g = 0; g < FN; ++g) b[u][g] = loadv<VW>(pb[g] + (c + u) * CH);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int s = 0; s < VW; ++s)
-#pragma unroll
-                for (int f = 0; f < FM; ++f)
-#pragma unroll
-                    for (int g = 0; g < FN; ++g)
-                        acc[f][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][f].v[s], b[u][g].v[s], acc[f][g], 0, 0, 0);
-    }
-    for (; c < c_end; ++c) {
-        const int64_t e = c * CH;
-        V a[FM], b[FN];
-#pragma unroll
-        for (int f = 0; f < FM; ++f) a[f] = loadv<VW>(pa[f] + e);
-#pragma unroll
-        for (int g = 0; g < FN; ++g) b[g] = loadv<VW>(pb[g] + e);
+        for (int g = 0; g < FN; ++g) b[g] = *reinterpret_cast<const R*>(pb[g] + c * CH);
+    };
+    auto mma = [&](const R (&a)[FM], const R (&b)[FN]) {
 #pragma unroll
         for (int s = 0; s < VW; ++s)
 #pragma unroll
             for (int f = 0; f < FM; ++f)
 #pragma unroll
                 for (int g = 0; g < FN; ++g)
-                    acc[f][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[f].v[s], b[g].v[s], acc[f][g], 0, 0, 0);
+                    acc[f][g] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a[f][s], (double)b[g][s], acc[f][g],
+                                                                    0, 0, 0);
+    };
+    // two register stages: the next chunk's loads are in flight while a chunk's MFMAs run (the
+    // last refill of an even count re-reads its final chunk)
+    if (c_begin < c_end) {
+        R a0[FM], b0[FN], a1[FM], b1[FN];
+        int64_t c = c_begin;
+        load(a0, b0, c);
+        for (; c + 2 <= c_end; c += 2) {
+            load(a1, b1, c + 1);
+            mma(a0, b0);
+            load(a0, b0, c + 2 < c_end ? c + 2 : c + 1);
+            mma(a1, b1);
+        }
+        if (c < c_end) mma(a0, b0);
     }
     // v_mfma_f64_16x16x4f64 leaves G row 16f + lq + 4r, column 16g + lr in lane (lr, lq),
     // register r; waves add in a fixed order
