@@ -3,6 +3,8 @@
 // for the design; this header only holds device code.
 #pragma once
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace chebdm {
@@ -101,10 +103,13 @@ __device__ __forceinline__ void split3_bf16(const float* x, bf16x8& hi, bf16x8& 
     }
 }
 
-template <int P, int KU, int FM, int FN>
+// LOW: the wave tile sits on the diagonal of a diagonal tile (square, row0 == col0), so blocks
+// f > g lie wholly below the diagonal, where the epilogue stores nothing: their MFMAs are left out.
+template <int P, int KU, int FM, int FN, bool LOW = false>
 __device__ __forceinline__ void mma_chunk(typename Traits<P>::Acc (&acc)[FM][FN],
                                           const Frag<typename Traits<P>::T, KU> (&a)[FM],
                                           const Frag<typename Traits<P>::T, KU> (&b)[FN]) {
+    static_assert(!LOW || FM == FN, "diagonal blocks of a square wave tile");
     if constexpr (P == P_F64) {
 #pragma unroll
         for (int s = 0; s < KU; ++s)
@@ -112,7 +117,8 @@ __device__ __forceinline__ void mma_chunk(typename Traits<P>::Acc (&acc)[FM][FN]
             for (int f = 0; f < FM; ++f)
 #pragma unroll
                 for (int g = 0; g < FN; ++g)
-                    acc[f][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[f].v[s], b[g].v[s], acc[f][g], 0, 0, 0);
+                    if (!LOW || f <= g)
+                        acc[f][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[f].v[s], b[g].v[s], acc[f][g], 0, 0, 0);
     } else if constexpr (P == P_F32) {
 #pragma unroll
         for (int s = 0; s < KU; ++s)
@@ -120,7 +126,8 @@ __device__ __forceinline__ void mma_chunk(typename Traits<P>::Acc (&acc)[FM][FN]
             for (int f = 0; f < FM; ++f)
 #pragma unroll
                 for (int g = 0; g < FN; ++g)
-                    acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[f].v[s], b[g].v[s], acc[f][g], 0, 0, 0);
+                    if (!LOW || f <= g)
+                        acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[f].v[s], b[g].v[s], acc[f][g], 0, 0, 0);
     } else if constexpr (P == P_BF16X6) {
         // x = hi + mid + lo; keep every term down to 2^-16 relative, smallest first
 #pragma unroll
@@ -134,6 +141,7 @@ __device__ __forceinline__ void mma_chunk(typename Traits<P>::Acc (&acc)[FM][FN]
             for (int f = 0; f < FM; ++f)
 #pragma unroll
                 for (int g = 0; g < FN; ++g) {
+                    if (LOW && f > g) continue;
                     acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[f], bh[g], acc[f][g], 0, 0, 0);
                     acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f], bl[g], acc[f][g], 0, 0, 0);
                     acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[f], bm[g], acc[f][g], 0, 0, 0);
@@ -154,6 +162,7 @@ __device__ __forceinline__ void mma_chunk(typename Traits<P>::Acc (&acc)[FM][FN]
             for (int f = 0; f < FM; ++f)
 #pragma unroll
                 for (int g = 0; g < FN; ++g) {
+                    if (LOW && f > g) continue;
                     acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[f], bh[g], acc[f][g], 0, 0, 0);
                     acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f], bl[g], acc[f][g], 0, 0, 0);
                     acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f], bh[g], acc[f][g], 0, 0, 0);
@@ -313,7 +322,9 @@ __device__ __forceinline__ void tile_epilogue(const GemmDesc<typename Traits<P>:
 // loads to the end of the loop body, behind most of the MFMAs); -1: 1 for float32 (N = 4000,
 // three products: 1.766 -> 1.700 ms; N = 2000, four: 0.425 -> 0.407), 0 otherwise (float64
 // already issues them early; no change).
-template <int P, int BM, int WGM, int WGN, int KU, int SK = 1, int RB = 16, int SB = -1>
+// DS: a wavefront whose wave tile lies on the diagonal of a diagonal tile leaves out the MFMAs of
+// the blocks below the diagonal (where dynamic scheduling turns the shorter tile into time saved).
+template <int P, int BM, int WGM, int WGN, int KU, int SK = 1, int RB = 16, int SB = -1, bool DS = false>
 __device__ __forceinline__ void gemm_tile(const GemmDesc<typename Traits<P>::T>& g, int64_t n, int64_t ld,
                                           int64_t kpad, int ti, int tj, int64_t k_lo = 0, int64_t k_hi = -1,
                                           typename Traits<P>::Acc* part = nullptr) {
@@ -364,20 +375,31 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<typename Traits<P>::T>&
         kbeg = k_lo + units * ks / SK * (2 * CH);
         kend = k_lo + units * (ks + 1) / SK * (2 * CH);
     }
-    if (kend > kbeg) {
+    // One copy of the loop per MFMA set: all blocks, or (DS) the diagonal wave tile's blocks on and
+    // above the diagonal.
+    auto kloop = [&](auto low) {
+        constexpr bool L = decltype(low)::value;
         load(a0, b0, kbeg);
         load(a1, b1, kbeg + CH);
         for (int64_t k0 = kbeg; k0 + 2 * CH < kend; k0 += 2 * CH) {
-            mma_chunk<P, KU, FM, FN>(acc, a0, b0);
+            mma_chunk<P, KU, FM, FN, L>(acc, a0, b0);
             if constexpr (kSB) __builtin_amdgcn_sched_barrier(0);
             load(a0, b0, k0 + 2 * CH);
             if constexpr (kSB) __builtin_amdgcn_sched_barrier(0);
-            mma_chunk<P, KU, FM, FN>(acc, a1, b1);
+            mma_chunk<P, KU, FM, FN, L>(acc, a1, b1);
             if constexpr (kSB) __builtin_amdgcn_sched_barrier(0);
             load(a1, b1, k0 + 3 * CH);
         }
-        mma_chunk<P, KU, FM, FN>(acc, a0, b0);
-        mma_chunk<P, KU, FM, FN>(acc, a1, b1);
+        mma_chunk<P, KU, FM, FN, L>(acc, a0, b0);
+        mma_chunk<P, KU, FM, FN, L>(acc, a1, b1);
+    };
+    if (kend > kbeg) {
+        if constexpr (DS && FM == FN) {
+            if (diag_tile && row0 == col0) kloop(std::true_type{});
+            else kloop(std::false_type{});
+        } else {
+            kloop(std::false_type{});
+        }
     }
     if constexpr (SK > 1) {
         // partial sums of the K slices 1..SK-1 through LDS, added in slice order

@@ -34,6 +34,9 @@ __global__ void __launch_bounds__(64)
 k_batch_gemm(const GemmDesc<typename Traits<P>::T>* __restrict__ descs, const BatchGeom* __restrict__ geo,
              const TileItem* __restrict__ items, int nitems, int* __restrict__ counter) {
     constexpr int KU64 = BatchKU<P>::K64, KU32 = BatchKU<P>::K32;
+    // diagonal wave tiles skip their below-diagonal blocks (the claimed items even the load out);
+    // the split-bf16 loops would spill registers with the second loop copy, so they keep one
+    constexpr bool kDS = P == P_F64 || P == P_F32;
     for (;;) {
         int idx = 0;
         if (threadIdx.x == 0) idx = atomicAdd(counter, 1);
@@ -46,13 +49,13 @@ k_batch_gemm(const GemmDesc<typename Traits<P>::T>* __restrict__ descs, const Ba
         upper_tile(it.t, gm.ntile, ti, tj);
         if (gm.tile == 64) {
             const int64_t kpad = (gm.n + 8 * KU64 - 1) / (8 * KU64) * (8 * KU64);
-            gemm_tile<P, 64, 1, 1, KU64>(g, gm.n, gm.ld, kpad, ti, tj);
+            gemm_tile<P, 64, 1, 1, KU64, 1, 16, -1, kDS>(g, gm.n, gm.ld, kpad, ti, tj);
         } else if (gm.tile == 48) {   // only where ceil(n / 48) * 48 <= ld (the host checks)
             const int64_t kpad = (gm.n + 8 * KU64 - 1) / (8 * KU64) * (8 * KU64);
-            gemm_tile<P, 48, 1, 1, KU64>(g, gm.n, gm.ld, kpad, ti, tj);
+            gemm_tile<P, 48, 1, 1, KU64, 1, 16, -1, kDS>(g, gm.n, gm.ld, kpad, ti, tj);
         } else {
             const int64_t kpad = (gm.n + 8 * KU32 - 1) / (8 * KU32) * (8 * KU32);
-            gemm_tile<P, 32, 1, 1, KU32>(g, gm.n, gm.ld, kpad, ti, tj);
+            gemm_tile<P, 32, 1, 1, KU32, 1, 16, -1, kDS>(g, gm.n, gm.ld, kpad, ti, tj);
         }
     }
 }
