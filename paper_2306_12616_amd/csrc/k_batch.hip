@@ -47,15 +47,21 @@ k_batch_gemm(const GemmDesc<typename Traits<P>::T>* __restrict__ descs, const Ba
         const GemmDesc<typename Traits<P>::T> g = descs[it.p];
         int ti, tj;
         upper_tile(it.t, gm.ntile, ti, tj);
+        // A tile of the last tile column whose columns end within its first half runs as the left
+        // wave tile of a 1 x 2 split (the right half is all padding); a single wavefront may do
+        // that because an unsplit K range has no barrier.
+        const bool half = tj == gm.ntile - 1 && gm.n - (int64_t)tj * gm.tile <= gm.tile / 2;
         if (gm.tile == 64) {
             const int64_t kpad = (gm.n + 8 * KU64 - 1) / (8 * KU64) * (8 * KU64);
-            gemm_tile<P, 64, 1, 1, KU64, 1, 16, -1, kDS>(g, gm.n, gm.ld, kpad, ti, tj);
+            if (half) gemm_tile<P, 64, 1, 2, KU64>(g, gm.n, gm.ld, kpad, ti, tj);
+            else gemm_tile<P, 64, 1, 1, KU64, 1, 16, -1, kDS>(g, gm.n, gm.ld, kpad, ti, tj);
         } else if (gm.tile == 48) {   // only where ceil(n / 48) * 48 <= ld (the host checks)
             const int64_t kpad = (gm.n + 8 * KU64 - 1) / (8 * KU64) * (8 * KU64);
             gemm_tile<P, 48, 1, 1, KU64, 1, 16, -1, kDS>(g, gm.n, gm.ld, kpad, ti, tj);
         } else {
             const int64_t kpad = (gm.n + 8 * KU32 - 1) / (8 * KU32) * (8 * KU32);
-            gemm_tile<P, 32, 1, 1, KU32, 1, 16, -1, kDS>(g, gm.n, gm.ld, kpad, ti, tj);
+            if (half) gemm_tile<P, 32, 1, 2, KU32>(g, gm.n, gm.ld, kpad, ti, tj);
+            else gemm_tile<P, 32, 1, 1, KU32, 1, 16, -1, kDS>(g, gm.n, gm.ld, kpad, ti, tj);
         }
     }
 }
