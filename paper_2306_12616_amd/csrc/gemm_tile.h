@@ -364,10 +364,12 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<typename Traits<P>::T>&
     };
 
     // Two register stages: while one chunk's MFMAs run, the other chunk's registers are being
-    // refilled.  The K range is a multiple of 2 CH; the last two chunks are consumed after the
-    // loop with no further loads, so the epilogue's addends are the only loads behind them
-    // (clamped reloads of the last chunks there cost 1-3 % of the product time, N = 1000 - 4000,
-    // and 3 % of the 512-problem batch).
+    // refilled.  K ranges come in units of 2 CH; the range that holds the end of K stops at the
+    // chunk holding element n - 1 (the rest of kpad is zero padding), so it may hold an odd number
+    // of chunks, whose last refill then loads one padding chunk that is not used.  The last one
+    // or two chunks are consumed after the loop with no further loads, so the epilogue's addends
+    // are the only loads behind them (clamped reloads of the last chunks there cost 1-3 % of the
+    // product time, N = 1000 - 4000, and 3 % of the 512-problem batch).
     if (k_hi < 0) k_hi = kpad;
     int64_t kbeg = k_lo, kend = k_hi;
     if constexpr (SK > 1) {
@@ -375,13 +377,21 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<typename Traits<P>::T>&
         kbeg = k_lo + units * ks / SK * (2 * CH);
         kend = k_lo + units * (ks + 1) / SK * (2 * CH);
     }
+    // (the split-bf16 tiles keep whole units: their 48-tiles would spill registers with the
+    // guarded last chunk)
+    constexpr bool kOdd = P == P_F64 || P == P_F32;
+    if constexpr (kOdd) {
+        const int64_t kceil = (n + CH - 1) / CH * CH;   // kpad or kpad - CH: a non-empty range keeps a chunk
+        if (kend > kceil) kend = kceil;
+    }
     // One copy of the loop per MFMA set: all blocks, or (DS) the diagonal wave tile's blocks on and
-    // above the diagonal.
+    // above the diagonal.  Every chunk loaded lies below kpad.
     auto kloop = [&](auto low) {
         constexpr bool L = decltype(low)::value;
         load(a0, b0, kbeg);
         load(a1, b1, kbeg + CH);
-        for (int64_t k0 = kbeg; k0 + 2 * CH < kend; k0 += 2 * CH) {
+        int64_t k0 = kbeg;
+        for (; k0 + 2 * CH < kend; k0 += 2 * CH) {
             mma_chunk<P, KU, FM, FN, L>(acc, a0, b0);
             if constexpr (kSB) __builtin_amdgcn_sched_barrier(0);
             load(a0, b0, k0 + 2 * CH);
@@ -391,7 +401,7 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<typename Traits<P>::T>&
             load(a1, b1, k0 + 3 * CH);
         }
         mma_chunk<P, KU, FM, FN, L>(acc, a0, b0);
-        mma_chunk<P, KU, FM, FN, L>(acc, a1, b1);
+        if (!kOdd || k0 + CH < kend) mma_chunk<P, KU, FM, FN, L>(acc, a1, b1);
     };
     if (kend > kbeg) {
         if constexpr (DS && FM == FN) {
