@@ -122,21 +122,29 @@ k_gemm_fix(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, 
                                        part + (int64_t)tile * nslice * slice_accs<P, BM, WGM, WGN>(), nslice);
 }
 
-// Stream-K launches of the one-wavefront register tiles.  The launch's W tiles times U K units
-// (2 CH each) are dealt in equal contiguous ranges to G resident work-groups, so the chip runs
-// W / G rounds of tile time instead of a whole number of them.  A tile inside one range runs
-// whole with its epilogue; a tile shared by several ranges leaves each piece's raw accumulators
-// in slot 2 r (the first tile of range r) or 2 r + 1 (its last), and a fix-up launch adds the
-// pieces in range order (fixed order: deterministic) and runs the epilogue.  Ranges go to
-// work-groups in XCD order, so neighbouring tiles share an XCD's L2.
+// Stream-K launches of the one-wavefront register tiles.  Of the launch's W tiles, the first dp
+// (whole rounds of the G resident work-groups, when what is left still gives every range four K
+// units) run whole, tile r + j G on work-group r; the other W - dp tiles times U K units (2 CH
+// each) are dealt in equal contiguous ranges to the G work-groups, so the chip runs W / G rounds
+// of tile time instead of a whole number of them, and only the tiles of the last partial round
+// are cut into pieces.  A tile inside one range runs whole with its epilogue; a tile shared by
+// several ranges leaves each piece's raw accumulators in slot 2 r (the first tile of range r) or
+// 2 r + 1 (its last), and a fix-up launch adds the pieces in range order (fixed order:
+// deterministic) and runs the epilogue.  Ranges go to work-groups in XCD order, so neighbouring
+// tiles share an XCD's L2.
 __device__ __forceinline__ int64_t sk_range_begin(int64_t total, int64_t r, int64_t G) { return total * r / G; }
 
 template <int P, int BM, int KU, int RB>
 __global__ void __launch_bounds__(64)
 k_gemm_sk(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, int64_t kpad, int ntile, int ntri,
-          int64_t units, int64_t total, typename Traits<P>::Acc* part) {
+          int64_t dp, int64_t units, int64_t total, typename Traits<P>::Acc* part) {
     constexpr int CH = 4 * KU;
     const int64_t G = gridDim.x, r = xcd_order((int)blockIdx.x, (int)gridDim.x);
+    for (int64_t t = r; t < dp; t += G) {
+        int z, ti, tj;
+        lin_tile((int)t, ntri, ntile, z, ti, tj);
+        gemm_tile<P, BM, 1, 1, KU, 1, RB>(batch.d[z], n, ld, kpad, ti, tj);
+    }
     const int64_t a = sk_range_begin(total, r, G), b = sk_range_begin(total, r + 1, G);
     if (a == b) return;
     const int64_t t0 = a / units, t1 = (b - 1) / units;
@@ -144,7 +152,7 @@ k_gemm_sk(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, i
         const int64_t u0 = (a > t * units ? a : t * units) - t * units;
         const int64_t u1 = (b < (t + 1) * units ? b : (t + 1) * units) - t * units;
         int z, ti, tj;
-        lin_tile((int)t, ntri, ntile, z, ti, tj);
+        lin_tile((int)(dp + t), ntri, ntile, z, ti, tj);
         if (u0 == 0 && u1 == units) {
             gemm_tile<P, BM, 1, 1, KU, 1, RB>(batch.d[z], n, ld, kpad, ti, tj);
         } else {
@@ -155,18 +163,18 @@ k_gemm_sk(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, i
     }
 }
 
-// One work-group per tile; tiles inside one range were finished by k_gemm_sk.
+// One work-group per tile past dp; tiles inside one range were finished by k_gemm_sk.
 template <int P, int BM, int RB>
 __global__ void __launch_bounds__(64)
-k_gemm_sk_fix(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, int ntile, int ntri, int64_t units,
-              int64_t total, int64_t G, const typename Traits<P>::Acc* part) {
+k_gemm_sk_fix(const GemmBatch<typename Traits<P>::T> batch, int64_t n, int64_t ld, int ntile, int ntri, int64_t dp,
+              int64_t units, int64_t total, int64_t G, const typename Traits<P>::Acc* part) {
     const int64_t t = blockIdx.x;
     // range holding iteration i: the largest r with total r / G <= i
     const int64_t ra = ((t * units + 1) * G + total - 1) / total - 1;
     const int64_t rb = (((t + 1) * units) * G + total - 1) / total - 1;
     if (ra == rb) return;
     int z, ti, tj;
-    lin_tile((int)t, ntri, ntile, z, ti, tj);
+    lin_tile((int)(dp + t), ntri, ntile, z, ti, tj);
     gemm_tile_fix_slots<P, BM, RB>(batch.d[z], n, ld, ti, tj, part, (int)(rb - ra + 1), [&](int i) -> int64_t {
         const int64_t r = ra + i;
         const int64_t a = sk_range_begin(total, r, G), b = sk_range_begin(total, r + 1, G);
@@ -199,12 +207,15 @@ hipError_t launch_sk(const GemmBatch<typename Traits<P>::T>& b, int64_t n, int64
     const int64_t kpad = (n + 2 * CH - 1) / (2 * CH) * (2 * CH);
     const int ntile = (int)((n + BM - 1) / BM);
     const int ntri = ntile * (ntile + 1) / 2;
-    const int64_t W = (int64_t)ntri * b.count, units = kpad / (2 * CH), total = W * units;
+    const int64_t W = (int64_t)ntri * b.count, units = kpad / (2 * CH);
+    int64_t dp = W / G * G;                       // whole rounds run whole ...
+    if ((W - dp) * units < 4 * G) dp = 0;         // ... while the rest still gives four units a range
+    const int64_t total = (W - dp) * units;
     Acc* part = static_cast<Acc*>(scratch);
     hipLaunchKernelGGL((k_gemm_sk<P, BM, KU, RB>), dim3((unsigned)G), dim3(64), 0, st, b, n, ld, kpad, ntile, ntri,
-                       units, total, part);
-    hipLaunchKernelGGL((k_gemm_sk_fix<P, BM, RB>), dim3((unsigned)W), dim3(64), 0, st, b, n, ld, ntile, ntri, units,
-                       total, G, (const Acc*)part);
+                       dp, units, total, part);
+    hipLaunchKernelGGL((k_gemm_sk_fix<P, BM, RB>), dim3((unsigned)(W - dp)), dim3(64), 0, st, b, n, ld, ntile, ntri,
+                       dp, units, total, G, (const Acc*)part);
     return hipGetLastError();
 }
 
